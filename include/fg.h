@@ -1,0 +1,214 @@
+/*
+ * fg.h -- C-ABI of libfg.so, the MI355X (gfx950) per-frame hot path of
+ * FilterGS, an LoD 3D Gaussian Splatting renderer (Wang et al., CVPR 2026).
+ *
+ * A frame is four stream-ordered calls:
+ *
+ *   fg_filter      traversal-free parallel filtering of an LoD Gaussian tree
+ *                  (Sec. 3.2: R&L filter + Ancestor filter, every node
+ *                  evaluated independently, Eq. (4)) and stream compaction
+ *                  of the selection;
+ *   fg_preprocess  EWA projection of the selected Gaussians to 2D conics and
+ *                  colours (Sec. 3.1, Eq. (1)) and their tile rectangles under
+ *                  the opacity-aware shrink radius (Sec. 3.3, threshold tau of
+ *                  Eq. (8));
+ *   fg_sort        (tile, depth) ordering of the Gaussian-tile pairs (Sec. 3.3)
+ *                  by prefix scan, key emission and LDS-staged radix sorts,
+ *                  plus per-tile ranges;
+ *   fg_render      per-tile front-to-back alpha blending, Eq. (2).
+ *
+ * Conventions shared by every entry point:
+ *
+ *  - Pointers named in a struct or argument as "device" are device memory on
+ *    the current HIP device. Structs themselves (fg_tree, fg_camera,
+ *    fg_splats, fg_tune) are passed by host pointer and read during the call
+ *    only; the library keeps no reference to them.
+ *  - The caller owns every buffer. The library allocates nothing in these
+ *    calls; scratch memory comes in through (ws, ws_bytes), sized by the
+ *    matching *_workspace_size function. Workspace contents need no
+ *    initialisation and are not preserved between calls.
+ *  - `stream` is a hipStream_t (NULL = the null stream). Every call only
+ *    enqueues work on it: no host synchronisation, no host reads of device
+ *    data, so a sequence of calls can be captured into a HIP graph. Counts
+ *    that depend on the data (n_sel, n_pairs) stay in device memory and the
+ *    kernels read them there.
+ *  - Synchronous errors (bad arguments, launch failures) are returned as a
+ *    negative FG_ERR_* code and nothing is enqueued after the failing launch.
+ *    Data-dependent problems are reported in the device word *status as
+ *    FG_STATUS_* bits: fg_filter stores 0 into it first, later stages OR bits
+ *    in. After an overflow bit, the matching count holds the size that was
+ *    required, outputs beyond the capacity were not written, the outputs of
+ *    that frame are undefined, and the caller retries with larger buffers.
+ *  - Floating point follows one numeric contract on CPU and GPU: IEEE
+ *    binary32, round to nearest even, no contraction, correctly rounded
+ *    division and square root, and exp/log evaluated by fixed published
+ *    methods, so selections, tile sets, orders and pixels are reproducible
+ *    bit for bit.
+ *  - The library keeps no global mutable state; calls on different streams
+ *    with disjoint buffers may overlap.
+ */
+#ifndef FG_H
+#define FG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define FG_OK 0
+#define FG_ERR_INVALID_ARG (-1)   /* null pointer, negative size, bad enum */
+#define FG_ERR_INVALID_TREE (-2)  /* tree fields inconsistent (sizes, depth) */
+#define FG_ERR_UNSUPPORTED (-3)   /* e.g. SH degree > 3, image too large */
+#define FG_ERR_WORKSPACE (-4)     /* ws_bytes below the *_workspace_size value */
+#define FG_ERR_HIP (-5)           /* a HIP launch or runtime call failed */
+
+/* ---- device status bits ------------------------------------------------ */
+#define FG_STATUS_SEL_OVERFLOW 1u   /* more selected nodes than cap_sel */
+#define FG_STATUS_PAIR_OVERFLOW 2u  /* more Gaussian-tile pairs than cap_pairs */
+#define FG_STATUS_BAD_PARENT 4u     /* a parent index >= the child's index or
+                                       an ancestor chain longer than max_depth */
+
+/* ---- inputs ------------------------------------------------------------ */
+
+/* An LoD Gaussian tree (Sec. 3.1 "Hierarchical Gaussian Tree"): every node is
+ * a complete Gaussian with mean mu, covariance R(q) diag(s)^2 R(q)^T, opacity
+ * and spherical-harmonic colour (Sec. 3.1, Eq. (1)). The ancestor path of a
+ * node (Sec. 3.2 "Ancestor Filter") is its chain of parent links.
+ * All planes are device memory, structure of arrays. */
+typedef struct fg_tree {
+    int64_t n_nodes;         /* N, 0 <= N < 2^31 */
+    int64_t n_internal_span; /* every internal (non-leaf) node has index < this;
+                                nodes at or beyond it are all leaves */
+    int32_t sh_degree;       /* D in 0..3; (D+1)^2 coefficients per channel */
+    int32_t max_depth;       /* longest root-to-node chain, 0..15 */
+    const float* mean;       /* [3][N] x, y, z planes, world units */
+    const float* scale;      /* [3][N] linear (activated) scales */
+    const float* quat;       /* [4][N] rotation (w, x, y, z), any non-zero norm */
+    const float* opacity;    /* [N] activated opacity; nodes outside (0, 1] emit nothing */
+    const float* sh;         /* [N][(D+1)^2][3] coefficient-major, RGB-minor */
+    const int32_t* parent;   /* [N] parent index (< own index), -1 for a root */
+    const uint8_t* flags;    /* [N] bit 0: leaf. Read only for index < n_internal_span */
+} fg_tree;
+
+/* Pinhole camera: x_c = R x_w + t, axes x right, y down, z forward.
+ * Pixel (i, j) has its centre at (i + 0.5, j + 0.5); u = fx x_c / z_c + cx.
+ * A node is in the frustum when z_c > znear, |x_c| <= kx z_c and
+ * |y_c| <= ky z_c (a guard band around the image). Tiles are 16 x 16
+ * pixels; this view's tiles have the global ids tile_base + ty*Wt + tx with
+ * Wt = ceil(width/16). */
+typedef struct fg_camera {
+    float R[9];       /* row-major world->camera rotation */
+    float t[3];
+    float campos[3];  /* camera centre in world space (SH view direction) */
+    float fx, fy, cx, cy;
+    int32_t width, height;  /* 1..32768 */
+    float znear, kx, ky;
+    uint32_t tile_base;
+} fg_camera;
+
+/* Projected Gaussians ("splats"), device planes of capacity cap_sel entries,
+ * entry i describing the i-th selected node (sel_idx[i]). */
+typedef struct fg_splats {
+    float* xy;         /* [cap][2] 2D mean (u, v) in pixels */
+    float* conic_o;    /* [cap][4] (A, B, C, opacity): inverse 2D covariance
+                          [[A, B], [B, C]] and the node opacity */
+    float* rgb_depth;  /* [cap][4] colour (r, g, b) and camera-space depth */
+    uint16_t* rect;    /* [cap][4] tile rectangle [x0, x1) x [y0, y1) as
+                          (x0, y0, x1, y1); all zero when the splat emits nothing */
+    uint32_t* tiles;   /* [cap] (x1 - x0) * (y1 - y0): pairs this splat emits */
+} fg_splats;
+
+/* Speed-only knobs; results never depend on them. NULL = defaults. */
+typedef struct fg_tune {
+    int32_t render_batch;  /* splats staged in LDS per round: 32, 64, 128 or 256 (default 256) */
+    int32_t radix_bits;    /* digit width of the pair sort: 4..8 (default 8) */
+    int32_t reserved0;
+    int32_t reserved1;
+} fg_tune;
+
+/* ---- stage 1: traversal-free parallel filter (Sec. 3.2) ---------------- */
+
+/* Scratch bytes fg_filter needs for a tree of n_nodes nodes. */
+size_t fg_filter_workspace_size(int64_t n_nodes, int64_t n_internal_span);
+
+/* For every node n, independently:
+ *   F(n)     in-frustum test of the node centre (fg_camera);
+ *   small(n) F(n) and R_2D = 3 sqrt(lambda_max(Sigma_2D)) <= tau_R, with
+ *            Sigma_2D the EWA projection plus 0.3 px^2 on the diagonal
+ *            (R&L filter, Sec. 3.2; tau_R = 3 in the paper);
+ *   RL(n)    F(n) and (leaf(n) or small(n)) (leaf exemption);
+ *   sel(n)   RL(n) and no ancestor a of n has RL(a) (Ancestor filter).
+ * Outputs: sel_bits [ceil(N/32)] device words, bit n%32 of word n/32 = sel(n);
+ * sel_idx [cap_sel] device, the selected node ids in ascending order;
+ * *n_sel (device u32) the number selected; *status (device u32) is set to 0,
+ * then FG_STATUS_SEL_OVERFLOW / FG_STATUS_BAD_PARENT as they occur.
+ * Errors: FG_ERR_INVALID_ARG for null pointers or cap_sel < 0,
+ * FG_ERR_INVALID_TREE for n_nodes out of range, n_internal_span outside
+ * [0, n_nodes] or max_depth outside 0..15, FG_ERR_WORKSPACE. */
+int fg_filter(const fg_tree* tree, const fg_camera* cam, float tau_R, uint32_t* sel_bits, uint32_t* sel_idx,
+              int64_t cap_sel, uint32_t* n_sel, uint32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- stage 2: projection and shrunk extents (Sec. 3.1, Sec. 3.3) -------- */
+
+/* For i < min(*n_sel, cap_sel), node g = sel_idx[i]: camera-space centre,
+ * Sigma_2D (+0.3 px^2), conic = Sigma_2D^-1 (dropped when det <= 0), 2D mean,
+ * depth, colour 0.5 + sum_k sh_k Y_k(d) clamped at 0 with d the unit vector
+ * from campos to the mean and Y the orthonormal real SH basis, and the
+ * tile-set radius
+ *     r = 3 sqrt(lambda_max)                               if tau <= 0,
+ *     r = 0                                                if alpha0 <= tau,
+ *     r = min(3 sqrt(lambda_max), sqrt(2 lambda_max ln(alpha0 / tau)))  else
+ * (Sec. 3.3 "Gaussian Shrinking Strategy"; tau = lambda_G / G_bar, Eq. (8),
+ * or 1/255 for a fixed threshold). The rectangle holds every tile whose
+ * 16-px square meets [u - r, u + r] x [v - r, v + r]. Only the tile set
+ * shrinks; blending still evaluates the full Gaussian.
+ * Errors: FG_ERR_INVALID_ARG, FG_ERR_UNSUPPORTED (sh_degree > 3). */
+int fg_preprocess(const fg_tree* tree, const fg_camera* cam, float tau, const uint32_t* sel_idx,
+                  const uint32_t* n_sel, int64_t cap_sel, const fg_splats* out, uint32_t* status, void* stream);
+
+/* ---- stage 3: key emission, sort, ranges ------------------------------ */
+
+/* Scratch bytes fg_sort needs. */
+size_t fg_sort_workspace_size(int64_t cap_sel, int64_t cap_pairs, const fg_camera* cam);
+
+/* Orders the Gaussian-tile pairs by the key (tile id, depth bits) and then
+ * by splat index: splat i contributes one pair per tile of its rectangle.
+ * Outputs (device): tile_keys [cap_pairs] the sorted tile ids
+ * (tile_base + ty*Wt + tx), vals [cap_pairs] the matching splat indices (the
+ * full 64-bit key of entry k is tile_keys[k] << 32 | bits(depth[vals[k]]));
+ * *n_pairs (device u32); ranges [n_tiles][2] = [start, end) of each of this
+ * view's tiles in the sorted list ([0, 0) for an empty tile).
+ * Method: exclusive prefix scan of the tile counts in depth order, key
+ * emission, and stable LDS-staged LSD radix sorts (depth of the splats, then
+ * tile ids of the pairs), which gives the (tile, depth, index) order.
+ * Errors: FG_ERR_INVALID_ARG, FG_ERR_WORKSPACE; FG_STATUS_PAIR_OVERFLOW
+ * on the device when the pairs exceed cap_pairs. */
+int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t cap_sel, const fg_camera* cam,
+            uint32_t* tile_keys, uint32_t* vals, int64_t cap_pairs, uint32_t* n_pairs, uint32_t* ranges,
+            uint32_t* status, void* ws, size_t ws_bytes, const fg_tune* tune, void* stream);
+
+/* ---- stage 4: blending, Eq. (2) --------------------------------------- */
+
+/* For every pixel of tile t, front to back over ranges[t]:
+ *   power = -0.5 (A dx^2 + C dy^2) - B dx dy, d = (u, v) - pixel centre;
+ *   skip if power > 0; alpha = min(0.99, opacity exp(power)), skip if
+ *   alpha < 1/255; stop before a splat that would take T below 1e-4;
+ *   C += rgb alpha T; T *= (1 - alpha).
+ * Outputs (device): image [3][H][W] = C + T bg; final_T [H][W];
+ * n_contrib [H][W] = 1 + position (within the tile's range) of the last
+ * splat blended, 0 if none. bg is a host array of 3 floats.
+ * Errors: FG_ERR_INVALID_ARG. */
+int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
+              const float bg[3], float* image, float* final_T, uint32_t* n_contrib, const fg_tune* tune,
+              void* stream);
+
+/* Text for an FG_* return code. */
+const char* fg_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FG_H */

@@ -1,0 +1,485 @@
+// Gaussian-tile key emission, (tile, depth) ordering and per-tile ranges.
+//
+// The required order is ascending (tile id, depth bits, splat index). It is
+// reached with two stable sorts instead of one sort of 64-bit keys:
+//
+//   1. the splats are radix-sorted by their 32-bit depth key (ties keep
+//      ascending splat index);
+//   2. an exclusive prefix scan of the tile counts, taken in that depth
+//      order, gives each splat its output offset, and the splat emits one
+//      (tile id, splat index) pair per tile of its rectangle;
+//   3. the pairs are radix-sorted by tile id only (ceil(log2 tiles) bits),
+//      stably, so pairs of one tile keep the depth order of step 1.
+//
+// Pair traffic drops from ~6 passes over 12-byte (u64 key, u32 value)
+// records to 2 passes over 8-byte records at 1080p.
+//
+// Radix pass (LSD, one digit of BITS bits, stable), three kernels:
+//   k_hist      per 2048-item tile: digit histogram -> hist[digit][tile]
+//   k_rowscan   one workgroup per digit: exclusive scan over the tiles,
+//               digit totals
+//   k_scatter   per tile: stable local ranks (wave ballot match on the digit
+//               bits, per-wave counts combined in LDS in item order), items
+//               staged through LDS in locally sorted order, then written out
+//               so that consecutive lanes write consecutive addresses.
+#include "fg_device.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kIPT = 8;
+constexpr int kTileItems = kThreads * kIPT;  // 2048
+constexpr int kWaves = kThreads / fgd::kWave;
+constexpr int kEmitIPT = 8;
+constexpr int kEmitItems = kThreads * kEmitIPT;  // 2048
+
+__device__ __forceinline__ int64_t count_of(const uint32_t* p, int64_t cap)
+{
+    const int64_t n = (int64_t)*p;
+    return n < cap ? n : cap;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_wave, uint32_t& total)
+{
+    const int lane = fgd::lane_id();
+    const int wave = threadIdx.x / fgd::kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < fgd::kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, fgd::kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == fgd::kWave - 1) s_wave[wave] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) {
+        const uint32_t t = s_wave[w];
+        if (w < wave) before += t;
+        total += t;
+    }
+    __syncthreads();
+    return before + x - v;
+}
+
+template <int BITS>
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
+{
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < BITS; b++) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+template <int BITS>
+__global__ __launch_bounds__(kThreads) void k_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_p,
+                                                   int64_t cap, int shift, uint32_t* __restrict__ hist)
+{
+    constexpr int R = 1 << BITS;
+    __shared__ uint32_t h[R];
+    const int64_t n = count_of(n_p, cap);
+    const int64_t n_tiles = (n + kTileItems - 1) / kTileItems;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        for (int d = threadIdx.x; d < R; d += kThreads) h[d] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kIPT; r++) {
+            const int64_t idx = tile * kTileItems + r * kThreads + threadIdx.x;
+            const bool valid = idx < n;
+            const uint32_t d = valid ? (keys[idx] >> shift) & (R - 1) : 0u;
+            const uint64_t m = match_digit<BITS>(d, valid);
+            if (valid && (m & fgd::lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(m));
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < R; d += kThreads) hist[(int64_t)d * n_tiles + tile] = h[d];
+        __syncthreads();
+    }
+}
+
+// One workgroup per digit: exclusive scan of hist[digit][0..n_tiles) in place.
+__global__ __launch_bounds__(kThreads) void k_rowscan(const uint32_t* __restrict__ n_p, int64_t cap,
+                                                      uint32_t* __restrict__ hist, uint32_t* __restrict__ digit_total)
+{
+    __shared__ uint32_t s_wave[kWaves];
+    const int64_t n = count_of(n_p, cap);
+    const int64_t n_tiles = (n + kTileItems - 1) / kTileItems;
+    uint32_t* row = hist + (int64_t)blockIdx.x * n_tiles;
+    const int64_t per = (n_tiles + kThreads - 1) / kThreads;
+    const int64_t lo = threadIdx.x * per;
+    const int64_t hi = lo + per < n_tiles ? lo + per : n_tiles;
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; i++) s += row[i];
+    uint32_t total;
+    uint32_t run = block_excl_scan(s, s_wave, total);
+    for (int64_t i = lo; i < hi; i++) {
+        const uint32_t v = row[i];
+        row[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) digit_total[blockIdx.x] = total;
+}
+
+template <int BITS>
+__global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                      uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                      const uint32_t* __restrict__ n_p, int64_t cap, int shift,
+                                                      const uint32_t* __restrict__ hist,
+                                                      const uint32_t* __restrict__ digit_total)
+{
+    constexpr int R = 1 << BITS;
+    __shared__ uint32_t s_base[R];
+    __shared__ uint32_t s_run[R];
+    __shared__ uint32_t s_start[R];
+    __shared__ uint32_t s_wcnt[kWaves][R];
+    __shared__ uint32_t s_keys[kTileItems];
+    __shared__ uint32_t s_vals[kTileItems];
+    __shared__ uint32_t s_wave[kWaves];
+    const int64_t n = count_of(n_p, cap);
+    const int64_t n_tiles = (n + kTileItems - 1) / kTileItems;
+    const int tid = threadIdx.x;
+    const int wave = tid / fgd::kWave;
+    {
+        uint32_t tot;
+        const uint32_t v = tid < R ? digit_total[tid] : 0u;
+        const uint32_t e = block_excl_scan(v, s_wave, tot);
+        if (tid < R) s_base[tid] = e;
+    }
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        uint32_t k[kIPT], v[kIPT], rank[kIPT];
+#pragma unroll
+        for (int r = 0; r < kIPT; r++) {
+            const int64_t idx = tile * kTileItems + r * kThreads + tid;
+            const bool valid = idx < n;
+            k[r] = valid ? kin[idx] : 0xFFFFFFFFu;
+            v[r] = valid ? vin[idx] : 0u;
+        }
+        if (tid < R) s_run[tid] = 0;
+#pragma unroll
+        for (int r = 0; r < kIPT; r++) {
+            for (int d = tid; d < R * kWaves; d += kThreads) (&s_wcnt[0][0])[d] = 0;
+            __syncthreads();
+            const int64_t idx = tile * kTileItems + r * kThreads + tid;
+            const bool valid = idx < n;
+            const uint32_t d = (k[r] >> shift) & (R - 1);
+            const uint64_t m = match_digit<BITS>(d, valid);
+            const uint32_t below = (uint32_t)__popcll(m & fgd::lanemask_lt());
+            if (valid && below == 0) s_wcnt[wave][d] = (uint32_t)__popcll(m);
+            __syncthreads();
+            if (tid < R) {
+                uint32_t run = s_run[tid];
+#pragma unroll
+                for (int w = 0; w < kWaves; w++) {
+                    const uint32_t c = s_wcnt[w][tid];
+                    s_wcnt[w][tid] = run;
+                    run += c;
+                }
+                s_run[tid] = run;
+            }
+            __syncthreads();
+            rank[r] = s_wcnt[wave][d] + below;
+            __syncthreads();
+        }
+        {
+            uint32_t tot;
+            const uint32_t c = tid < R ? s_run[tid] : 0u;
+            const uint32_t e = block_excl_scan(c, s_wave, tot);
+            if (tid < R) s_start[tid] = e;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kIPT; r++) {
+            const int64_t idx = tile * kTileItems + r * kThreads + tid;
+            if (idx < n) {
+                const uint32_t d = (k[r] >> shift) & (R - 1);
+                const uint32_t pos = s_start[d] + rank[r];
+                s_keys[pos] = k[r];
+                s_vals[pos] = v[r];
+            }
+        }
+        __syncthreads();
+        const int64_t cnt = n - tile * kTileItems < kTileItems ? n - tile * kTileItems : kTileItems;
+#pragma unroll
+        for (int r = 0; r < kIPT; r++) {
+            const int p = r * kThreads + tid;
+            if (p < cnt) {
+                const uint32_t key = s_keys[p];
+                const uint32_t d = (key >> shift) & (R - 1);
+                const int64_t g = (int64_t)s_base[d] + hist[(int64_t)d * n_tiles + tile] + (p - s_start[d]);
+                kout[g] = key;
+                vout[g] = s_vals[p];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_depth_pack(const float4* __restrict__ rgb_depth,
+                                                         const uint32_t* __restrict__ n_p, int64_t cap,
+                                                         uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval)
+{
+    const int64_t n = count_of(n_p, cap);
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        dkey[i] = __float_as_uint(rgb_depth[i].w);
+        dval[i] = (uint32_t)i;
+    }
+}
+
+// Per 2048 splats in depth order: the sum of their tile counts.
+__global__ __launch_bounds__(kThreads) void k_count_reduce(const uint32_t* __restrict__ order,
+                                                           const uint32_t* __restrict__ tiles,
+                                                           const uint32_t* __restrict__ n_p, int64_t cap,
+                                                           uint32_t* __restrict__ bsum)
+{
+    __shared__ uint32_t s_wave[kWaves];
+    const int64_t n = count_of(n_p, cap);
+    const int64_t nblk = (n + kEmitItems - 1) / kEmitItems;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int r = 0; r < kEmitIPT; r++) {
+            const int64_t j = blk * kEmitItems + r * kThreads + threadIdx.x;
+            if (j < n) s += tiles[order[j]];
+        }
+        uint32_t total;
+        block_excl_scan(s, s_wave, total);
+        if (threadIdx.x == 0) bsum[blk] = total;
+    }
+}
+
+// One workgroup: exclusive scan of the block sums; n_pairs and overflow.
+__global__ __launch_bounds__(1024) void k_count_scan(uint32_t* __restrict__ bsum, const uint32_t* __restrict__ n_p,
+                                                     int64_t cap, int64_t cap_pairs, uint32_t* __restrict__ n_pairs,
+                                                     uint32_t* __restrict__ status)
+{
+    __shared__ unsigned long long part[1024];
+    const int64_t n = count_of(n_p, cap);
+    const int64_t nblk = (n + kEmitItems - 1) / kEmitItems;
+    const int t = threadIdx.x;
+    const int64_t per = (nblk + 1023) / 1024;
+    const int64_t lo = t * per;
+    const int64_t hi = lo + per < nblk ? lo + per : nblk;
+    unsigned long long s = 0;
+    for (int64_t i = lo; i < hi; i++) s += bsum[i];
+    part[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const unsigned long long v = t >= d ? part[t - d] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned long long run = part[t] - s;
+    for (int64_t i = lo; i < hi; i++) {
+        const uint32_t v = bsum[i];
+        bsum[i] = (uint32_t)(run < 0xFFFFFFFFull ? run : 0xFFFFFFFFull);
+        run += v;
+    }
+    if (t == 1023) {
+        const unsigned long long total = part[1023];
+        *n_pairs = (uint32_t)(total < 0xFFFFFFFFull ? total : 0xFFFFFFFFull);
+        if ((long long)total > cap_pairs) atomicOr(status, FG_STATUS_PAIR_OVERFLOW);
+    }
+}
+
+// Per 2048 splats in depth order (8 consecutive per thread): offsets by a
+// block scan plus the block's scanned sum, then one (tile id, splat) pair per
+// covered tile, rows then columns.
+__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles,
+                                                   const ushort4* __restrict__ rect, const uint32_t* __restrict__ n_p,
+                                                   int64_t cap, const uint32_t* __restrict__ bsum, int64_t cap_pairs,
+                                                   int Wt, uint32_t tile_base, uint32_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals)
+{
+    __shared__ uint32_t s_wave[kWaves];
+    const int64_t n = count_of(n_p, cap);
+    const int64_t nblk = (n + kEmitItems - 1) / kEmitItems;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t j0 = blk * kEmitItems + (int64_t)threadIdx.x * kEmitIPT;
+        uint32_t g[kEmitIPT], c[kEmitIPT];
+        uint32_t s = 0;
+#pragma unroll
+        for (int r = 0; r < kEmitIPT; r++) {
+            const int64_t j = j0 + r;
+            g[r] = j < n ? order[j] : 0u;
+            c[r] = j < n ? tiles[g[r]] : 0u;
+            s += c[r];
+        }
+        uint32_t total;
+        int64_t off = (int64_t)bsum[blk] + block_excl_scan(s, s_wave, total);
+#pragma unroll
+        for (int r = 0; r < kEmitIPT; r++) {
+            if (c[r]) {
+                const ushort4 q = rect[g[r]];
+                for (int ty = q.y; ty < q.w; ty++) {
+                    const uint32_t row = tile_base + (uint32_t)(ty * Wt);
+                    for (int tx = q.x; tx < q.z; tx++) {
+                        if (off < cap_pairs) {
+                            keys[off] = row + (uint32_t)tx;
+                            vals[off] = g[r];
+                        }
+                        ++off;
+                    }
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_ranges_clear(uint32_t* __restrict__ ranges, int64_t n_tiles)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 2 * n_tiles; t += (int64_t)gridDim.x * blockDim.x)
+        ranges[t] = 0u;
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_p, int64_t cap,
+                         uint32_t tile_base, int64_t n_tiles, uint32_t* __restrict__ ranges)
+{
+    const int64_t n = count_of(n_p, cap);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = keys[i];
+        const uint32_t t = k - tile_base;
+        if ((int64_t)t >= n_tiles) continue;
+        if (i == 0 || keys[i - 1] != k) ranges[2 * (int64_t)t] = (uint32_t)i;
+        if (i == n - 1 || keys[i + 1] != k) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+    }
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int64_t tiles_for(int64_t n) { return (n + kTileItems - 1) / kTileItems; }
+
+struct SortWs {
+    uint32_t *dkey0, *dval0, *dkey1, *dval1, *bsum, *kalt, *valt, *hist, *digit_total;
+};
+
+size_t carve(void* base, int64_t cap_sel, int64_t cap_pairs, SortWs* w)
+{
+    const int64_t ht = tiles_for(cap_sel > cap_pairs ? cap_sel : cap_pairs);
+    const size_t sizes[9] = {
+        (size_t)cap_sel * 4, (size_t)cap_sel * 4, (size_t)cap_sel * 4, (size_t)cap_sel * 4,
+        (size_t)((cap_sel + kEmitItems - 1) / kEmitItems + 1) * 4,
+        (size_t)cap_pairs * 4, (size_t)cap_pairs * 4,
+        (size_t)256 * (size_t)(ht + 1) * 4, (size_t)256 * 4};
+    uint32_t** dst[9] = {&w->dkey0, &w->dval0, &w->dkey1, &w->dval1, &w->bsum, &w->kalt, &w->valt, &w->hist,
+                         &w->digit_total};
+    size_t off = 0;
+    for (int i = 0; i < 9; i++) {
+        if (base) *dst[i] = (uint32_t*)((char*)base + off);
+        off += align_up(sizes[i] + 4);
+    }
+    return off;
+}
+
+template <int BITS>
+void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint32_t* n_p,
+                int64_t cap, int shift, const SortWs& w, hipStream_t s)
+{
+    int64_t grid = tiles_for(cap);
+    if (grid > 2048) grid = 2048;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_hist<BITS>, dim3((unsigned)grid), dim3(kThreads), 0, s, kin, n_p, cap, shift, w.hist);
+    hipLaunchKernelGGL(k_rowscan, dim3(1u << BITS), dim3(kThreads), 0, s, n_p, cap, w.hist, w.digit_total);
+    hipLaunchKernelGGL(k_scatter<BITS>, dim3((unsigned)grid), dim3(kThreads), 0, s, kin, vin, kout, vout, n_p, cap,
+                       shift, w.hist, w.digit_total);
+}
+
+void radix_pass_bits(int bits, const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                     const uint32_t* n_p, int64_t cap, int shift, const SortWs& w, hipStream_t s)
+{
+    switch (bits) {
+        case 4: radix_pass<4>(kin, vin, kout, vout, n_p, cap, shift, w, s); break;
+        case 5: radix_pass<5>(kin, vin, kout, vout, n_p, cap, shift, w, s); break;
+        case 6: radix_pass<6>(kin, vin, kout, vout, n_p, cap, shift, w, s); break;
+        case 7: radix_pass<7>(kin, vin, kout, vout, n_p, cap, shift, w, s); break;
+        default: radix_pass<8>(kin, vin, kout, vout, n_p, cap, shift, w, s); break;
+    }
+}
+
+}  // namespace
+
+extern "C" size_t fg_sort_workspace_size(int64_t cap_sel, int64_t cap_pairs, const fg_camera* cam)
+{
+    (void)cam;
+    if (cap_sel < 0 || cap_pairs < 0) return 0;
+    SortWs w;
+    return carve(nullptr, cap_sel, cap_pairs, &w);
+}
+
+extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t cap_sel, const fg_camera* cam,
+                       uint32_t* tile_keys, uint32_t* vals, int64_t cap_pairs, uint32_t* n_pairs, uint32_t* ranges,
+                       uint32_t* status, void* ws, size_t ws_bytes, const fg_tune* tune, void* stream)
+{
+    if (!splats || !n_sel || !cam || !n_pairs || !ranges || !status || cap_sel < 0 || cap_pairs < 0)
+        return FG_ERR_INVALID_ARG;
+    if (cap_sel >= ((int64_t)1 << 31) || cap_pairs >= ((int64_t)1 << 32) - 1) return FG_ERR_UNSUPPORTED;
+    if (cap_pairs > 0 && (!tile_keys || !vals)) return FG_ERR_INVALID_ARG;
+    if (cap_sel > 0 && (!splats->rgb_depth || !splats->rect || !splats->tiles)) return FG_ERR_INVALID_ARG;
+    if (cam->width <= 0 || cam->height <= 0) return FG_ERR_INVALID_ARG;
+    int bits = 8;
+    if (tune && tune->radix_bits) {
+        if (tune->radix_bits < 4 || tune->radix_bits > 8) return FG_ERR_INVALID_ARG;
+        bits = tune->radix_bits;
+    }
+    SortWs w;
+    const size_t need = carve(nullptr, cap_sel, cap_pairs, &w);
+    if (!ws || ws_bytes < need) return FG_ERR_WORKSPACE;
+    carve(ws, cap_sel, cap_pairs, &w);
+    hipStream_t s = (hipStream_t)stream;
+    const int Wt = (cam->width + 15) / 16, Ht = (cam->height + 15) / 16;
+    const int64_t n_tiles = (int64_t)Wt * Ht;
+    const uint64_t max_tile = (uint64_t)cam->tile_base + (uint64_t)n_tiles - 1;
+    if (max_tile > 0xFFFFFFFFull) return FG_ERR_UNSUPPORTED;
+
+    hipLaunchKernelGGL(k_ranges_clear, dim3((unsigned)((2 * n_tiles + 255) / 256 < 1024 ? (2 * n_tiles + 255) / 256 : 1024)),
+                       dim3(256), 0, s, ranges, n_tiles);
+    if (cap_sel == 0) {
+        hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(1024), 0, s, w.bsum, n_sel, cap_sel, cap_pairs, n_pairs, status);
+        return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
+    }
+    // 1. depth order of the splats (4 passes of 8 bits, result back in buffer 0)
+    int64_t g1 = (cap_sel + kThreads - 1) / kThreads;
+    if (g1 > 4096) g1 = 4096;
+    hipLaunchKernelGGL(k_depth_pack, dim3((unsigned)g1), dim3(kThreads), 0, s, (const float4*)splats->rgb_depth, n_sel,
+                       cap_sel, w.dkey0, w.dval0);
+    for (int p = 0; p < 4; p++) {
+        const bool even = (p % 2) == 0;
+        radix_pass<8>(even ? w.dkey0 : w.dkey1, even ? w.dval0 : w.dval1, even ? w.dkey1 : w.dkey0,
+                      even ? w.dval1 : w.dval0, n_sel, cap_sel, 8 * p, w, s);
+    }
+    // 2. scan of the tile counts in depth order and key emission
+    int64_t ge = (cap_sel + kEmitItems - 1) / kEmitItems;
+    if (ge > 4096) ge = 4096;
+    hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)ge), dim3(kThreads), 0, s, w.dval0, splats->tiles, n_sel, cap_sel,
+                       w.bsum);
+    hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(1024), 0, s, w.bsum, n_sel, cap_sel, cap_pairs, n_pairs, status);
+    int tile_bits = 1;
+    while (tile_bits < 32 && (max_tile >> tile_bits) != 0) ++tile_bits;
+    const int passes = (tile_bits + bits - 1) / bits;
+    // emit into the buffer that the last pass will not write
+    uint32_t* ek = (passes % 2) ? w.kalt : tile_keys;
+    uint32_t* ev = (passes % 2) ? w.valt : vals;
+    if (cap_pairs > 0) {
+        hipLaunchKernelGGL(k_emit, dim3((unsigned)ge), dim3(kThreads), 0, s, w.dval0, splats->tiles,
+                           (const ushort4*)splats->rect, n_sel, cap_sel, w.bsum, cap_pairs, Wt, cam->tile_base, ek, ev);
+        // 3. stable sort of the pairs by tile id
+        uint32_t *ka = ek, *va = ev, *kb = (ek == tile_keys) ? w.kalt : tile_keys, *vb = (ev == vals) ? w.valt : vals;
+        for (int p = 0; p < passes; p++) {
+            radix_pass_bits(bits, ka, va, kb, vb, n_pairs, cap_pairs, bits * p, w, s);
+            uint32_t* t;
+            t = ka; ka = kb; kb = t;
+            t = va; va = vb; vb = t;
+        }
+        int64_t gr = (cap_pairs + 255) / 256;
+        if (gr > 4096) gr = 4096;
+        hipLaunchKernelGGL(k_ranges, dim3((unsigned)gr), dim3(256), 0, s, tile_keys, n_pairs, cap_pairs, cam->tile_base,
+                           n_tiles, ranges);
+    }
+    (void)Ht;
+    return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
+}

@@ -1,0 +1,287 @@
+"""Python binding of libfg.so (include/fg.h): argument marshalling only.
+
+Every entry point of the C-ABI has a function of the same name here that
+takes torch CUDA tensors, passes their device pointers and the stream of
+torch's current stream, and raises ``FgError`` on a negative return code.
+All computation happens in the HIP kernels; this module never computes any
+part of the frame itself and has no CPU fallback: without the built library
+it raises.
+
+``DeviceTree`` uploads a tree; ``FrameBuffers`` owns the buffers of one view
+and ``render_frame`` chains the four stages.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfg.so")
+
+FG_STATUS_SEL_OVERFLOW = 1
+FG_STATUS_PAIR_OVERFLOW = 2
+FG_STATUS_BAD_PARENT = 4
+
+
+class FgError(RuntimeError):
+    pass
+
+
+class FgTree(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_internal_span", C.c_int64), ("sh_degree", C.c_int32),
+                ("max_depth", C.c_int32), ("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p), ("parent", C.c_void_p), ("flags", C.c_void_p)]
+
+
+class FgCamera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("campos", C.c_float * 3), ("fx", C.c_float),
+                ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float), ("width", C.c_int32),
+                ("height", C.c_int32), ("znear", C.c_float), ("kx", C.c_float), ("ky", C.c_float),
+                ("tile_base", C.c_uint32)]
+
+
+class FgSplats(C.Structure):
+    _fields_ = [("xy", C.c_void_p), ("conic_o", C.c_void_p), ("rgb_depth", C.c_void_p), ("rect", C.c_void_p),
+                ("tiles", C.c_void_p)]
+
+
+class FgTune(C.Structure):
+    _fields_ = [("render_batch", C.c_int32), ("radix_bits", C.c_int32), ("reserved0", C.c_int32),
+                ("reserved1", C.c_int32)]
+
+
+EXPORTS = ["fg_filter_workspace_size", "fg_filter", "fg_preprocess", "fg_sort_workspace_size", "fg_sort",
+           "fg_render", "fg_status_string"]
+
+_lib = None
+
+
+def lib():
+    """Load libfg.so (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FgError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_23891_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, f32, i32 = C.c_void_p, C.c_int64, C.c_float, C.c_int
+        L.fg_filter_workspace_size.restype = C.c_size_t
+        L.fg_filter_workspace_size.argtypes = [i64, i64]
+        L.fg_filter.restype = i32
+        L.fg_filter.argtypes = [vp, vp, f32, vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
+        L.fg_preprocess.restype = i32
+        L.fg_preprocess.argtypes = [vp, vp, f32, vp, vp, i64, vp, vp, vp]
+        L.fg_sort_workspace_size.restype = C.c_size_t
+        L.fg_sort_workspace_size.argtypes = [i64, i64, vp]
+        L.fg_sort.restype = i32
+        L.fg_sort.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp, vp, C.c_size_t, vp, vp]
+        L.fg_render.restype = i32
+        L.fg_render.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.fg_status_string.restype = C.c_char_p
+        L.fg_status_string.argtypes = [i32]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise FgError(f"{what}: {lib().fg_status_string(rc).decode()} ({rc})")
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _ref(s):
+    return C.cast(C.pointer(s), C.c_void_p)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def camera_struct(cam) -> FgCamera:
+    c = FgCamera()
+    c.R[:] = [float(v) for v in np.asarray(cam.R, np.float32)]
+    c.t[:] = [float(v) for v in np.asarray(cam.t, np.float32)]
+    c.campos[:] = [float(v) for v in np.asarray(cam.campos, np.float32)]
+    c.fx, c.fy, c.cx, c.cy = cam.fx, cam.fy, cam.cx, cam.cy
+    c.width, c.height = cam.width, cam.height
+    c.znear, c.kx, c.ky = cam.znear, cam.kx, cam.ky
+    c.tile_base = cam.tile_base
+    return c
+
+
+def tune_struct(render_batch: int = 0, radix_bits: int = 0) -> FgTune:
+    return FgTune(render_batch=render_batch, radix_bits=radix_bits, reserved0=0, reserved1=0)
+
+
+# ---------------------------------------------------------------------------
+# device-resident inputs and outputs
+# ---------------------------------------------------------------------------
+class DeviceTree:
+    """A synth.Tree (or equivalent arrays) uploaded to the GPU as the fg_tree planes."""
+
+    def __init__(self, tree, device="cuda"):
+        def up(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a).view(dt)).to(device)
+
+        self.mean = up(tree.mean.astype(np.float32), np.float32)
+        self.scale = up(tree.scale.astype(np.float32), np.float32)
+        self.quat = up(tree.quat.astype(np.float32), np.float32)
+        self.opacity = up(tree.opacity.astype(np.float32), np.float32)
+        self.sh = up(tree.sh.astype(np.float32), np.float32)
+        self.parent = up(tree.parent.astype(np.int32), np.int32)
+        self.flags = up(tree.flags.astype(np.uint8), np.uint8)
+        self.n_nodes = int(tree.parent.shape[0])
+        self.n_internal_span = int(tree.n_internal_span)
+        self.sh_degree = int(tree.sh_degree)
+        self.max_depth = int(tree.max_depth)
+
+    def struct(self) -> FgTree:
+        return FgTree(n_nodes=self.n_nodes, n_internal_span=self.n_internal_span, sh_degree=self.sh_degree,
+                      max_depth=self.max_depth, mean=self.mean.data_ptr(), scale=self.scale.data_ptr(),
+                      quat=self.quat.data_ptr(), opacity=self.opacity.data_ptr(), sh=self.sh.data_ptr(),
+                      parent=self.parent.data_ptr(), flags=self.flags.data_ptr())
+
+
+class Splats:
+    """Device planes of fg_splats with capacity cap."""
+
+    def __init__(self, cap: int, device="cuda"):
+        cap = max(int(cap), 1)
+        self.cap = cap
+        self.xy = torch.empty((cap, 2), dtype=torch.float32, device=device)
+        self.conic_o = torch.empty((cap, 4), dtype=torch.float32, device=device)
+        self.rgb_depth = torch.empty((cap, 4), dtype=torch.float32, device=device)
+        self.rect = torch.empty((cap, 4), dtype=torch.int16, device=device)
+        self.tiles = torch.empty((cap,), dtype=torch.int32, device=device)
+
+    def struct(self) -> FgSplats:
+        return FgSplats(xy=self.xy.data_ptr(), conic_o=self.conic_o.data_ptr(), rgb_depth=self.rgb_depth.data_ptr(),
+                        rect=self.rect.data_ptr(), tiles=self.tiles.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# the C-ABI, one function per entry point
+# ---------------------------------------------------------------------------
+def fg_filter_workspace_size(n_nodes: int, n_internal_span: int) -> int:
+    return int(lib().fg_filter_workspace_size(n_nodes, n_internal_span))
+
+
+def fg_sort_workspace_size(cap_sel: int, cap_pairs: int, cam) -> int:
+    cs = camera_struct(cam)
+    return int(lib().fg_sort_workspace_size(cap_sel, cap_pairs, _ref(cs)))
+
+
+def fg_filter(tree: DeviceTree, cam, tau_R: float, sel_bits, sel_idx, cap_sel: int, n_sel, status, ws,
+              stream=None):
+    ts, cs = tree.struct(), camera_struct(cam)
+    _check(lib().fg_filter(_ref(ts), _ref(cs), C.c_float(tau_R), _p(sel_bits), _p(sel_idx), cap_sel, _p(n_sel),
+                           _p(status), _p(ws), ws.numel() * ws.element_size(), _stream(stream)), "fg_filter")
+
+
+def fg_preprocess(tree: DeviceTree, cam, tau: float, sel_idx, n_sel, cap_sel: int, out: Splats, status,
+                  stream=None):
+    ts, cs, ss = tree.struct(), camera_struct(cam), out.struct()
+    _check(lib().fg_preprocess(_ref(ts), _ref(cs), C.c_float(tau), _p(sel_idx), _p(n_sel), cap_sel, _ref(ss),
+                               _p(status), _stream(stream)), "fg_preprocess")
+
+
+def fg_sort(splats: Splats, n_sel, cap_sel: int, cam, tile_keys, vals, cap_pairs: int, n_pairs, ranges, status, ws,
+            tune: Optional[FgTune] = None, stream=None):
+    ss, cs = splats.struct(), camera_struct(cam)
+    _check(lib().fg_sort(_ref(ss), _p(n_sel), cap_sel, _ref(cs), _p(tile_keys), _p(vals), cap_pairs, _p(n_pairs),
+                         _p(ranges), _p(status), _p(ws), ws.numel() * ws.element_size(),
+                         _ref(tune) if tune is not None else None, _stream(stream)), "fg_sort")
+
+
+def fg_render(splats: Splats, vals, ranges, cam, bg: Sequence[float], image, final_T, n_contrib,
+              tune: Optional[FgTune] = None, stream=None):
+    ss, cs = splats.struct(), camera_struct(cam)
+    bgv = (C.c_float * 3)(*[float(b) for b in bg])
+    _check(lib().fg_render(_ref(ss), _p(vals), _p(ranges), _ref(cs), C.cast(bgv, C.c_void_p), _p(image),
+                           _p(final_T), _p(n_contrib), _ref(tune) if tune is not None else None, _stream(stream)),
+           "fg_render")
+
+
+# ---------------------------------------------------------------------------
+# one view's buffers and the four-stage frame
+# ---------------------------------------------------------------------------
+class FrameBuffers:
+    """All buffers of one view; capacities are fixed at construction."""
+
+    def __init__(self, tree: DeviceTree, width: int, height: int, cap_sel: int, cap_pairs: int, device="cuda"):
+        self.width, self.height = width, height
+        self.cap_sel, self.cap_pairs = int(cap_sel), int(cap_pairs)
+        N = tree.n_nodes
+        i32 = torch.int32
+        self.sel_bits = torch.empty(max((N + 31) // 32, 1), dtype=i32, device=device)
+        self.sel_idx = torch.empty(max(self.cap_sel, 1), dtype=i32, device=device)
+        self.counts = torch.zeros(4, dtype=i32, device=device)  # n_sel, n_pairs, status, spare
+        self.filter_ws = torch.empty(fg_filter_workspace_size(N, tree.n_internal_span), dtype=torch.uint8,
+                                     device=device)
+        self.splats = Splats(self.cap_sel, device)
+        n_tiles = ((width + 15) // 16) * ((height + 15) // 16)
+        self.tile_keys = torch.empty(max(self.cap_pairs, 1), dtype=i32, device=device)
+        self.vals = torch.empty(max(self.cap_pairs, 1), dtype=i32, device=device)
+        self.ranges = torch.empty((n_tiles, 2), dtype=i32, device=device)
+
+        class _C:  # camera of this size, only for the workspace query
+            R = np.eye(3, dtype=np.float32).reshape(9); t = np.zeros(3, np.float32); campos = t
+            fx = fy = cx = cy = 1.0; znear = 0.2; kx = ky = 1.0; tile_base = 0
+        _C.width, _C.height = width, height
+        self.sort_ws = torch.empty(fg_sort_workspace_size(self.cap_sel, self.cap_pairs, _C), dtype=torch.uint8,
+                                   device=device)
+        self.image = torch.empty((3, height, width), dtype=torch.float32, device=device)
+        self.final_T = torch.empty((height, width), dtype=torch.float32, device=device)
+        self.n_contrib = torch.empty((height, width), dtype=i32, device=device)
+
+    @property
+    def n_sel(self):
+        return self.counts[0:1]
+
+    @property
+    def n_pairs(self):
+        return self.counts[1:2]
+
+    @property
+    def status(self):
+        return self.counts[2:3]
+
+
+def filter_stage(tree, cam, fb: FrameBuffers, tau_R=3.0, stream=None):
+    fg_filter(tree, cam, tau_R, fb.sel_bits, fb.sel_idx, fb.cap_sel, fb.n_sel, fb.status, fb.filter_ws, stream)
+
+
+def preprocess_stage(tree, cam, fb: FrameBuffers, tau=0.0, stream=None):
+    fg_preprocess(tree, cam, tau, fb.sel_idx, fb.n_sel, fb.cap_sel, fb.splats, fb.status, stream)
+
+
+def sort_stage(cam, fb: FrameBuffers, tune=None, stream=None):
+    fg_sort(fb.splats, fb.n_sel, fb.cap_sel, cam, fb.tile_keys, fb.vals, fb.cap_pairs, fb.n_pairs, fb.ranges,
+            fb.status, fb.sort_ws, tune, stream)
+
+
+def render_stage(cam, fb: FrameBuffers, bg=(0.0, 0.0, 0.0), tune=None, stream=None):
+    fg_render(fb.splats, fb.vals, fb.ranges, cam, bg, fb.image, fb.final_T, fb.n_contrib, tune, stream)
+
+
+def render_frame(tree: DeviceTree, cam, fb: FrameBuffers, tau_R: float = 3.0, tau: float = 0.0,
+                 bg=(0.0, 0.0, 0.0), tune: Optional[FgTune] = None, stream=None):
+    """Filter, preprocess, sort and blend one view into fb (asynchronous)."""
+    filter_stage(tree, cam, fb, tau_R, stream)
+    preprocess_stage(tree, cam, fb, tau, stream)
+    sort_stage(cam, fb, tune, stream)
+    render_stage(cam, fb, bg, tune, stream)
+
+
+def read_counts(fb: FrameBuffers):
+    """(n_sel, n_pairs, status) copied to the host (synchronises)."""
+    c = fb.counts.cpu().numpy().view(np.uint32)
+    return int(c[0]), int(c[1]), int(c[2])
