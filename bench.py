@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the FilterGS frame path on one MI355X.
+
+Workload: the 20,000,003-node synthetic city LoD tree (17.5M leaves, 8 levels,
+SH degree 3, 600 x 600 x 50 m) seen by the 64-frame 1920x1080 fly-through at
+40 m altitude; tau_R = 3 px (Sec. 3.2) and the scene's GTC threshold
+tau = lambda_G / G_bar with lambda_G = 0.2 (Eq. (8), Sec. 4.1).
+
+A step is one frame: fg_filter, fg_preprocess, fg_sort and fg_render on the
+device-resident tree. FPS = timed frames / wall time between two device
+synchronisations (frames divided by cumulative time, as in Sec. 4.1).
+Per-stage times come from HIP events recorded on the stream the kernels run
+on. Prints one JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--steps 64] [--warmup 5] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# fp32 VALU issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation
+# per lane per clock (no packed-fp32 issue, no contraction into FMA).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# fp32 operations of the blend per fragment class (the arithmetic of Eq. (2)
+# as evaluated: each add, multiply, compare or fused multiply-add is one op)
+OPS_EVAL, OPS_EXP, OPS_PASS, OPS_BLEND = 12, 16, 3, 9
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pct(x, q):
+    return float(np.percentile(np.asarray(x, np.float64), q))
+
+
+def filter_bytes(tree, small_words, n_sel):
+    """Bytes the filter must move for one frame: parent of every node, flags,
+    mean/scale/quat of internal nodes, the mean of every leaf that no small
+    ancestor culls, the small bits, the selection mask and the compacted ids."""
+    N, span = tree.n_nodes, tree.n_internal_span
+    small = ((small_words[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1).reshape(-1)[:span].astype(bool)
+    culled = np.zeros(N, bool)
+    offs = np.cumsum([0] + tree.level_sizes)
+    for lvl in range(1, len(tree.level_sizes)):
+        a, b = offs[lvl], offs[lvl + 1]
+        p = tree.parent[a:b]
+        culled[a:b] = culled[p] | small[p]
+    leaves_tested = int((~culled[span:]).sum())
+    return (4 * N + 41 * span + span // 8 + 12 * leaves_tested + N // 8 + 4 * n_sel), leaves_tested
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        log("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'Sharding').")
+        sys.exit(2)
+
+    import torch
+    from paper_2603_23891_amd import fg, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    fg.lib()
+    with open(os.path.join(ROOT, "tests", "golden", "city_tau.json")) as f:
+        tau = float(json.load(f)["city20m"]["tau"])
+    tau_R = synth.TAU_R
+
+    t0 = time.time()
+    log("generating the 20M-node city tree ...")
+    tree = synth.city_tree(synth.CITY20M)
+    log(f"  {tree.n_nodes} nodes, levels {tree.level_sizes}, {time.time() - t0:.1f} s")
+    dtree = fg.DeviceTree(tree)
+    torch.cuda.synchronize()
+    log(f"  uploaded, {time.time() - t0:.1f} s")
+    cams = synth.city20m_frames(64)
+    W, H = cams[0].width, cams[0].height
+    fb = fg.FrameBuffers(dtree, W, H, cap_sel=8_000_000, cap_pairs=48_000_000)
+    stream = torch.cuda.current_stream()
+
+    def frame(cam, stats=None, ev=None):
+        if ev: ev[0].record(stream)
+        fg.filter_stage(dtree, cam, fb, tau_R)
+        if ev: ev[1].record(stream)
+        fg.preprocess_stage(dtree, cam, fb, tau)
+        if ev: ev[2].record(stream)
+        fg.sort_stage(cam, fb)
+        if ev: ev[3].record(stream)
+        fg.render_stage(cam, fb, frag_stats=stats)
+        if ev: ev[4].record(stream)
+
+    for k in range(args.warmup):
+        frame(cams[k % 64])
+    torch.cuda.synchronize()
+    K = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(K):
+        frame(cams[k % 64], ev=evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    fps = K / wall
+    stage_names = ["filter", "preprocess", "sort", "render"]
+    st = {n: [evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(K)] for i, n in enumerate(stage_names)}
+    frame_ms = [evs[k][0].elapsed_time(evs[k][4]) for k in range(K)]
+    log(f"timed {K} frames: {fps:.1f} FPS, {1e3 * wall / K:.3f} ms/frame wall")
+
+    # untimed pass over the same frames: counts and fragment statistics
+    counts = []
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    tot = dict(filter=0.0, preprocess=0.0, sort=0.0, render_ops=0.0, frags_blended=0, frags_eval=0)
+    n_frames_used = min(K, 64)
+    for k in range(n_frames_used):
+        stats.zero_()
+        frame(cams[k], stats=stats)
+        torch.cuda.synchronize()
+        n_sel, n_pairs, status = fg.read_counts(fb)
+        assert status == 0, f"frame {k}: status {status}"
+        words = fb.filter_ws[: 4 * ((tree.n_internal_span + 31) // 32)].cpu().numpy().view(np.uint32)
+        fbytes, leaves_tested = filter_bytes(tree, words, n_sel)
+        s = stats.cpu().numpy().astype(np.float64)
+        n_tiles = cams[k].n_tiles
+        passes = int(np.ceil(max(1, int(n_tiles - 1).bit_length()) / 8))
+        sbytes = n_sel * (12 + 4 * 20 + 8 + 16) + n_pairs * (8 + 20 * passes + 4) + 8 * n_tiles
+        pbytes = 292 * n_sel
+        ops = OPS_EVAL * s[0] + OPS_EXP * s[1] + OPS_PASS * s[2] + OPS_BLEND * s[3]
+        counts.append(dict(n_sel=n_sel, n_pairs=n_pairs, leaves_tested=leaves_tested, frags_eval=int(s[0]),
+                           frags_blended=int(s[3])))
+        tot["filter"] += fbytes
+        tot["preprocess"] += pbytes
+        tot["sort"] += sbytes
+        tot["render_ops"] += ops
+        tot["frags_blended"] += int(s[3])
+        tot["frags_eval"] += int(s[0])
+    f = n_frames_used
+    mean_ms = {n: float(np.mean(st[n][:f])) for n in stage_names}
+    stages = {}
+    for n in ("filter", "preprocess", "sort"):
+        gbs = (tot[n] / f) / (mean_ms[n] * 1e-3) / 1e9
+        stages[n] = dict(ms_median=pct(st[n], 50), ms_p95=pct(st[n], 95), bound="hbm",
+                         bytes_per_frame=tot[n] / f, achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS)
+    tops = (tot["render_ops"] / f) / (mean_ms["render"] * 1e-3) / 1e12
+    stages["render"] = dict(ms_median=pct(st["render"], 50), ms_p95=pct(st["render"], 95), bound="alu",
+                            ops_per_frame=tot["render_ops"] / f, achieved_Tops=tops, frac=tops / VALU_PEAK_TOPS,
+                            blended_frags_per_s=(tot["frags_blended"] / f) / (mean_ms["render"] * 1e-3),
+                            evaluated_frags_per_s=(tot["frags_eval"] / f) / (mean_ms["render"] * 1e-3))
+    dominant = max(stage_names, key=lambda n: mean_ms[n])
+    d = stages[dominant]
+    if d["bound"] == "alu":
+        roofline = dict(bound="alu", kernel="k_render", achieved=d["achieved_Tops"], peak=VALU_PEAK_TOPS,
+                        unit="TFLOP/s", frac=d["frac"], traffic=None)
+    else:
+        roofline = dict(bound="hbm", kernel=dominant, achieved=d["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=d["frac"], traffic=None)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("CPU oracle on frame 0 ...")
+        t1 = time.perf_counter()
+        ref = oracle.render_frame(tree, cams[0], tau_R, tau)
+        dt = time.perf_counter() - t1
+        assert ref["sel_idx"].size == counts[0]["n_sel"] and ref["keys"].size == counts[0]["n_pairs"]
+        cpu = dict(value=1.0 / dt, unit="frames/s", cores=1, kind="oracle",
+                   sample=f"frame 0 of the fly-through, all four stages, single-threaded C ({dt:.1f} s)")
+        log(f"  oracle frame 0: {dt:.1f} s")
+
+    cnt = {k: [c[k] for c in counts] for k in counts[0]}
+    out = {
+        "metric": "FPS @1080p, 20M-node LoD tree (filter+shrink+raster); fwd+bwd ms/view",
+        "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "city20m fly-through: 20,000,003-node LoD tree (17.5M leaves, 8 levels, SH3), "
+                               "64 frames 1920x1080 at 40 m altitude, pitch -20 deg",
+                   "tau_R": tau_R, "tau": tau, "lambda_G": synth.LAMBDA_G,
+                   "n_sel_mean": float(np.mean(cnt["n_sel"])), "n_pairs_mean": float(np.mean(cnt["n_pairs"])),
+                   "n_pairs_max": int(np.max(cnt["n_pairs"]))},
+        "stage_ms": {n: dict(median=pct(st[n], 50), p95=pct(st[n], 95)) for n in stage_names},
+        "frame_ms_events": dict(median=pct(frame_ms, 50), p95=pct(frame_ms, 95)),
+        "stages": stages,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fwd_bwd_ms_per_view": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

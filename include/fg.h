@@ -68,8 +68,12 @@ extern "C" {
 /* ---- device status bits ------------------------------------------------ */
 #define FG_STATUS_SEL_OVERFLOW 1u   /* more selected nodes than cap_sel */
 #define FG_STATUS_PAIR_OVERFLOW 2u  /* more Gaussian-tile pairs than cap_pairs */
-#define FG_STATUS_BAD_PARENT 4u     /* a parent index >= the child's index or
-                                       an ancestor chain longer than max_depth */
+#define FG_STATUS_BAD_PARENT 4u     /* a parent index >= the child's index, a
+                                       parent that is a leaf, or an ancestor chain
+                                       longer than max_depth */
+#define FG_STATUS_LOOKBACK_STALL 8u /* a compaction workgroup gave up waiting for
+                                       its predecessor (never expected; outputs
+                                       of the frame are then undefined) */
 
 /* ---- inputs ------------------------------------------------------------ */
 
@@ -123,7 +127,7 @@ typedef struct fg_splats {
 
 /* Speed-only knobs; results never depend on them. NULL = defaults. */
 typedef struct fg_tune {
-    int32_t render_batch;  /* splats staged in LDS per round: 32, 64, 128 or 256 (default 256) */
+    int32_t render_batch;  /* splats per blend work item (chunk): 256, 512 or 1024 (default 512) */
     int32_t radix_bits;    /* digit width of the pair sort: 4..8 (default 8) */
     int32_t reserved0;
     int32_t reserved1;
@@ -192,6 +196,9 @@ int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t cap_sel, con
 
 /* ---- stage 4: blending, Eq. (2) --------------------------------------- */
 
+/* Scratch bytes fg_render needs for this image size and pair capacity. */
+size_t fg_render_workspace_size(const fg_camera* cam, int64_t cap_pairs, const fg_tune* tune);
+
 /* For every pixel of tile t, front to back over ranges[t]:
  *   power = -0.5 (A dx^2 + C dy^2) - B dx dy, d = (u, v) - pixel centre;
  *   skip if power > 0; alpha = min(0.99, opacity exp(power)), skip if
@@ -199,10 +206,19 @@ int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t cap_sel, con
  *   C += rgb alpha T; T *= (1 - alpha).
  * Outputs (device): image [3][H][W] = C + T bg; final_T [H][W];
  * n_contrib [H][W] = 1 + position (within the tile's range) of the last
- * splat blended, 0 if none. bg is a host array of 3 floats.
- * Errors: FG_ERR_INVALID_ARG. */
+ * splat blended, 0 if none. bg is a host array of 3 floats. cap_pairs is
+ * the capacity the sort ran with (it bounds the range lengths and sizes the
+ * workspace). Long ranges are cut into chunks whose skip tests run in
+ * parallel; the transmittance chain still runs in list order, so results are
+ * those of one sequential pass.
+ * frag_stats: NULL, or 4 device counters that the call adds to (the caller
+ * zeroes them): [0] (pixel, splat) tests evaluated, [1] tests that reach the
+ * exponential (-5.6 <= power <= 0), [2] tests with alpha >= 1/255, [3] splats
+ * blended. Results do not depend on whether counting is on.
+ * Errors: FG_ERR_INVALID_ARG, FG_ERR_WORKSPACE; FG_STATUS_LOOKBACK_STALL. */
 int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
-              const float bg[3], float* image, float* final_T, uint32_t* n_contrib, const fg_tune* tune,
+              const float bg[3], float* image, float* final_T, uint32_t* n_contrib, int64_t cap_pairs,
+              unsigned long long* frag_stats, uint32_t* status, void* ws, size_t ws_bytes, const fg_tune* tune,
               void* stream);
 
 /* Text for an FG_* return code. */

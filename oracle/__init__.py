@@ -69,6 +69,7 @@ def lib():
         L.fgo_sort.argtypes = [vp, i64, vp, vp, vp, vp]
         L.fgo_render.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.fgo_render_pixels.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp]
+        L.fgo_kpc.argtypes = [vp, vp, vp, vp, vp]
         assert L.fgo_splat_size() == SPLAT_DTYPE.itemsize
         _lib = L
     return _lib
@@ -234,3 +235,39 @@ def render_frame(tree, cam, tau_R: float = 3.0, tau: float = 0.0, bg=(0.0, 0.0, 
     img, T, nc = render(splats, vals, ranges, cam, bg)
     return dict(sel_mask=mask, sel_idx=sel, splats=splats, keys=keys, vals=vals, ranges=ranges, image=img,
                 final_T=T, n_contrib=nc)
+
+
+def kpc(splats, vals, ranges, cam) -> np.ndarray:
+    """Key-value pair contribution (Eq. (5)) of every sorted pair, float64."""
+    splats = np.ascontiguousarray(splats)
+    vals = np.ascontiguousarray(vals, np.uint32)
+    ranges = np.ascontiguousarray(ranges, np.uint32)
+    cs, cp = _cam_ptr(cam)
+    out = np.zeros(max(vals.size, 1), np.float64)
+    lib().fgo_kpc(_ptr(splats), _ptr(vals if vals.size else np.zeros(1, np.uint32)), _ptr(ranges), cp, _ptr(out))
+    return out[: vals.size]
+
+
+def gtc_view(kpc_pairs, ranges) -> float:
+    """View GTC (Eq. (7)): mean over the tiles that hold pairs of the tile GTC
+    (Eq. (6)), the mean KPC over all pairs of the tile."""
+    ranges = np.asarray(ranges).reshape(-1, 2).astype(np.int64)
+    g = []
+    for lo, hi in ranges:
+        if hi > lo:
+            g.append(kpc_pairs[lo:hi].sum() / (hi - lo))
+    return float(np.mean(g)) if g else 0.0
+
+
+def scene_tau(tree, cams, lambda_G: float = 0.2, tau_R: float = 3.0) -> dict:
+    """Eq. (8): G_bar = mean of the view GTCs (3-sigma extents, the filtered
+    cut), tau = lambda_G / G_bar."""
+    t = _tree_ref(tree)
+    gv = []
+    for cam in cams:
+        _, sel = filter(t, cam, tau_R)
+        sp = preprocess(t, cam, 0.0, sel)
+        keys, vals, ranges = sort(sp, cam)
+        gv.append(gtc_view(kpc(sp, vals, ranges, cam), ranges))
+    G = float(np.mean(gv))
+    return dict(G_views=gv, G_bar=G, lambda_G=lambda_G, tau=lambda_G / G)

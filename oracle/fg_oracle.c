@@ -548,3 +548,45 @@ void fgo_log_array(const float* x, float* y, int64_t n)
 {
     for (int64_t i = 0; i < n; i++) y[i] = fgo_log(x[i]);
 }
+
+/* ---------------------------------------------------------------------- */
+/* Key-value pair contribution, Eq. (5)                                   */
+/* ---------------------------------------------------------------------- */
+
+/* KPC of every pair of the sorted list: for each pixel of tile t, the
+ * product alpha * T (T the transmittance before the splat) of each splat the
+ * pixel actually blends is added to that pair's entry, in float64. Pairs a
+ * pixel skips (power > 0, alpha < 1/255) or never reaches (terminated)
+ * receive nothing from it. kpc has one entry per sorted pair. */
+void fgo_kpc(const fgo_splat* s, const uint32_t* vals, const uint32_t* ranges, const fgo_camera* c, double* kpc)
+{
+    int W = c->width, H = c->height;
+    int Wt = (W + 15) / 16, Ht = (H + 15) / 16;
+    uint32_t np = 0;
+    for (int t = 0; t < Wt * Ht; t++)
+        if (ranges[2 * t + 1] > np) np = ranges[2 * t + 1];
+    for (uint32_t k = 0; k < np; k++) kpc[k] = 0.0;
+    for (int ty = 0; ty < Ht; ty++)
+        for (int tx = 0; tx < Wt; tx++) {
+            int t = ty * Wt + tx;
+            for (int py = ty * 16; py < ty * 16 + 16 && py < H; py++)
+                for (int px = tx * 16; px < tx * 16 + 16 && px < W; px++) {
+                    float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+                    float T = 1.0f;
+                    for (uint32_t k = ranges[2 * t]; k < ranges[2 * t + 1]; k++) {
+                        const fgo_splat* g = &s[vals[k]];
+                        float dx = g->u - fpx;
+                        float dy = g->v - fpy;
+                        float power = -0.5f * ((g->A * dx) * dx + (g->C * dy) * dy) - (g->B * dx) * dy;
+                        if (power > 0.0f) continue;
+                        float alpha = g->opacity * fgo_exp(power);
+                        alpha = alpha < 0.99f ? alpha : 0.99f;
+                        if (alpha < 1.0f / 255.0f) continue;
+                        float Tn = T * (1.0f - alpha);
+                        if (Tn < 1e-4f) break;
+                        kpc[k] += (double)alpha * (double)T;
+                        T = Tn;
+                    }
+                }
+        }
+}

@@ -5,29 +5,62 @@
 // in-frustum node, with no level-by-level walk (Eq. (4)). Here the same
 // per-node decision is split so that HBM traffic is minimal:
 //
-//   k_small   internal nodes only (index < n_internal_span): frustum test,
-//             EWA Sigma_2D, R_2D = 3 sqrt(lambda_max) <= tau_R -> 1 bit/node.
-//             Leaves never need R_2D (the leaf exemption keeps every
-//             in-frustum leaf), so their scale/rotation are never read.
-//   k_select  every node: chase the parent chain through the small bits
-//             (an internal node passes R&L exactly when it is small, so the
-//             Ancestor filter only needs those bits, which stay in L2/MALL),
-//             then RL(n) = small(n) for internal nodes or F(n) for leaves.
-//             Only leaves that survive the chase read their mean. Wave
-//             ballots give the selection bits and per-block counts.
-//   k_scan    exclusive scan of the block counts (one workgroup), n_sel.
-//   k_compact writes the selected ids in ascending order.
+//   k_small    internal nodes (index < n_internal_span): frustum test, EWA
+//              Sigma_2D, small = R_2D = 3 sqrt(lambda_max) <= tau_R. Leaves
+//              never need R_2D (the leaf exemption keeps every in-frustum
+//              leaf), so their scale and rotation are never read.
+//   k_blocked  internal nodes: blocked(a) = small(a) or small(b) for some
+//              ancestor b (a short parent-chain walk over internal nodes whose
+//              small bits and parent links stay in L2). An internal node
+//              passes R&L exactly when it is small, so a node n is removed by
+//              the Ancestor filter exactly when blocked(parent(n)).
+//   k_select   every node, one pass: RL(n) = small(n) for internal nodes and
+//              F(n) for leaves; sel(n) = RL(n) and not blocked(parent(n)).
+//              Leaves of blocked parents never read their mean. Wave ballots
+//              give the selection words; the compacted ids are written in
+//              ascending order with a single-pass decoupled look-back scan
+//              across workgroups (Merrill & Garland 2016), workgroups taking
+//              their tile index from an atomic ticket so every predecessor a
+//              workgroup waits on has already started. A descriptor packs its
+//              state and value in one 64-bit word, so relaxed agent-scope
+//              atomics suffice (no cache-wide release/acquire per access).
 #include "fg_device.h"
 
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kRounds = 8;                   // nodes per thread in k_select
+constexpr int kTileNodes = kBlock * kRounds;  // nodes per k_select workgroup
+constexpr int kWaves = kBlock / fgd::kWave;
 
-__global__ void k_reset(uint32_t* status, uint32_t* n_sel)
+// look-back descriptor: state in bits 63..62 (0 none, 1 aggregate, 2 prefix), value in bits 31..0
+constexpr unsigned long long kAgg = 1ull << 62;
+constexpr unsigned long long kPre = 2ull << 62;
+constexpr uint32_t kSpinLimit = 1u << 26;
+
+__global__ void k_reset(uint32_t* __restrict__ status, uint32_t* __restrict__ n_sel, uint32_t* __restrict__ ticket,
+                        unsigned long long* __restrict__ desc, int64_t n_desc)
 {
-    if (threadIdx.x == 0) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) {
         *status = 0u;
         *n_sel = 0u;
+        *ticket = 0u;
+    }
+    for (int64_t i = i0; i < n_desc; i += (int64_t)gridDim.x * blockDim.x) desc[i] = 0ull;
+}
+
+__device__ __forceinline__ bool bit_of(const uint32_t* __restrict__ w, int64_t i)
+{
+    return (w[i >> 5] >> (i & 31)) & 1u;
+}
+
+__device__ __forceinline__ void store_wave_bits(uint32_t* __restrict__ words, int64_t base, int64_t limit,
+                                                uint64_t bits)
+{
+    if (fgd::lane_id() == 0 && base < limit) {
+        words[base >> 5] = (uint32_t)bits;
+        if (base + 32 < limit) words[(base >> 5) + 1] = (uint32_t)(bits >> 32);
     }
 }
 
@@ -49,138 +82,166 @@ __global__ __launch_bounds__(kBlock) void k_small(const float* __restrict__ mean
             small = 3.0f * sqrtf(fgd::lambda_max(a, b, c)) <= tau_R;
         }
     }
-    const uint64_t bits = __ballot(small);
-    const int64_t base = n - (int64_t)fgd::lane_id();
-    if (fgd::lane_id() == 0 && base < span) {
-        small_bits[base >> 5] = (uint32_t)bits;
-        small_bits[(base >> 5) + 1] = (uint32_t)(bits >> 32);
-    }
+    store_wave_bits(small_bits, n - (int64_t)fgd::lane_id(), span, __ballot(small));
 }
 
-__device__ __forceinline__ bool bit_of(const uint32_t* __restrict__ w, int64_t i)
+__global__ __launch_bounds__(kBlock) void k_blocked(const int32_t* __restrict__ parent, const uint8_t* __restrict__ flags,
+                                                    const uint32_t* __restrict__ small_bits, int64_t span,
+                                                    int max_depth, uint32_t* __restrict__ blocked_bits,
+                                                    uint32_t* __restrict__ status)
 {
-    return (w[i >> 5] >> (i & 31)) & 1u;
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool blocked = false, bad = false;
+    if (n < span && !(flags[n] & 1u)) {
+        blocked = bit_of(small_bits, n);
+        int64_t a = n;
+        int32_t p = parent[n];
+        int hops = 0;
+        while (!blocked && p >= 0) {
+            if ((int64_t)p >= a || (int64_t)p >= span || hops >= max_depth) {
+                bad = true;
+                break;
+            }
+            blocked = bit_of(small_bits, p);
+            a = p;
+            p = parent[p];
+            ++hops;
+        }
+    }
+    store_wave_bits(blocked_bits, n - (int64_t)fgd::lane_id(), span, __ballot(blocked));
+    if (__ballot(bad) && fgd::lane_id() == 0) atomicOr(status, FG_STATUS_BAD_PARENT);
 }
 
 __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mean, const int32_t* __restrict__ parent,
                                                    const uint8_t* __restrict__ flags,
-                                                   const uint32_t* __restrict__ small_bits, int64_t N, int64_t span,
-                                                   int max_depth, fgd::Cam cam, uint32_t* __restrict__ sel_bits,
-                                                   uint32_t* __restrict__ block_count, uint32_t* __restrict__ status)
+                                                   const uint32_t* __restrict__ small_bits,
+                                                   const uint32_t* __restrict__ blocked_bits, int64_t N, int64_t span,
+                                                   fgd::Cam cam, uint32_t* __restrict__ sel_bits,
+                                                   uint32_t* __restrict__ sel_idx, int64_t cap_sel,
+                                                   uint32_t* __restrict__ n_sel, uint32_t* __restrict__ ticket,
+                                                   unsigned long long* __restrict__ desc,
+                                                   uint32_t* __restrict__ status)
 {
-    __shared__ uint32_t wave_count[kBlock / fgd::kWave];
-    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    bool sel = false;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_off[kRounds * kWaves];
+    __shared__ uint32_t s_excl;
+    const int tid = threadIdx.x;
+    const int wave = tid / fgd::kWave;
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t n_tiles = (N + kTileNodes - 1) / kTileNodes;
+    uint64_t ball[kRounds];
     bool bad = false;
-    if (n < N) {
-        bool culled = false;
-        int32_t a = parent[n];
-        int hops = 0;
-        while (a >= 0) {
-            if ((int64_t)a >= n || (int64_t)a >= span || hops >= max_depth) {
-                bad = true;
-                break;
+#pragma unroll
+    for (int r = 0; r < kRounds; r++) {
+        const int64_t n = tile * kTileNodes + r * kBlock + tid;
+        bool sel = false;
+        if (n < N) {
+            const int32_t p = parent[n];
+            bool culled = false;
+            if (p >= 0) {
+                if ((int64_t)p >= n || (int64_t)p >= span) bad = true;
+                else culled = bit_of(blocked_bits, p);
             }
-            if (bit_of(small_bits, a)) {
-                culled = true;
-                break;
-            }
-            a = parent[a];
-            ++hops;
-        }
-        if (!culled && !bad) {
-            const bool leaf = n >= span || (flags[n] & 1u);
-            if (leaf) {
-                float x, y, z;
-                fgd::to_camera(cam, mean[n], mean[N + n], mean[2 * N + n], x, y, z);
-                sel = fgd::in_frustum(cam, x, y, z);
-            } else {
-                sel = bit_of(small_bits, n);
+            if (!culled && !bad) {
+                const bool leaf = n >= span || (flags[n] & 1u);
+                if (leaf) {
+                    float x, y, z;
+                    fgd::to_camera(cam, mean[n], mean[N + n], mean[2 * N + n], x, y, z);
+                    sel = fgd::in_frustum(cam, x, y, z);
+                } else {
+                    sel = bit_of(small_bits, n);
+                }
             }
         }
+        ball[r] = __ballot(sel);
+        store_wave_bits(sel_bits, n - (int64_t)fgd::lane_id(), N, ball[r]);
+        if (fgd::lane_id() == 0) s_off[r * kWaves + wave] = (uint32_t)__popcll(ball[r]);
     }
-    const uint64_t bits = __ballot(sel);
-    const uint64_t badw = __ballot(bad);
-    const int64_t base = n - (int64_t)fgd::lane_id();
-    const int wave = threadIdx.x / fgd::kWave;
-    if (fgd::lane_id() == 0) {
-        if (base < N) {
-            sel_bits[base >> 5] = (uint32_t)bits;
-            if (base + 32 < N) sel_bits[(base >> 5) + 1] = (uint32_t)(bits >> 32);
+    if (__ballot(bad) && fgd::lane_id() == 0) atomicOr(status, FG_STATUS_BAD_PARENT);
+    __syncthreads();
+    if (tid == 0) {
+        // exclusive offsets of the (round, wave) groups inside the tile, in node order
+        uint32_t run = 0;
+        for (int i = 0; i < kRounds * kWaves; i++) {
+            const uint32_t c = s_off[i];
+            s_off[i] = run;
+            run += c;
         }
-        wave_count[wave] = (uint32_t)__popcll(bits);
-        if (badw) atomicOr(status, FG_STATUS_BAD_PARENT);
+        const uint32_t agg = run;
+        uint32_t excl = 0;
+        if (tile == 0) {
+            __hip_atomic_store(&desc[0], kPre | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&desc[tile], kAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int64_t j = tile - 1;
+            uint32_t spins = 0;
+            while (j >= 0) {
+                const unsigned long long d = __hip_atomic_load(&desc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long state = d & (3ull << 62);
+                if (state == 0ull) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > kSpinLimit) {  // never expected: predecessors always publish
+                        atomicOr(status, FG_STATUS_LOOKBACK_STALL);
+                        break;
+                    }
+                    continue;
+                }
+                excl += (uint32_t)d;
+                if (state == kPre) break;
+                --j;
+            }
+            __hip_atomic_store(&desc[tile], kPre | (unsigned long long)(excl + agg), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_excl = excl;
+        if (tile == n_tiles - 1) {
+            const uint32_t total = excl + agg;
+            *n_sel = total;
+            if ((int64_t)total > cap_sel) atomicOr(status, FG_STATUS_SEL_OVERFLOW);
+        }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (int w = 0; w < kBlock / fgd::kWave; w++) s += wave_count[w];
-        block_count[blockIdx.x] = s;
+    const uint32_t base = s_excl;
+    const uint64_t lt = fgd::lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < kRounds; r++) {
+        if ((ball[r] >> fgd::lane_id()) & 1ull) {
+            const uint32_t off = base + s_off[r * kWaves + wave] + (uint32_t)__popcll(ball[r] & lt);
+            if ((int64_t)off < cap_sel) sel_idx[off] = (uint32_t)(tile * kTileNodes + r * kBlock + tid);
+        }
     }
-}
-
-// Exclusive scan of nb block counts by one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ block_count,
-                                               uint32_t* __restrict__ block_off, int64_t nb, int64_t cap_sel,
-                                               uint32_t* __restrict__ n_sel, uint32_t* __restrict__ status)
-{
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (nb + 1023) / 1024;
-    const int64_t lo = t * per;
-    const int64_t hi = lo + per < nb ? lo + per : nb;
-    uint32_t s = 0;
-    for (int64_t i = lo; i < hi; i++) s += block_count[i];
-    part[t] = s;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the 1024 partial sums
-    for (int d = 1; d < 1024; d <<= 1) {
-        uint32_t v = t >= d ? part[t - d] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[t] - s;
-    for (int64_t i = lo; i < hi; i++) {
-        block_off[i] = run;
-        run += block_count[i];
-    }
-    if (t == 1023) {
-        const uint32_t total = part[1023];
-        *n_sel = total;
-        if ((int64_t)total > cap_sel) atomicOr(status, FG_STATUS_SEL_OVERFLOW);
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__ sel_bits,
-                                                    const uint32_t* __restrict__ block_count,
-                                                    const uint32_t* __restrict__ block_off, int64_t N,
-                                                    int64_t cap_sel, uint32_t* __restrict__ sel_idx)
-{
-    __shared__ uint32_t wave_count[kBlock / fgd::kWave];
-    if (block_count[blockIdx.x] == 0) return;  // uniform per block
-    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool sel = n < N && bit_of(sel_bits, n);
-    const uint64_t bits = __ballot(sel);
-    const int wave = threadIdx.x / fgd::kWave;
-    if (fgd::lane_id() == 0) wave_count[wave] = (uint32_t)__popcll(bits);
-    __syncthreads();
-    uint32_t off = block_off[blockIdx.x];
-    for (int w = 0; w < wave; w++) off += wave_count[w];
-    off += (uint32_t)__popcll(bits & fgd::lanemask_lt());
-    if (sel && (int64_t)off < cap_sel) sel_idx[off] = (uint32_t)n;
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct FilterWs {
+    uint32_t *small_bits, *blocked_bits, *ticket;
+    unsigned long long* desc;
+};
+
+size_t carve(void* base, int64_t N, int64_t span, FilterWs* w)
+{
+    const size_t words = (size_t)((span + 63) / 64) * 2 + 2;
+    const size_t n_desc = (size_t)((N + kTileNodes - 1) / kTileNodes) + 1;
+    const size_t sizes[4] = {words * 4, words * 4, 64, n_desc * 8};
+    void** dst[4] = {(void**)&w->small_bits, (void**)&w->blocked_bits, (void**)&w->ticket, (void**)&w->desc};
+    size_t off = 0;
+    for (int i = 0; i < 4; i++) {
+        if (base) *dst[i] = (char*)base + off;
+        off += align_up(sizes[i]);
+    }
+    return off;
+}
 
 }  // namespace
 
 extern "C" size_t fg_filter_workspace_size(int64_t n_nodes, int64_t n_internal_span)
 {
     if (n_nodes < 0 || n_internal_span < 0) return 0;
-    const size_t small_words = (size_t)((n_internal_span + 63) / 64) * 2;
-    const size_t nb = (size_t)((n_nodes + kBlock - 1) / kBlock);
-    return align_up(small_words * 4 + 8) + 2 * align_up(nb * 4 + 4);
+    FilterWs w;
+    return carve(nullptr, n_nodes, n_internal_span, &w);
 }
 
 extern "C" int fg_filter(const fg_tree* tree, const fg_camera* cam, float tau_R, uint32_t* sel_bits,
@@ -195,27 +256,25 @@ extern "C" int fg_filter(const fg_tree* tree, const fg_camera* cam, float tau_R,
     if (N > 0 && (!tree->mean || !tree->parent || (span > 0 && (!tree->scale || !tree->quat || !tree->flags))))
         return FG_ERR_INVALID_ARG;
     if (cam->width <= 0 || cam->height <= 0) return FG_ERR_INVALID_ARG;
-    const size_t need = fg_filter_workspace_size(N, span);
-    if (!ws || ws_bytes < need) return FG_ERR_WORKSPACE;
+    FilterWs w;
+    if (!ws || ws_bytes < carve(nullptr, N, span, &w)) return FG_ERR_WORKSPACE;
+    carve(ws, N, span, &w);
     hipStream_t s = (hipStream_t)stream;
     const fgd::Cam c = fgd::make_cam(*cam);
-    char* w = (char*)ws;
-    uint32_t* small_bits = (uint32_t*)w;
-    w += align_up((size_t)((span + 63) / 64) * 2 * 4 + 8);
-    const int64_t nb = (N + kBlock - 1) / kBlock;
-    uint32_t* block_count = (uint32_t*)w;
-    w += align_up((size_t)nb * 4 + 4);
-    uint32_t* block_off = (uint32_t*)w;
-
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, status, n_sel);
+    const int64_t n_tiles = (N + kTileNodes - 1) / kTileNodes;
+    int64_t rg = (n_tiles + 255) / 256;
+    rg = rg < 1 ? 1 : (rg > 1024 ? 1024 : rg);
+    hipLaunchKernelGGL(k_reset, dim3((unsigned)rg), dim3(256), 0, s, status, n_sel, w.ticket, w.desc, n_tiles);
     if (N == 0) return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
-    if (span > 0)
-        hipLaunchKernelGGL(k_small, dim3((unsigned)((span + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tree->mean,
-                           tree->scale, tree->quat, tree->flags, N, span, c, tau_R, small_bits);
-    hipLaunchKernelGGL(k_select, dim3((unsigned)nb), dim3(kBlock), 0, s, tree->mean, tree->parent, tree->flags,
-                       small_bits, N, span, tree->max_depth, c, sel_bits, block_count, status);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, block_count, block_off, nb, cap_sel, n_sel, status);
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kBlock), 0, s, sel_bits, block_count, block_off, N,
-                       cap_sel, sel_idx);
+    if (span > 0) {
+        const dim3 g((unsigned)((span + kBlock - 1) / kBlock));
+        hipLaunchKernelGGL(k_small, g, dim3(kBlock), 0, s, tree->mean, tree->scale, tree->quat, tree->flags, N, span, c,
+                           tau_R, w.small_bits);
+        hipLaunchKernelGGL(k_blocked, g, dim3(kBlock), 0, s, tree->parent, tree->flags, w.small_bits, span,
+                           tree->max_depth, w.blocked_bits, status);
+    }
+    hipLaunchKernelGGL(k_select, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, tree->mean, tree->parent, tree->flags,
+                       w.small_bits, w.blocked_bits, N, span, c, sel_bits, sel_idx, cap_sel, n_sel, w.ticket, w.desc,
+                       status);
     return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
 }

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(HERE, "libfg.so")
 FG_STATUS_SEL_OVERFLOW = 1
 FG_STATUS_PAIR_OVERFLOW = 2
 FG_STATUS_BAD_PARENT = 4
+FG_STATUS_LOOKBACK_STALL = 8
 
 
 class FgError(RuntimeError):
@@ -55,7 +56,7 @@ class FgTune(C.Structure):
 
 
 EXPORTS = ["fg_filter_workspace_size", "fg_filter", "fg_preprocess", "fg_sort_workspace_size", "fg_sort",
-           "fg_render", "fg_status_string"]
+           "fg_render_workspace_size", "fg_render", "fg_status_string"]
 
 _lib = None
 
@@ -79,7 +80,9 @@ def lib():
         L.fg_sort.restype = i32
         L.fg_sort.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp, vp, C.c_size_t, vp, vp]
         L.fg_render.restype = i32
-        L.fg_render.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.fg_render_workspace_size.restype = C.c_size_t
+        L.fg_render_workspace_size.argtypes = [vp, i64, vp]
+        L.fg_render.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, C.c_size_t, vp, vp]
         L.fg_status_string.restype = C.c_char_p
         L.fg_status_string.argtypes = [i32]
         _lib = L
@@ -201,13 +204,19 @@ def fg_sort(splats: Splats, n_sel, cap_sel: int, cam, tile_keys, vals, cap_pairs
                          _ref(tune) if tune is not None else None, _stream(stream)), "fg_sort")
 
 
-def fg_render(splats: Splats, vals, ranges, cam, bg: Sequence[float], image, final_T, n_contrib,
-              tune: Optional[FgTune] = None, stream=None):
+def fg_render_workspace_size(cam, cap_pairs: int, tune: Optional[FgTune] = None) -> int:
+    cs = camera_struct(cam)
+    return int(lib().fg_render_workspace_size(_ref(cs), cap_pairs, _ref(tune) if tune is not None else None))
+
+
+def fg_render(splats: Splats, vals, ranges, cam, bg: Sequence[float], image, final_T, n_contrib, cap_pairs: int,
+              frag_stats, status, ws, tune: Optional[FgTune] = None, stream=None):
     ss, cs = splats.struct(), camera_struct(cam)
     bgv = (C.c_float * 3)(*[float(b) for b in bg])
     _check(lib().fg_render(_ref(ss), _p(vals), _p(ranges), _ref(cs), C.cast(bgv, C.c_void_p), _p(image),
-                           _p(final_T), _p(n_contrib), _ref(tune) if tune is not None else None, _stream(stream)),
-           "fg_render")
+                           _p(final_T), _p(n_contrib), cap_pairs, _p(frag_stats), _p(status), _p(ws),
+                           ws.numel() * ws.element_size(), _ref(tune) if tune is not None else None,
+                           _stream(stream)), "fg_render")
 
 
 # ---------------------------------------------------------------------------
@@ -238,6 +247,8 @@ class FrameBuffers:
         _C.width, _C.height = width, height
         self.sort_ws = torch.empty(fg_sort_workspace_size(self.cap_sel, self.cap_pairs, _C), dtype=torch.uint8,
                                    device=device)
+        self.render_ws = torch.empty(fg_render_workspace_size(_C, self.cap_pairs, tune_struct(256)),
+                                     dtype=torch.uint8, device=device)
         self.image = torch.empty((3, height, width), dtype=torch.float32, device=device)
         self.final_T = torch.empty((height, width), dtype=torch.float32, device=device)
         self.n_contrib = torch.empty((height, width), dtype=i32, device=device)
@@ -268,8 +279,9 @@ def sort_stage(cam, fb: FrameBuffers, tune=None, stream=None):
             fb.status, fb.sort_ws, tune, stream)
 
 
-def render_stage(cam, fb: FrameBuffers, bg=(0.0, 0.0, 0.0), tune=None, stream=None):
-    fg_render(fb.splats, fb.vals, fb.ranges, cam, bg, fb.image, fb.final_T, fb.n_contrib, tune, stream)
+def render_stage(cam, fb: FrameBuffers, bg=(0.0, 0.0, 0.0), tune=None, stream=None, frag_stats=None):
+    fg_render(fb.splats, fb.vals, fb.ranges, cam, bg, fb.image, fb.final_T, fb.n_contrib, fb.cap_pairs, frag_stats,
+              fb.status, fb.render_ws, tune, stream)
 
 
 def render_frame(tree: DeviceTree, cam, fb: FrameBuffers, tau_R: float = 3.0, tau: float = 0.0,

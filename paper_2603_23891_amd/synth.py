@@ -420,3 +420,44 @@ def flythrough(n_frames: int, seed: int = 1, n_ctrl: int = 8, half_extent: float
             base += cam.n_tiles
         cams.append(cam)
     return cams
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+# Leaves of the city trees lie on thin horizontal patches (blob sigma_z =
+# 2 cm) at ~290 leaves/m^2, leaf log-scale N(-3.5, 0.5): at 1080p with
+# tau_R = 3 px, parents of such leaves pass the radius test beyond ~150 m and
+# coarser levels beyond ~300-800 m, so cuts span several levels. Volumetric
+# blobs (sigma = 18, 18, 10 m) would make every cut all-leaves at tau_R = 3.
+CITY1M = CitySpec(n_leaves=1_000_000, box=(100.0, 100.0, 30.0), n_blobs=64, blob_sigma=(3.0, 3.0, 0.02),
+                  leaf_log_scale_mu=-3.5, seed=0)
+CITY20M = CitySpec(n_leaves=17_500_000, box=(300.0, 300.0, 50.0), n_blobs=256, blob_sigma=(6.0, 6.0, 0.02),
+                   leaf_log_scale_mu=-3.5, seed=0)
+CITY_PITCH_DEG = -20.0
+CITY_ALTITUDE = 40.0
+LAMBDA_G = 0.2   # Sec. 4.1: shrink aggressiveness used in all experiments
+TAU_R = 3.0      # Sec. 3.2: R&L pixel-radius threshold
+
+
+def city1m_camera() -> Camera:
+    """One 1920x1080 view from (0, -120, 30) facing +y, tilted down 30 degrees."""
+    return make_camera(yaw_pitch_rotation(math.pi / 2, math.radians(-30.0)), (0.0, -120.0, 30.0), 1920, 1080)
+
+
+def city20m_frames(n_frames: int = 64) -> List[Camera]:
+    """The 64-frame 1080p fly-through at 40 m altitude (closed spline, seed 1)."""
+    return flythrough(n_frames, seed=1, altitude=CITY_ALTITUDE, pitch_deg=CITY_PITCH_DEG)
+
+
+def city20m_training_views(n: int = 8) -> List[Camera]:
+    """Views for the GTC pre-pass: the same path, half-way between the frames' spline knots."""
+    return flythrough(n, seed=1, altitude=CITY_ALTITUDE, pitch_deg=CITY_PITCH_DEG,
+                      params=(np.arange(n) + 0.5) * (8.0 / n))
+
+
+def city20m_batch_views(n: int = 32) -> List[Camera]:
+    """32 views on the path with +-15 deg yaw jitter and mixed resolutions (global tile ids)."""
+    res = [(1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)]
+    return flythrough(n, seed=1, altitude=CITY_ALTITUDE, pitch_deg=CITY_PITCH_DEG, yaw_jitter_deg=15.0,
+                      params=np.arange(n) * (8.0 / n), resolutions=res)

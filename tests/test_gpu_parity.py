@@ -59,6 +59,32 @@ def test_ragged_image_and_city_block():
         assert_frame_parity(g, o)
 
 
+@pytest.mark.parametrize("opacity_logit_mu", [-3.0, 1.0])
+def test_heavy_tiles_chunked_blend(opacity_logit_mu):
+    """Thousands of small splats on a few tiles: multi-chunk tiles hand the pixel
+    state over between work items; translucent (no termination) and opaque
+    (termination inside a later chunk) variants."""
+    rng = np.random.default_rng(7)
+    n = 12000
+    cam = synth.make_camera(np.eye(3), (0, 0, 0), 200, 120)
+    z = rng.uniform(20, 60, n)
+    px = rng.uniform(60, 110, n)
+    py = rng.uniform(40, 80, n)
+    mean = np.stack([(px - cam.cx) * z / cam.fx, (py - cam.cy) * z / cam.fy, z], 1)
+    scale = np.exp(rng.normal(-3.2, 0.4, (n, 3))) * z[:, None] / 40
+    q = rng.standard_normal((n, 4)); q /= np.linalg.norm(q, axis=1, keepdims=True)
+    op = 1 / (1 + np.exp(-rng.normal(opacity_logit_mu, 1.0, n)))
+    sh = rng.normal(0, 0.3, (n, 1, 3))
+    from tests.helpers import flat_tree
+    tree = flat_tree(mean, scale, q, op, sh)
+    o = oracle.render_frame(tree, cam, 3.0, 0.0)
+    L = (o["ranges"][:, 1].astype(np.int64) - o["ranges"][:, 0])
+    assert L.max() > 2048
+    for chunk in (256, 512, 1024):
+        g = run_gpu_frame(tree, cam, 3.0, 0.0, tune=fg.tune_struct(chunk, 0))
+        assert_frame_parity(g, o)
+
+
 def test_empty_view_and_single_node():
     cam = synth.tiny_camera(25)
     away = synth.make_camera(np.diag([1.0, -1.0, -1.0]), (0, 0, -25), 64, 48)  # looking away from the tree
@@ -75,7 +101,7 @@ def test_tune_knobs_do_not_change_results(tiny_dev):
     cam = synth.tiny_camera(25)
     ref = run_gpu_frame(TINY, cam, 3.0, 1 / 255, dtree=tiny_dev)
     for rb in (4, 5, 6, 7, 8):
-        for B in (32, 64, 128, 256):
+        for B in (256, 512, 1024):
             g = run_gpu_frame(TINY, cam, 3.0, 1 / 255, dtree=tiny_dev, tune=fg.tune_struct(B, rb))
             for k in ("tile_keys", "vals", "ranges", "image", "final_T", "n_contrib"):
                 assert np.array_equal(g[k], ref[k]), (rb, B, k)
