@@ -17,6 +17,9 @@
  *                  plus per-tile ranges;
  *   fg_render      per-tile front-to-back alpha blending, Eq. (2).
  *
+ * and, for training, fg_activate and fg_render_backward (gradients of a loss
+ * on the image w.r.t. the raw Gaussian parameters).
+ *
  * Conventions shared by every entry point:
  *
  *  - Pointers named in a struct or argument as "device" are device memory on
@@ -209,17 +212,72 @@ size_t fg_render_workspace_size(const fg_camera* cam, int64_t cap_pairs, const f
  * splat blended, 0 if none. bg is a host array of 3 floats. cap_pairs is
  * the capacity the sort ran with (it bounds the range lengths and sizes the
  * workspace). Long ranges are cut into chunks whose skip tests run in
- * parallel; the transmittance chain still runs in list order, so results are
- * those of one sequential pass.
+ * parallel (a first launch writes per-pixel pass masks); the transmittance
+ * chain still runs in list order, so results are those of one sequential
+ * pass.
  * frag_stats: NULL, or 4 device counters that the call adds to (the caller
  * zeroes them): [0] (pixel, splat) tests evaluated, [1] tests that reach the
  * exponential (-5.6 <= power <= 0), [2] tests with alpha >= 1/255, [3] splats
  * blended. Results do not depend on whether counting is on.
- * Errors: FG_ERR_INVALID_ARG, FG_ERR_WORKSPACE; FG_STATUS_LOOKBACK_STALL. */
+ * status is reserved (not written). Errors: FG_ERR_INVALID_ARG,
+ * FG_ERR_WORKSPACE. */
 int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
               const float bg[3], float* image, float* final_T, uint32_t* n_contrib, int64_t cap_pairs,
               unsigned long long* frag_stats, uint32_t* status, void* ws, size_t ws_bytes, const fg_tune* tune,
               void* stream);
+
+/* ---- differentiable form (Sec. 3.1: differentiable splatting) ---------- */
+
+/* Raw, unconstrained parameters of M Gaussians (device planes). The activated
+ * values are scale = exp(log_scale) and opacity = 1 / (1 + exp(-logit)). */
+typedef struct fg_params {
+    int64_t m;
+    int32_t sh_degree;       /* 0..3 */
+    int32_t pad;
+    const float* mean;       /* [3][M] */
+    const float* log_scale;  /* [3][M] */
+    const float* quat;       /* [4][M] (w, x, y, z), any non-zero norm */
+    const float* logit;      /* [M] */
+    const float* sh;         /* [M][(D+1)^2][3] */
+} fg_params;
+
+/* Gradients of a scalar loss w.r.t. the raw parameters, same shapes as
+ * fg_params (device, overwritten; zero for Gaussians not rendered). */
+typedef struct fg_grads {
+    float* mean;
+    float* log_scale;
+    float* quat;
+    float* logit;
+    float* sh;
+} fg_grads;
+
+/* scale [3][M] = exp(log_scale), opacity [M] = 1 / (1 + exp(-logit)), with the
+ * library's exponential (|argument| <= 87). The activated planes, with p->mean,
+ * p->quat and p->sh, form an fg_tree of M root leaves (parent -1, flags 1)
+ * that fg_filter / fg_preprocess / fg_sort / fg_render render.
+ * Errors: FG_ERR_INVALID_ARG. */
+int fg_activate(const fg_params* p, float* scale, float* opacity, void* stream);
+
+/* Scratch bytes fg_render_backward needs (9 floats per splat). */
+size_t fg_render_backward_workspace_size(int64_t cap_sel);
+
+/* Backward pass of a frame rendered from p (after fg_activate) by fg_filter,
+ * fg_preprocess, fg_sort and fg_render: given dL/dimage [3][H][W] (device),
+ * writes dL/d(raw parameters) into out. Inputs are that frame's sel_idx,
+ * n_sel (device), splats, sorted vals, ranges, final_T and n_contrib, the
+ * same camera and background. For every pixel the blended splats are the
+ * forward's (position below n_contrib and the same skip tests), visited back
+ * to front with the transmittance recovered from final_T
+ * (T_k = T_{k+1} / (1 - alpha_k)); alpha capped at 0.99 passes no gradient to
+ * opacity or position; the tile rectangle and shrink radius are piecewise
+ * constant and pass none. Gradients are summed with float32 atomics, so the
+ * summation order (and the last bits) vary between runs.
+ * Errors: FG_ERR_INVALID_ARG, FG_ERR_UNSUPPORTED (sh_degree > 3),
+ * FG_ERR_WORKSPACE. */
+int fg_render_backward(const fg_params* p, const fg_camera* cam, const float bg[3], const uint32_t* sel_idx,
+                       const uint32_t* n_sel, int64_t cap_sel, const fg_splats* splats, const uint32_t* vals,
+                       const uint32_t* ranges, const float* final_T, const uint32_t* n_contrib,
+                       const float* dL_dimage, const fg_grads* out, void* ws, size_t ws_bytes, void* stream);
 
 /* Text for an FG_* return code. */
 const char* fg_status_string(int code);

@@ -70,6 +70,8 @@ def lib():
         L.fgo_render.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.fgo_render_pixels.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp]
         L.fgo_kpc.argtypes = [vp, vp, vp, vp, vp]
+        L.fgo_activate.argtypes = [vp, vp, i64, vp, vp]
+        L.fgo_replay64.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         assert L.fgo_splat_size() == SPLAT_DTYPE.itemsize
         _lib = L
     return _lib
@@ -271,3 +273,79 @@ def scene_tau(tree, cams, lambda_G: float = 0.2, tau_R: float = 3.0) -> dict:
         gv.append(gtc_view(kpc(sp, vals, ranges, cam), ranges))
     G = float(np.mean(gv))
     return dict(G_views=gv, G_bar=G, lambda_G=lambda_G, tau=lambda_G / G)
+
+
+# ---------------------------------------------------------------------------
+# differentiable form
+# ---------------------------------------------------------------------------
+class _Params(C.Structure):
+    _fields_ = [("m", C.c_int64), ("sh_degree", C.c_int32), ("pad", C.c_int32), ("mean", C.c_void_p),
+                ("log_scale", C.c_void_p), ("quat", C.c_void_p), ("logit", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class ParamsRef:
+    """ctypes view of raw Gaussian parameters (mean [3,M], log_scale [3,M], quat [4,M], logit [M], sh [M,K,3])."""
+
+    def __init__(self, mean, log_scale, quat, logit, sh, sh_degree):
+        self.keep = [np.ascontiguousarray(a, np.float32) for a in (mean, log_scale, quat, logit, sh)]
+        m, ls, q, lg, s = self.keep
+        self.m = int(lg.shape[0])
+        self.s = _Params(m=self.m, sh_degree=sh_degree, pad=0, mean=m.ctypes.data, log_scale=ls.ctypes.data,
+                         quat=q.ctypes.data, logit=lg.ctypes.data, sh=s.ctypes.data)
+        self.sh_degree = sh_degree
+
+    @property
+    def ptr(self):
+        return C.cast(C.pointer(self.s), C.c_void_p)
+
+
+def activate(log_scale, logit):
+    """float32 scale = exp(log_scale), opacity = sigmoid(logit) with the project's exponential."""
+    ls = np.ascontiguousarray(log_scale, np.float32)
+    lg = np.ascontiguousarray(logit, np.float32)
+    sc = np.empty_like(ls)
+    op = np.empty_like(lg)
+    lib().fgo_activate(_ptr(ls), _ptr(lg), lg.size, _ptr(sc), _ptr(op))
+    return sc, op
+
+
+def flat_tree_from_params(prm: ParamsRef):
+    """A tree whose nodes are the activated Gaussians, every one a root leaf."""
+    from types import SimpleNamespace
+    mean, log_scale, quat, logit, sh = prm.keep
+    sc, op = activate(log_scale, logit)
+    m = prm.m
+    return SimpleNamespace(mean=mean, scale=sc, quat=quat, opacity=op, sh=sh, parent=np.full(m, -1, np.int32),
+                           flags=np.ones(m, np.uint8), sh_degree=prm.sh_degree, n_internal_span=0, max_depth=0,
+                           n_nodes=m)
+
+
+def forward32(prm: ParamsRef, cam, tau: float = 0.0, bg=(0.0, 0.0, 0.0)) -> dict:
+    """The float32 frame of the activated Gaussians (all are root leaves)."""
+    return render_frame(flat_tree_from_params(prm), cam, 1e30, tau, bg)
+
+
+def replay64(prm: ParamsRef, cam, fwd: dict, dL_dimage=None, bg=(0.0, 0.0, 0.0), want_image=True):
+    """float64 replay of the float32 forward's decisions: image and gradients."""
+    cs, cp = _cam_ptr(cam)
+    H, W = cam.height, cam.width
+    bgv = np.asarray(bg, np.float32)
+    sel = np.ascontiguousarray(fwd["sel_idx"], np.uint32)
+    splats = np.ascontiguousarray(fwd["splats"])
+    vals = np.ascontiguousarray(fwd["vals"], np.uint32)
+    ranges = np.ascontiguousarray(fwd["ranges"], np.uint32)
+    nc = np.ascontiguousarray(fwd["n_contrib"], np.uint32)
+    img = np.zeros((3, H, W), np.float64) if want_image else None
+    m, K = prm.m, (prm.sh_degree + 1) ** 2
+    grads = None
+    dl = None
+    if dL_dimage is not None:
+        dl = np.ascontiguousarray(dL_dimage, np.float64)
+        grads = dict(mean=np.zeros((3, m)), log_scale=np.zeros((3, m)), quat=np.zeros((4, m)), logit=np.zeros(m),
+                     sh=np.zeros((m, K, 3)))
+    z = lambda a: None if a is None else _ptr(a)
+    one = np.zeros(1, np.uint32)
+    lib().fgo_replay64(prm.ptr, cp, _ptr(bgv), _ptr(sel if sel.size else one), sel.size, _ptr(splats),
+                       _ptr(vals if vals.size else one), _ptr(ranges), _ptr(nc), z(dl), z(img),
+                       *(z(grads[k]) if grads else None for k in ("mean", "log_scale", "quat", "logit", "sh")))
+    return img, grads

@@ -590,3 +590,340 @@ void fgo_kpc(const fgo_splat* s, const uint32_t* vals, const uint32_t* ranges, c
                 }
         }
 }
+
+/* ---------------------------------------------------------------------- */
+/* Differentiable form: activation, float64 replay forward and backward   */
+/* ---------------------------------------------------------------------- */
+
+/* Raw (unconstrained) Gaussian parameters of M Gaussians. */
+typedef struct fgo_params {
+    int64_t m;
+    int32_t sh_degree;
+    int32_t pad;
+    const float* mean;      /* [3][m] */
+    const float* log_scale; /* [3][m] */
+    const float* quat;      /* [4][m] (w, x, y, z), any non-zero norm */
+    const float* logit;     /* [m] opacity logits */
+    const float* sh;        /* [m][K][3] */
+} fgo_params;
+
+/* float32 activations: scale = exp(log_scale), opacity = 1 / (1 + exp(-logit)),
+ * with the same exponential as the blend (valid for |x| <= 87). */
+void fgo_activate(const float* log_scale, const float* logit, int64_t m, float* scale, float* opacity)
+{
+    for (int64_t i = 0; i < 3 * m; i++) scale[i] = fgo_exp(log_scale[i]);
+    for (int64_t i = 0; i < m; i++) opacity[i] = 1.0f / (1.0f + fgo_exp(-logit[i]));
+}
+
+typedef struct {
+    double u, v, A, B, C, o, rgb[3], z;
+    double pc[3], S2[3], Q[4];  /* camera-space centre, Sigma_2D (a, b, c) */
+    double rgb_raw[3];          /* colour before the clamp at 0 */
+    double dir[3], dlen;        /* unit view direction, distance */
+    double s[3], qh[4], qn, R[9], M[9], Sig[6], J[4], T[6], Y[16];
+} proj64;
+
+static void sh_basis64(int degree, double x, double y, double z, double* Y)
+{
+    const double c0 = 0.28209479177387814, c1 = 0.48860251190291992, c2a = 1.0925484305920792,
+                 c2b = 0.31539156525252005, c2c = 0.54627421529603959, c3a = 0.59004358992664352,
+                 c3b = 2.8906114426405538, c3c = 0.45704579946446572, c3d = 0.3731763325901154,
+                 c3e = 1.4453057213202769;
+    Y[0] = c0;
+    if (degree < 1) return;
+    Y[1] = c1 * y; Y[2] = c1 * z; Y[3] = c1 * x;
+    if (degree < 2) return;
+    Y[4] = c2a * x * y; Y[5] = c2a * y * z; Y[6] = c2b * (3 * z * z - 1); Y[7] = c2a * x * z;
+    Y[8] = c2c * (x * x - y * y);
+    if (degree < 3) return;
+    Y[9] = c3a * y * (3 * x * x - y * y); Y[10] = c3b * x * y * z; Y[11] = c3c * y * (5 * z * z - 1);
+    Y[12] = c3d * z * (5 * z * z - 3); Y[13] = c3c * x * (5 * z * z - 1); Y[14] = c3e * z * (x * x - y * y);
+    Y[15] = c3a * x * (x * x - 3 * y * y);
+}
+
+/* Partial derivatives dY_k/d(x, y, z) of the same polynomials. */
+static void sh_basis_grad64(int degree, double x, double y, double z, double* dY /* [16][3] */)
+{
+    const double c1 = 0.48860251190291992, c2a = 1.0925484305920792, c2b = 0.31539156525252005,
+                 c2c = 0.54627421529603959, c3a = 0.59004358992664352, c3b = 2.8906114426405538,
+                 c3c = 0.45704579946446572, c3d = 0.3731763325901154, c3e = 1.4453057213202769;
+    for (int i = 0; i < 48; i++) dY[i] = 0.0;
+    if (degree < 1) return;
+    dY[1 * 3 + 1] = c1; dY[2 * 3 + 2] = c1; dY[3 * 3 + 0] = c1;
+    if (degree < 2) return;
+    dY[4 * 3 + 0] = c2a * y; dY[4 * 3 + 1] = c2a * x;
+    dY[5 * 3 + 1] = c2a * z; dY[5 * 3 + 2] = c2a * y;
+    dY[6 * 3 + 2] = 6 * c2b * z;
+    dY[7 * 3 + 0] = c2a * z; dY[7 * 3 + 2] = c2a * x;
+    dY[8 * 3 + 0] = 2 * c2c * x; dY[8 * 3 + 1] = -2 * c2c * y;
+    if (degree < 3) return;
+    dY[9 * 3 + 0] = 6 * c3a * x * y; dY[9 * 3 + 1] = c3a * (3 * x * x - 3 * y * y);
+    dY[10 * 3 + 0] = c3b * y * z; dY[10 * 3 + 1] = c3b * x * z; dY[10 * 3 + 2] = c3b * x * y;
+    dY[11 * 3 + 1] = c3c * (5 * z * z - 1); dY[11 * 3 + 2] = 10 * c3c * y * z;
+    dY[12 * 3 + 2] = c3d * (15 * z * z - 3);
+    dY[13 * 3 + 0] = c3c * (5 * z * z - 1); dY[13 * 3 + 2] = 10 * c3c * x * z;
+    dY[14 * 3 + 0] = 2 * c3e * x * z; dY[14 * 3 + 1] = -2 * c3e * y * z; dY[14 * 3 + 2] = c3e * (x * x - y * y);
+    dY[15 * 3 + 0] = c3a * (3 * x * x - 3 * y * y); dY[15 * 3 + 1] = -6 * c3a * x * y;
+}
+
+/* float64 projection of raw Gaussian g (same formulas as preprocess_one). */
+static void project64(const fgo_params* p, const fgo_camera* c, int64_t g, proj64* o)
+{
+    int64_t m = p->m;
+    double mu[3] = {p->mean[g], p->mean[m + g], p->mean[2 * m + g]};
+    const double* Wd;
+    double W[9];
+    for (int i = 0; i < 9; i++) W[i] = c->R[i];
+    Wd = W;
+    for (int i = 0; i < 3; i++) o->pc[i] = Wd[3 * i] * mu[0] + Wd[3 * i + 1] * mu[1] + Wd[3 * i + 2] * mu[2] + (double)c->t[i];
+    for (int i = 0; i < 3; i++) o->s[i] = exp((double)p->log_scale[i * m + g]);
+    double q[4] = {p->quat[g], p->quat[m + g], p->quat[2 * m + g], p->quat[3 * m + g]};
+    o->qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int i = 0; i < 4; i++) o->qh[i] = q[i] / o->qn;
+    double w = o->qh[0], x = o->qh[1], y = o->qh[2], z = o->qh[3];
+    double* R = o->R;
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) o->M[3 * i + j] = R[3 * i + j] * o->s[j];
+    int k = 0;
+    for (int i = 0; i < 3; i++)
+        for (int j = i; j < 3; j++)
+            o->Sig[k++] = o->M[3 * i] * o->M[3 * j] + o->M[3 * i + 1] * o->M[3 * j + 1] + o->M[3 * i + 2] * o->M[3 * j + 2];
+    double X = o->pc[0], Yc = o->pc[1], Z = o->pc[2];
+    o->J[0] = c->fx / Z; o->J[1] = -c->fx * X / (Z * Z); o->J[2] = c->fy / Z; o->J[3] = -c->fy * Yc / (Z * Z);
+    for (int j = 0; j < 3; j++) {
+        o->T[j] = o->J[0] * W[j] + o->J[1] * W[6 + j];
+        o->T[3 + j] = o->J[2] * W[3 + j] + o->J[3] * W[6 + j];
+    }
+    double Sg[9] = {o->Sig[0], o->Sig[1], o->Sig[2], o->Sig[1], o->Sig[3], o->Sig[4], o->Sig[2], o->Sig[4], o->Sig[5]};
+    double U[6];
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 3; j++)
+            U[3 * i + j] = o->T[3 * i] * Sg[j] + o->T[3 * i + 1] * Sg[3 + j] + o->T[3 * i + 2] * Sg[6 + j];
+    double s00 = U[0] * o->T[0] + U[1] * o->T[1] + U[2] * o->T[2];
+    double s01 = U[0] * o->T[3] + U[1] * o->T[4] + U[2] * o->T[5];
+    double s11 = U[3] * o->T[3] + U[4] * o->T[4] + U[5] * o->T[5];
+    o->S2[0] = s00 + 0.3; o->S2[1] = s01; o->S2[2] = s11 + 0.3;
+    double det = o->S2[0] * o->S2[2] - o->S2[1] * o->S2[1];
+    o->A = o->S2[2] / det; o->B = -o->S2[1] / det; o->C = o->S2[0] / det;
+    o->u = c->fx * X / Z + c->cx;
+    o->v = c->fy * Yc / Z + c->cy;
+    o->z = Z;
+    o->o = 1.0 / (1.0 + exp(-(double)p->logit[g]));
+    double d[3] = {mu[0] - c->campos[0], mu[1] - c->campos[1], mu[2] - c->campos[2]};
+    o->dlen = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int i = 0; i < 3; i++) o->dir[i] = d[i] / o->dlen;
+    sh_basis64(p->sh_degree, o->dir[0], o->dir[1], o->dir[2], o->Y);
+    int K = (p->sh_degree + 1) * (p->sh_degree + 1);
+    const float* sh = p->sh + (size_t)g * K * 3;
+    for (int ch = 0; ch < 3; ch++) {
+        double acc = 0.5;
+        for (int kk = 0; kk < K; kk++) acc += o->Y[kk] * sh[kk * 3 + ch];
+        o->rgb_raw[ch] = acc;
+        o->rgb[ch] = acc < 0 ? 0 : acc;
+    }
+}
+
+/* The float32 decisions of the blend for (pixel, splat): 1 = blended
+ * (position < n_contrib and both skip tests pass), with *clamped = 1 when
+ * alpha hit the 0.99 cap. Same arithmetic as blend_pixel. */
+static int blended32(const fgo_splat* g, int px, int py, uint32_t pos, uint32_t n_contrib, int* clamped)
+{
+    if (pos >= n_contrib) return 0;
+    float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    float dx = g->u - fpx, dy = g->v - fpy;
+    float power = -0.5f * ((g->A * dx) * dx + (g->C * dy) * dy) - (g->B * dx) * dy;
+    if (power > 0.0f) return 0;
+    float a = g->opacity * fgo_exp(power);
+    *clamped = !(a < 0.99f);
+    a = a < 0.99f ? a : 0.99f;
+    return a >= 1.0f / 255.0f;
+}
+
+/* Float64 replay of the blend and its gradient. For every pixel the set of
+ * blended splats, their order and the alpha clamp are those of the float32
+ * forward (splats32, vals, ranges, n_contrib); all values are recomputed in
+ * float64 from the raw parameters, so the result is the image of the smooth
+ * piece the float32 forward is on and, with dL_dimage, its exact gradient.
+ * image64 [3][H][W] (may be NULL); gradients (may be NULL) are accumulated
+ * into float64 arrays shaped like the raw parameters. */
+void fgo_replay64(const fgo_params* p, const fgo_camera* c, const float bg[3], const uint32_t* sel_idx, int64_t n_sel,
+                  const fgo_splat* splats32, const uint32_t* vals, const uint32_t* ranges, const uint32_t* n_contrib,
+                  const double* dL_dimage, double* image64, double* g_mean, double* g_log_scale, double* g_quat,
+                  double* g_logit, double* g_sh)
+{
+    int W = c->width, H = c->height;
+    int Wt = (W + 15) / 16, Ht = (H + 15) / 16;
+    int64_t m = p->m;
+    int K = (p->sh_degree + 1) * (p->sh_degree + 1);
+    proj64* P = (proj64*)malloc(sizeof(proj64) * (size_t)(n_sel > 0 ? n_sel : 1));
+    double* gs = (double*)calloc((size_t)(n_sel > 0 ? n_sel : 1) * 9, sizeof(double)); /* du dv dA dB dC do dr dg db */
+    for (int64_t i = 0; i < n_sel; i++) project64(p, c, (int64_t)sel_idx[i], &P[i]);
+    uint32_t maxlen = 1;
+    for (int t = 0; t < Wt * Ht; t++)
+        if (ranges[2 * t + 1] - ranges[2 * t] > maxlen) maxlen = ranges[2 * t + 1] - ranges[2 * t];
+    uint32_t* list = (uint32_t*)malloc(sizeof(uint32_t) * maxlen);
+    int* clampv = (int*)malloc(sizeof(int) * maxlen);
+    for (int ty = 0; ty < Ht; ty++)
+        for (int tx = 0; tx < Wt; tx++) {
+            int t = ty * Wt + tx;
+            uint32_t r0 = ranges[2 * t], r1 = ranges[2 * t + 1];
+            for (int py = ty * 16; py < ty * 16 + 16 && py < H; py++)
+                for (int px = tx * 16; px < tx * 16 + 16 && px < W; px++) {
+                    size_t o = (size_t)py * W + px;
+                    int nb = 0;
+                    for (uint32_t k = r0; k < r1; k++) {
+                        int cl = 0;
+                        if (blended32(&splats32[vals[k]], px, py, k - r0, n_contrib[o], &cl)) {
+                            list[nb] = vals[k];
+                            clampv[nb] = cl;
+                            nb++;
+                        }
+                    }
+                    double fpx = px + 0.5, fpy = py + 0.5;
+                    double Tv = 1.0, C[3] = {0, 0, 0};
+                    for (int b = 0; b < nb; b++) {
+                        const proj64* q = &P[list[b]];
+                        double dx = q->u - fpx, dy = q->v - fpy;
+                        double power = -0.5 * (q->A * dx * dx + q->C * dy * dy) - q->B * dx * dy;
+                        double a = clampv[b] ? 0.99 : q->o * exp(power);
+                        for (int ch = 0; ch < 3; ch++) C[ch] += q->rgb[ch] * a * Tv;
+                        Tv *= (1.0 - a);
+                    }
+                    if (image64)
+                        for (int ch = 0; ch < 3; ch++) image64[(size_t)ch * W * H + o] = C[ch] + Tv * bg[ch];
+                    if (!dL_dimage) continue;
+                    double G[3] = {dL_dimage[o], dL_dimage[(size_t)W * H + o], dL_dimage[2 * (size_t)W * H + o]};
+                    double S[3] = {Tv * bg[0], Tv * bg[1], Tv * bg[2]};
+                    double Tn = Tv;
+                    for (int b = nb - 1; b >= 0; b--) {
+                        const proj64* q = &P[list[b]];
+                        double* gq = &gs[9 * (size_t)list[b]];
+                        double dx = q->u - fpx, dy = q->v - fpy;
+                        double power = -0.5 * (q->A * dx * dx + q->C * dy * dy) - q->B * dx * dy;
+                        double e = exp(power);
+                        double a = clampv[b] ? 0.99 : q->o * e;
+                        double Tk = Tn / (1.0 - a);
+                        double dLda = 0.0;
+                        for (int ch = 0; ch < 3; ch++) {
+                            gq[6 + ch] += G[ch] * a * Tk;
+                            dLda += G[ch] * (q->rgb[ch] * Tk - S[ch] / (1.0 - a));
+                            S[ch] += q->rgb[ch] * a * Tk;
+                        }
+                        Tn = Tk;
+                        if (clampv[b]) continue;
+                        double dLdp = dLda * a;
+                        gq[5] += dLda * e;
+                        gq[0] += dLdp * (-(q->A * dx + q->B * dy));
+                        gq[1] += dLdp * (-(q->C * dy + q->B * dx));
+                        gq[2] += dLdp * (-0.5 * dx * dx);
+                        gq[3] += dLdp * (-dx * dy);
+                        gq[4] += dLdp * (-0.5 * dy * dy);
+                    }
+                }
+        }
+    free(list);
+    free(clampv);
+    if (!dL_dimage) {
+        free(P);
+        free(gs);
+        return;
+    }
+    /* projection backward: splat gradients -> raw parameters */
+    for (int64_t i = 0; i < n_sel; i++) {
+        const proj64* q = &P[i];
+        const double* gq = &gs[9 * (size_t)i];
+        int64_t g = sel_idx[i];
+        double W9[9];
+        for (int k = 0; k < 9; k++) W9[k] = c->R[k];
+        double dmu[3] = {0, 0, 0}, dpc[3] = {0, 0, 0};
+        /* colour -> SH and view direction */
+        double dd[3] = {0, 0, 0};
+        double dY[48];
+        sh_basis_grad64(p->sh_degree, q->dir[0], q->dir[1], q->dir[2], dY);
+        const float* sh = p->sh + (size_t)g * K * 3;
+        for (int ch = 0; ch < 3; ch++) {
+            double gr = q->rgb_raw[ch] < 0 ? 0.0 : gq[6 + ch];
+            for (int k = 0; k < K; k++) {
+                if (g_sh) g_sh[((size_t)g * K + k) * 3 + ch] += gr * q->Y[k];
+                for (int a = 0; a < 3; a++) dd[a] += gr * sh[k * 3 + ch] * dY[k * 3 + a];
+            }
+        }
+        double ddot = dd[0] * q->dir[0] + dd[1] * q->dir[1] + dd[2] * q->dir[2];
+        for (int a = 0; a < 3; a++) dmu[a] += (dd[a] - q->dir[a] * ddot) / q->dlen;
+        /* opacity */
+        if (g_logit) g_logit[g] += gq[5] * q->o * (1.0 - q->o);
+        /* 2D mean */
+        double X = q->pc[0], Yc = q->pc[1], Z = q->pc[2];
+        dpc[0] += gq[0] * c->fx / Z;
+        dpc[1] += gq[1] * c->fy / Z;
+        dpc[2] += -(gq[0] * c->fx * X + gq[1] * c->fy * Yc) / (Z * Z);
+        /* conic (A, B, C) -> Sigma_2D: dL/dSigma = -Q G Q, G = [[gA, gB/2], [gB/2, gC]] */
+        double Q[4] = {q->A, q->B, q->B, q->C};
+        double Gm[4] = {gq[2], gq[3] / 2, gq[3] / 2, gq[4]};
+        double QG[4] = {Q[0] * Gm[0] + Q[1] * Gm[2], Q[0] * Gm[1] + Q[1] * Gm[3], Q[2] * Gm[0] + Q[3] * Gm[2],
+                        Q[2] * Gm[1] + Q[3] * Gm[3]};
+        double QGQ[4] = {QG[0] * Q[0] + QG[1] * Q[2], QG[0] * Q[1] + QG[1] * Q[3], QG[2] * Q[0] + QG[3] * Q[2],
+                         QG[2] * Q[1] + QG[3] * Q[3]};
+        double Hs[4] = {-QGQ[0], -QGQ[1], -QGQ[2], -QGQ[3]}; /* symmetric dL/dSigma_2D */
+        /* Sigma_2D = T Sigma T^T: dL/dSigma = T^T H T, dL/dT = 2 H T Sigma */
+        const double* T = q->T;
+        double Sg[9] = {q->Sig[0], q->Sig[1], q->Sig[2], q->Sig[1], q->Sig[3], q->Sig[4], q->Sig[2], q->Sig[4], q->Sig[5]};
+        double dSig[9];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                double v = 0;
+                for (int r = 0; r < 2; r++)
+                    for (int s2 = 0; s2 < 2; s2++) v += T[3 * r + a] * Hs[2 * r + s2] * T[3 * s2 + b];
+                dSig[3 * a + b] = v;
+            }
+        double HT[6];
+        for (int r = 0; r < 2; r++)
+            for (int b = 0; b < 3; b++) HT[3 * r + b] = Hs[2 * r] * T[b] + Hs[2 * r + 1] * T[3 + b];
+        double dT[6];
+        for (int r = 0; r < 2; r++)
+            for (int b = 0; b < 3; b++)
+                dT[3 * r + b] = 2 * (HT[3 * r] * Sg[b] + HT[3 * r + 1] * Sg[3 + b] + HT[3 * r + 2] * Sg[6 + b]);
+        /* T = J W: dL/dJ = dT W^T; J00 = fx/z, J02 = -fx x/z^2, J11 = fy/z, J12 = -fy y/z^2 */
+        double dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0;
+        for (int b = 0; b < 3; b++) {
+            dJ00 += dT[b] * W9[b];
+            dJ02 += dT[b] * W9[6 + b];
+            dJ11 += dT[3 + b] * W9[3 + b];
+            dJ12 += dT[3 + b] * W9[6 + b];
+        }
+        dpc[0] += dJ02 * (-c->fx / (Z * Z));
+        dpc[1] += dJ12 * (-c->fy / (Z * Z));
+        dpc[2] += dJ00 * (-c->fx / (Z * Z)) + dJ11 * (-c->fy / (Z * Z)) + dJ02 * (2 * c->fx * X / (Z * Z * Z)) +
+                  dJ12 * (2 * c->fy * Yc / (Z * Z * Z));
+        for (int a = 0; a < 3; a++) dmu[a] += W9[a] * dpc[0] + W9[3 + a] * dpc[1] + W9[6 + a] * dpc[2];
+        /* Sigma = M M^T: dL/dM = 2 dSig M (dSig symmetric) */
+        double dM[9];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++)
+                dM[3 * a + b] = 2 * (dSig[3 * a] * q->M[b] + dSig[3 * a + 1] * q->M[3 + b] + dSig[3 * a + 2] * q->M[6 + b]);
+        double ds[3] = {0, 0, 0}, dR[9];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                ds[b] += dM[3 * a + b] * q->R[3 * a + b];
+                dR[3 * a + b] = dM[3 * a + b] * q->s[b];
+            }
+        double w = q->qh[0], x = q->qh[1], y = q->qh[2], z = q->qh[3];
+        double dqh[4];
+        dqh[0] = 2 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+        dqh[1] = 2 * (y * dR[1] + z * dR[2] + y * dR[3] - 2 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] - 2 * x * dR[8]);
+        dqh[2] = 2 * (-2 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] - 2 * y * dR[8]);
+        dqh[3] = 2 * (-2 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2 * z * dR[4] + y * dR[5] + x * dR[6] + y * dR[7]);
+        double qd = dqh[0] * w + dqh[1] * x + dqh[2] * y + dqh[3] * z;
+        if (g_quat)
+            for (int a = 0; a < 4; a++) g_quat[a * m + g] += (dqh[a] - q->qh[a] * qd) / q->qn;
+        if (g_log_scale)
+            for (int a = 0; a < 3; a++) g_log_scale[a * m + g] += ds[a] * q->s[a];
+        if (g_mean)
+            for (int a = 0; a < 3; a++) g_mean[a * m + g] += dmu[a];
+    }
+    free(P);
+    free(gs);
+}

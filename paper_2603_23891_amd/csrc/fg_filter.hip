@@ -133,26 +133,54 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
     const int64_t n_tiles = (N + kTileNodes - 1) / kTileNodes;
     uint64_t ball[kRounds];
     bool bad = false;
+    // Loads are issued phase by phase for all rounds at once (parent links and
+    // flags, then the parents' blocked bits, then leaf positions), so a
+    // workgroup waits three memory latencies rather than three per round.
+    int32_t par[kRounds];
+    uint32_t fl[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; r++) {
+        const int64_t n = tile * kTileNodes + r * kBlock + tid;
+        par[r] = n < N ? parent[n] : -1;
+        fl[r] = (n < N && n < span) ? (uint32_t)flags[n] : 1u;
+    }
+    uint32_t cull[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; r++) {
+        const int64_t n = tile * kTileNodes + r * kBlock + tid;
+        const int32_t p = par[r];
+        cull[r] = 0u;
+        if (n < N && p >= 0) {
+            if ((int64_t)p >= n || (int64_t)p >= span) {
+                bad = true;
+                cull[r] = 1u;
+            } else {
+                cull[r] = (blocked_bits[p >> 5] >> (p & 31)) & 1u;
+            }
+        }
+    }
+    float mx[kRounds], my[kRounds], mz[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; r++) {
+        const int64_t n = tile * kTileNodes + r * kBlock + tid;
+        mx[r] = my[r] = mz[r] = 0.0f;
+        if (n < N && !cull[r] && (fl[r] & 1u)) {
+            mx[r] = mean[n];
+            my[r] = mean[N + n];
+            mz[r] = mean[2 * N + n];
+        }
+    }
 #pragma unroll
     for (int r = 0; r < kRounds; r++) {
         const int64_t n = tile * kTileNodes + r * kBlock + tid;
         bool sel = false;
-        if (n < N) {
-            const int32_t p = parent[n];
-            bool culled = false;
-            if (p >= 0) {
-                if ((int64_t)p >= n || (int64_t)p >= span) bad = true;
-                else culled = bit_of(blocked_bits, p);
-            }
-            if (!culled && !bad) {
-                const bool leaf = n >= span || (flags[n] & 1u);
-                if (leaf) {
-                    float x, y, z;
-                    fgd::to_camera(cam, mean[n], mean[N + n], mean[2 * N + n], x, y, z);
-                    sel = fgd::in_frustum(cam, x, y, z);
-                } else {
-                    sel = bit_of(small_bits, n);
-                }
+        if (n < N && !cull[r]) {
+            if (fl[r] & 1u) {  // leaf: RL = in frustum
+                float x, y, z;
+                fgd::to_camera(cam, mx[r], my[r], mz[r], x, y, z);
+                sel = fgd::in_frustum(cam, x, y, z);
+            } else {  // internal: RL = small
+                sel = bit_of(small_bits, n);
             }
         }
         ball[r] = __ballot(sel);
@@ -161,45 +189,63 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
     }
     if (__ballot(bad) && fgd::lane_id() == 0) atomicOr(status, FG_STATUS_BAD_PARENT);
     __syncthreads();
-    if (tid == 0) {
-        // exclusive offsets of the (round, wave) groups inside the tile, in node order
-        uint32_t run = 0;
-        for (int i = 0; i < kRounds * kWaves; i++) {
-            const uint32_t c = s_off[i];
-            s_off[i] = run;
-            run += c;
+    if (tid < fgd::kWave) {
+        // wave 0: exclusive offsets of the (round, wave) groups in node order ...
+        uint32_t agg = 0;
+        if (tid == 0) {
+            uint32_t run = 0;
+            for (int i = 0; i < kRounds * kWaves; i++) {
+                const uint32_t c = s_off[i];
+                s_off[i] = run;
+                run += c;
+            }
+            agg = run;
+            __hip_atomic_store(&desc[tile], (tile == 0 ? kPre : kAgg) | agg, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        const uint32_t agg = run;
+        agg = __shfl(agg, 0, fgd::kWave);
+        // ... then the look-back, 64 predecessors per step: lane i reads the
+        // descriptor of tile j - i; the nearest "prefix" lane ends the walk
+        // once no lane before it is still unpublished.
         uint32_t excl = 0;
-        if (tile == 0) {
-            __hip_atomic_store(&desc[0], kPre | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&desc[tile], kAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tile > 0) {
             int64_t j = tile - 1;
             uint32_t spins = 0;
-            while (j >= 0) {
-                const unsigned long long d = __hip_atomic_load(&desc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int lane = fgd::lane_id();
+            for (;;) {
+                const int64_t idx = j - lane;
+                const unsigned long long d =
+                    idx >= 0 ? __hip_atomic_load(&desc[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kPre;
                 const unsigned long long state = d & (3ull << 62);
-                if (state == 0ull) {
+                const uint64_t pend = __ballot(state == 0ull);
+                const uint64_t pre = __ballot(state == kPre);
+                const uint64_t upto = pre ? (pre & (~pre + 1ull)) * 2ull - 1ull : ~0ull;  // lanes 0..first prefix
+                if (pend & upto) {
                     __builtin_amdgcn_s_sleep(1);
                     if (++spins > kSpinLimit) {  // never expected: predecessors always publish
-                        atomicOr(status, FG_STATUS_LOOKBACK_STALL);
+                        if (lane == 0) atomicOr(status, FG_STATUS_LOOKBACK_STALL);
                         break;
                     }
                     continue;
                 }
-                excl += (uint32_t)d;
-                if (state == kPre) break;
-                --j;
+                uint32_t v = ((upto >> lane) & 1ull) ? (uint32_t)d : 0u;
+#pragma unroll
+                for (int o = fgd::kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, fgd::kWave);
+                excl += v;
+                if (pre) break;
+                j -= fgd::kWave;
             }
-            __hip_atomic_store(&desc[tile], kPre | (unsigned long long)(excl + agg), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (tid == 0)
+                __hip_atomic_store(&desc[tile], kPre | (unsigned long long)(excl + agg), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_excl = excl;
-        if (tile == n_tiles - 1) {
-            const uint32_t total = excl + agg;
-            *n_sel = total;
-            if ((int64_t)total > cap_sel) atomicOr(status, FG_STATUS_SEL_OVERFLOW);
+        if (tid == 0) {
+            s_excl = excl;
+            if (tile == n_tiles - 1) {
+                const uint32_t total = excl + agg;
+                *n_sel = total;
+                if ((int64_t)total > cap_sel) atomicOr(status, FG_STATUS_SEL_OVERFLOW);
+            }
         }
     }
     __syncthreads();

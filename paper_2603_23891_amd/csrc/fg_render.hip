@@ -4,34 +4,30 @@
 // (power > 0, alpha < 1/255) depend only on the splat and the pixel, not on
 // the transmittance; only the product T_i = prod (1 - alpha_j), the early
 // stop (T < 1e-4) and the colour sum run sequentially. Tiles near a horizon
-// can hold ~10^4 splats whose pixels seldom saturate, so one workgroup per
-// tile would leave the frame waiting on a single long chain. Instead each
-// tile's sorted range is cut into chunks of CHUNK splats, one work item per
-// chunk:
+// can hold ~10^4 splats whose pixels seldom saturate, so one workgroup that
+// tests every (pixel, splat) of such a tile would leave the frame waiting on
+// it. The blend therefore runs in two launches:
 //
-//   phase 1  (all chunks in parallel) the chunk's splat records are staged in
-//            LDS and every pixel (one thread each, 256 per 16x16 tile) marks
-//            in a bit mask the splats whose alpha passes the skip tests;
-//   phase 2  (in chunk order) the item takes over the per-pixel state
-//            (T, C, last, done) left by the previous chunk of its tile and
-//            walks only the marked splats, recomputing alpha with the same
-//            function, so every value and decision is bit-identical to one
-//            sequential pass. It then hands the state to the next chunk
-//            (plain stores, one agent-scope release fence, then a per-tile
-//            counter; the receiver polls the counter with relaxed loads and
-//            takes one acquire fence) or, for the tile's last chunk, writes
-//            the pixels.
+//   k_masks   every chunk of CHUNK splats of a "heavy" tile (more than CHUNK
+//             splats) is one work item: its splat records are staged in LDS
+//             and each splat marks, in per-pixel bit masks, the pixels where
+//             its alpha passes the skip tests (splat-parallel, see pass_masks);
+//             the masks go to global memory. All chunks run in parallel.
+//   k_render  one workgroup per tile (heavy tiles first, tiles claimed from an
+//             atomic ticket): one pixel per lane walks the tile's splats in
+//             list order, chunk by chunk, visiting only the marked ones and
+//             recomputing alpha with the same function, so every value and
+//             decision is bit-identical to one sequential pass. Light tiles
+//             compute their single chunk's masks in place.
 //
-// Work items are claimed from an atomic ticket in (tile, chunk) order, so an
-// item only ever waits for an item claimed before it by a running workgroup.
-// Items of a tile with a single chunk never wait.
+// The launch boundary orders the mask writes before their reads; no
+// workgroup ever waits for another.
 #include "fg_device.h"
 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / fgd::kWave;
-constexpr uint32_t kSpinLimit = 1u << 26;
+constexpr int kScanThreads = 256;
 
 // exp(power) <= exp(-5.6) < 1/255 for power < -5.6, so with opacity <= 1 the
 // splat is skipped either way: testing this first avoids evaluating the
@@ -39,248 +35,313 @@ constexpr uint32_t kSpinLimit = 1u << 26;
 constexpr float kSkipPower = -5.6f;
 
 struct RenderWs {
-    uint32_t* nch;        // [n_tiles] chunks per tile, then its first item (exclusive scan)
-    uint32_t* slot;       // [n_tiles] state slot of a multi-chunk tile
-    uint32_t* done_cnt;   // [n_tiles] chunks of the tile already handed over
-    uint32_t* item_tile;  // [max_items]
-    uint32_t* counters;   // [0] ticket, [1] n_items
-    float* state;         // [max_slots][6][256] T, C0, C1, C2, last, done
+    uint32_t* nch;        // [n_tiles] chunks per tile
+    uint32_t* mfirst;     // [n_tiles] first mask item of a heavy tile
+    uint32_t* order;      // [n_tiles] tiles in processing order, heavy first
+    uint32_t* mitem;      // [max_mask_items] mask item -> tile
+    uint32_t* counters;   // [0] ticket, [1] heavy tiles, [2] mask items (clamped)
+    uint32_t* masks;      // [max_mask_items][CHUNK/32][256]
 };
 
-__device__ __forceinline__ float splat_alpha(float2 m, float4 co, float fpx, float fpy, float& power)
-{
-    const float dx = m.x - fpx;
-    const float dy = m.y - fpy;
-    power = -0.5f * ((co.x * dx) * dx + (co.z * dy) * dy) - (co.y * dx) * dy;
-    float alpha = co.w * fgd::exp_neg(power);
-    return alpha < 0.99f ? alpha : 0.99f;
-}
+struct Frag {
+    unsigned n_eval, n_exp, n_pass, n_blend;
+};
 
 template <int CHUNK>
 __global__ __launch_bounds__(kThreads) void k_chunk_count(const uint32_t* __restrict__ ranges, int64_t n_tiles,
-                                                          uint32_t* __restrict__ nch, uint32_t* __restrict__ done_cnt)
+                                                          uint32_t* __restrict__ nch)
 {
     const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (t < n_tiles) {
         const uint32_t L = ranges[2 * t + 1] - ranges[2 * t];
         nch[t] = L == 0 ? 1u : (L + CHUNK - 1) / CHUNK;
-        done_cnt[t] = 0u;
     }
 }
 
-// One workgroup of 1024 threads: exclusive scan of the chunk counts (first
-// item of each tile), state slots of multi-chunk tiles, the item -> tile map,
-// n_items, and the ticket reset. 8 consecutive tiles per thread per round.
-__global__ __launch_bounds__(1024) void k_chunk_scan(uint32_t* __restrict__ nch, uint32_t* __restrict__ slot,
-                                                     uint32_t* __restrict__ item_tile, int64_t n_tiles,
-                                                     int64_t max_items, uint32_t* __restrict__ counters)
+// One workgroup: orders the tiles (heavy ones first, each group in tile
+// order), numbers the mask items of heavy tiles and resets the ticket.
+// 8 consecutive tiles per thread per round; two running counts (heavy tiles,
+// mask items) are scanned together in one 64-bit word; a light tile's place
+// is its index minus the heavy tiles before it.
+__global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __restrict__ nch, int64_t n_tiles,
+                                                           int64_t max_mask_items, uint32_t* __restrict__ mfirst,
+                                                           uint32_t* __restrict__ order, uint32_t* __restrict__ mitem,
+                                                           uint32_t* __restrict__ counters)
 {
-    __shared__ unsigned long long s_wave[1024 / fgd::kWave];
+    __shared__ unsigned long long s_wave[kScanThreads / fgd::kWave];
     __shared__ unsigned long long s_carry;
+    __shared__ uint32_t s_heavy_total;
     const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
-    if (tid == 0) s_carry = 0ull;
-    __syncthreads();
-    for (int64_t base = 0; base < n_tiles; base += 8 * 1024) {
-        uint32_t c[8];
-        unsigned long long sum = 0;  // low 32: items, high 32: multi-chunk tiles
-#pragma unroll
-        for (int k = 0; k < 8; k++) {
-            const int64_t t = base + (int64_t)tid * 8 + k;
-            c[k] = t < n_tiles ? nch[t] : 0u;
-            sum += (unsigned long long)c[k] | ((unsigned long long)(c[k] > 1) << 32);
-        }
-        unsigned long long x = sum;
-#pragma unroll
-        for (int d = 1; d < fgd::kWave; d <<= 1) {
-            const unsigned long long y = __shfl_up(x, d, fgd::kWave);
-            if (lane >= d) x += y;
-        }
-        if (lane == fgd::kWave - 1) s_wave[wave] = x;
+    // pass 0 counts the heavy tiles (light tiles are placed after them), pass 1 places
+    for (int pass = 0; pass < 2; pass++) {
+        if (tid == 0) s_carry = 0ull;
         __syncthreads();
-        unsigned long long before = s_carry, total = 0;
-        for (int w = 0; w < 1024 / fgd::kWave; w++) {
-            if (w < wave) before += s_wave[w];
-            total += s_wave[w];
-        }
-        unsigned long long run = before + x - sum;
+        const uint32_t heavy_total = pass ? s_heavy_total : 0u;
+        for (int64_t base = 0; base < n_tiles; base += 8 * kScanThreads) {
+            uint32_t c[8];
+            unsigned long long sum = 0;  // low 32: heavy tiles, high 32: mask items
 #pragma unroll
-        for (int k = 0; k < 8; k++) {
-            const int64_t t = base + (int64_t)tid * 8 + k;
-            if (t < n_tiles) {
-                const uint32_t first = (uint32_t)run;
-                nch[t] = first;
-                slot[t] = (uint32_t)(run >> 32);
-                for (uint32_t i = 0; i < c[k]; i++)
-                    if ((int64_t)(first + i) < max_items) item_tile[first + i] = (uint32_t)t;
+            for (int k = 0; k < 8; k++) {
+                const int64_t t = base + (int64_t)tid * 8 + k;
+                c[k] = t < n_tiles ? nch[t] : 1u;
+                if (c[k] > 1) sum += 1ull | ((unsigned long long)c[k] << 32);
             }
-            run += (unsigned long long)c[k] | ((unsigned long long)(c[k] > 1) << 32);
+            unsigned long long x = sum;
+#pragma unroll
+            for (int d = 1; d < fgd::kWave; d <<= 1) {
+                const unsigned long long y = __shfl_up(x, d, fgd::kWave);
+                if (lane >= d) x += y;
+            }
+            if (lane == fgd::kWave - 1) s_wave[wave] = x;
+            __syncthreads();
+            unsigned long long before = s_carry, total = 0;
+            for (int w = 0; w < kScanThreads / fgd::kWave; w++) {
+                if (w < wave) before += s_wave[w];
+                total += s_wave[w];
+            }
+            if (pass) {
+                unsigned long long run = before + x - sum;
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    const int64_t t = base + (int64_t)tid * 8 + k;
+                    if (t < n_tiles) {
+                        const uint32_t hv = (uint32_t)run;          // heavy tiles before t
+                        const uint32_t mf = (uint32_t)(run >> 32);  // mask items before t
+                        if (c[k] > 1) {
+                            order[hv] = (uint32_t)t;
+                            mfirst[t] = mf;
+                            for (uint32_t i = 0; i < c[k]; i++)
+                                if ((int64_t)(mf + i) < max_mask_items) mitem[mf + i] = (uint32_t)t;
+                            run += 1ull | ((unsigned long long)c[k] << 32);
+                        } else {
+                            order[heavy_total + (uint32_t)(t - hv)] = (uint32_t)t;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid == 0) s_carry += total;
+            __syncthreads();
+        }
+        if (tid == 0) {
+            if (!pass) {
+                s_heavy_total = (uint32_t)s_carry;
+            } else {
+                const uint32_t items = (uint32_t)(s_carry >> 32);
+                counters[0] = 0u;
+                counters[1] = (uint32_t)s_carry;
+                counters[2] = (int64_t)items < max_mask_items ? items : (uint32_t)max_mask_items;
+            }
         }
         __syncthreads();
-        if (tid == 0) s_carry += total;
+    }
+}
+
+// Stage splats [start, start + cnt) of the sorted list into LDS.
+__device__ __forceinline__ void stage(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
+                                      const float4* __restrict__ rgb_depth, const uint32_t* __restrict__ vals,
+                                      uint32_t start, int cnt, float2* s_xy, float4* s_co, float4* s_rgb)
+{
+    for (int j = threadIdx.x; j < cnt; j += kThreads) {
+        const uint32_t g = vals[start + j];
+        s_xy[j] = xy[g];
+        s_co[j] = conic_o[g];
+        if (s_rgb) s_rgb[j] = rgb_depth[g];
+    }
+}
+
+// Splat-parallel skip tests: each lane takes one staged splat and tests only
+// the pixels of the tile inside a conservative box around its power >= -5.6
+// ellipse (d^T Q d <= 11.2, half-widths sqrt(11.2 Sigma_xx) and
+// sqrt(11.2 Sigma_yy) widened by 1% + 1 px); every pixel outside the box has
+// power < -5.6 and would be skipped by the same test. Inside the box the
+// tests are the per-pixel ones of Eq. (2), bit for bit. s_mask [word][pixel]
+// must be zero on entry.
+template <bool STATS>
+__device__ __forceinline__ void pass_masks(const float2* s_xy, const float4* s_co, int cnt, int tx, int ty, int W,
+                                           int H, uint32_t* s_mask, Frag& f)
+{
+    const float tx0 = (float)(tx * fgd::kTile), ty0 = (float)(ty * fgd::kTile);
+    const float tx1 = fminf(tx0 + 15.0f, (float)(W - 1)), ty1 = fminf(ty0 + 15.0f, (float)(H - 1));
+    for (int j = threadIdx.x; j < cnt; j += kThreads) {
+        const float2 mm = s_xy[j];
+        const float4 co = s_co[j];
+        float bx0 = tx0, bx1 = tx1, by0 = ty0, by1 = ty1;
+        const float qdet = co.x * co.z - co.y * co.y;
+        if (qdet > 0.0f) {
+            const float ex = sqrtf(11.2f * co.z / qdet) * 1.01f + 1.0f;
+            const float ey = sqrtf(11.2f * co.x / qdet) * 1.01f + 1.0f;
+            bx0 = fmaxf(bx0, floorf(mm.x - ex - 0.5f));
+            bx1 = fminf(bx1, ceilf(mm.x + ex - 0.5f));
+            by0 = fmaxf(by0, floorf(mm.y - ey - 0.5f));
+            by1 = fminf(by1, ceilf(mm.y + ey - 0.5f));
+        }
+        if (!(bx0 <= bx1 && by0 <= by1)) continue;
+        const int ix0 = (int)bx0, ix1 = (int)bx1, iy0 = (int)by0, iy1 = (int)by1;
+        const uint32_t bit = 1u << (j & 31);
+        uint32_t* mrow = s_mask + (j >> 5) * kThreads;
+        for (int py = iy0; py <= iy1; py++) {
+            const float fy = (float)py + 0.5f;
+            for (int px = ix0; px <= ix1; px++) {
+                const float fx = (float)px + 0.5f;
+                const float dx = mm.x - fx;
+                const float dy = mm.y - fy;
+                const float power = -0.5f * ((co.x * dx) * dx + (co.z * dy) * dy) - (co.y * dx) * dy;
+                if (STATS) ++f.n_eval;
+                if (power > 0.0f || power < kSkipPower) continue;
+                if (STATS) ++f.n_exp;
+                float alpha = co.w * fgd::exp_neg(power);
+                alpha = alpha < 0.99f ? alpha : 0.99f;
+                if (alpha < 1.0f / 255.0f) continue;
+                if (STATS) ++f.n_pass;
+                atomicOr(&mrow[(py - ty * fgd::kTile) * fgd::kTile + (px - tx * fgd::kTile)], bit);
+            }
+        }
+    }
+}
+
+template <bool STATS, int N>
+__device__ __forceinline__ void flush_stats(const Frag& f, unsigned long long* frag_stats)
+{
+    if (!STATS) return;
+    const unsigned long long c[4] = {f.n_eval, f.n_exp, f.n_pass, f.n_blend};
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        unsigned long long v = c[k];
+#pragma unroll
+        for (int d = fgd::kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, fgd::kWave);
+        if (fgd::lane_id() == 0) atomicAdd(&frag_stats[k], v);
+    }
+}
+
+template <int CHUNK, bool STATS>
+__global__ __launch_bounds__(kThreads) void k_masks(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
+                                                    const uint32_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ ranges, int W, int H, int Wt,
+                                                    RenderWs ws, unsigned long long* __restrict__ frag_stats)
+{
+    constexpr int kWords = CHUNK / 32;
+    __shared__ float2 s_xy[CHUNK];
+    __shared__ float4 s_co[CHUNK];
+    __shared__ uint32_t s_mask[kWords * kThreads];
+    Frag f = {0, 0, 0, 0};
+    const uint32_t n_items = ws.counters[2];
+    for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const uint32_t tile = ws.mitem[item];
+        const uint32_t chunk = item - ws.mfirst[tile];
+        const uint32_t r0 = ranges[2 * tile], r1 = ranges[2 * tile + 1];
+        const uint32_t start = r0 + chunk * CHUNK;
+        const int cnt = (int)(r1 - start < (uint32_t)CHUNK ? r1 - start : (uint32_t)CHUNK);
+        for (int i = threadIdx.x; i < kWords * kThreads; i += kThreads) s_mask[i] = 0u;
+        stage(xy, conic_o, nullptr, vals, start, cnt, s_xy, s_co, nullptr);
+        __syncthreads();
+        pass_masks<STATS>(s_xy, s_co, cnt, (int)(tile % (uint32_t)Wt), (int)(tile / (uint32_t)Wt), W, H, s_mask, f);
+        __syncthreads();
+        uint32_t* out = ws.masks + (size_t)item * (kWords * kThreads);
+        for (int i = threadIdx.x; i < kWords * kThreads; i += kThreads) out[i] = s_mask[i];
         __syncthreads();
     }
-    if (tid == 0) {
-        const uint32_t items = (uint32_t)s_carry;
-        counters[0] = 0u;
-        counters[1] = (int64_t)items < max_items ? items : (uint32_t)max_items;
-    }
+    flush_stats<STATS, 3>(f, frag_stats);
 }
 
 template <int CHUNK, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
                                                      const float4* __restrict__ rgb_depth,
                                                      const uint32_t* __restrict__ vals,
-                                                     const uint32_t* __restrict__ ranges, int W, int H, int Wt,
-                                                     float bg0, float bg1, float bg2, RenderWs ws, int64_t max_slots,
+                                                     const uint32_t* __restrict__ ranges, int64_t n_tiles, int W,
+                                                     int H, int Wt, float bg0, float bg1, float bg2, RenderWs ws,
                                                      float* __restrict__ image, float* __restrict__ final_T,
                                                      uint32_t* __restrict__ n_contrib,
-                                                     unsigned long long* __restrict__ frag_stats,
-                                                     uint32_t* __restrict__ status)
+                                                     unsigned long long* __restrict__ frag_stats)
 {
     constexpr int kWords = CHUNK / 32;
     __shared__ float2 s_xy[CHUNK];
     __shared__ float4 s_co[CHUNK];
     __shared__ float4 s_rgb[CHUNK];
+    __shared__ uint32_t s_mask[kWords * kThreads];
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
-    const uint32_t n_items = ws.counters[1];
-    uint32_t n_eval = 0, n_exp = 0, n_pass = 0, n_blend = 0;
+    const uint32_t n_mask_items = ws.counters[2];
+    Frag f = {0, 0, 0, 0};
     for (;;) {
         if (tid == 0) s_item = atomicAdd(&ws.counters[0], 1u);
         __syncthreads();
         const uint32_t item = s_item;
-        if (item >= n_items) break;
-        const uint32_t tile = ws.item_tile[item];
-        const uint32_t first = ws.nch[tile];
-        const uint32_t chunk = item - first;
+        if ((int64_t)item >= n_tiles) break;
+        const uint32_t tile = ws.order[item];
         const uint32_t r0 = ranges[2 * tile], r1 = ranges[2 * tile + 1];
-        const bool last_chunk = (uint64_t)r0 + (uint64_t)(chunk + 1) * CHUNK >= (uint64_t)r1;
-        const uint32_t start = r0 + chunk * CHUNK;
-        const int cnt = r1 > start ? (int)(r1 - start < (uint32_t)CHUNK ? r1 - start : (uint32_t)CHUNK) : 0;
+        const uint32_t nch = ws.nch[tile];
+        const uint32_t mf = nch > 1 ? ws.mfirst[tile] : 0u;
         const int tx = (int)(tile % (uint32_t)Wt), ty = (int)(tile / (uint32_t)Wt);
         const int px = tx * fgd::kTile + (tid % fgd::kTile);
         const int py = ty * fgd::kTile + (tid / fgd::kTile);
         const bool inside = px < W && py < H;
         const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
-
-        // ---- phase 1: stage the chunk and mark the splats whose alpha passes
-        for (int j = tid; j < cnt; j += kThreads) {
-            const uint32_t g = vals[start + j];
-            s_xy[j] = xy[g];
-            s_co[j] = conic_o[g];
-            s_rgb[j] = rgb_depth[g];
-        }
-        __syncthreads();
-        uint32_t mask[kWords];
+        float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+        uint32_t last = 0;
+        bool done = !inside;
+        for (uint32_t chunk = 0; chunk < nch; chunk++) {
+            // a workgroup stops once every pixel of the tile has terminated
+            if (__syncthreads_count(done) == kThreads) break;
+            const uint32_t start = r0 + chunk * CHUNK;
+            const int cnt = r1 > start ? (int)(r1 - start < (uint32_t)CHUNK ? r1 - start : (uint32_t)CHUNK) : 0;
+            const bool stored = nch > 1 && mf + chunk < n_mask_items;
+            if (!stored)
+                for (int i = tid; i < kWords * kThreads; i += kThreads) s_mask[i] = 0u;
+            stage(xy, conic_o, rgb_depth, vals, start, cnt, s_xy, s_co, s_rgb);
+            uint32_t mreg[kWords];
+            if (stored) {
+                const uint32_t* src = ws.masks + (size_t)(mf + chunk) * (kWords * kThreads);
 #pragma unroll
-        for (int w = 0; w < kWords; w++) {
-            uint32_t m = 0;
-            if (inside) {
-                const int jn = cnt - w * 32 < 32 ? cnt - w * 32 : 32;
-                for (int b = 0; b < jn; b++) {
-                    const int j = w * 32 + b;
+                for (int w = 0; w < kWords; w++) mreg[w] = src[w * kThreads + tid];
+            }
+            __syncthreads();
+            if (!stored) {
+                pass_masks<STATS>(s_xy, s_co, cnt, tx, ty, W, H, s_mask, f);
+                __syncthreads();
+#pragma unroll
+                for (int w = 0; w < kWords; w++) mreg[w] = s_mask[w * kThreads + tid];
+            }
+#pragma unroll
+            for (int w = 0; w < kWords; w++) {
+                uint32_t m = mreg[w];
+                while (m != 0u && !done) {
+                    const int j = w * 32 + __builtin_ctz(m);
+                    m &= m - 1u;
                     const float2 mm = s_xy[j];
                     const float4 co = s_co[j];
                     const float dx = mm.x - fpx;
                     const float dy = mm.y - fpy;
                     const float power = -0.5f * ((co.x * dx) * dx + (co.z * dy) * dy) - (co.y * dx) * dy;
-                    if (STATS) ++n_eval;
-                    if (power > 0.0f || power < kSkipPower) continue;
-                    if (STATS) ++n_exp;
                     float alpha = co.w * fgd::exp_neg(power);
                     alpha = alpha < 0.99f ? alpha : 0.99f;
-                    if (alpha < 1.0f / 255.0f) continue;
-                    if (STATS) ++n_pass;
-                    m |= 1u << b;
-                }
-            }
-            mask[w] = m;
-        }
-
-        // ---- phase 2: take over the pixel state and walk the marked splats
-        float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-        uint32_t last = 0;
-        bool done = !inside;
-        const uint32_t sl = ws.slot[tile];
-        float* st = ws.state + (size_t)(sl < max_slots ? sl : 0) * (6 * kThreads);
-        if (chunk > 0) {
-            if (tid == 0) {
-                uint32_t spins = 0;
-                while (__hip_atomic_load(&ws.done_cnt[tile], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != chunk) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (++spins > kSpinLimit) {  // never expected: the previous chunk always hands over
-                        atomicOr(status, FG_STATUS_LOOKBACK_STALL);
+                    const float Tn = T * (1.0f - alpha);
+                    if (Tn < 1e-4f) {
+                        done = true;
                         break;
                     }
+                    const float4 c = s_rgb[j];
+                    C0 = C0 + (c.x * alpha) * T;
+                    C1 = C1 + (c.y * alpha) * T;
+                    C2 = C2 + (c.z * alpha) * T;
+                    T = Tn;
+                    last = chunk * CHUNK + (uint32_t)j + 1u;
+                    if (STATS) ++f.n_blend;
                 }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-            __syncthreads();
-            T = st[0 * kThreads + tid];
-            C0 = st[1 * kThreads + tid];
-            C1 = st[2 * kThreads + tid];
-            C2 = st[3 * kThreads + tid];
-            last = __float_as_uint(st[4 * kThreads + tid]);
-            done = st[5 * kThreads + tid] != 0.0f;
-        }
-#pragma unroll
-        for (int w = 0; w < kWords; w++) {
-            uint32_t m = mask[w];
-            while (m != 0u && !done) {
-                const int b = __builtin_ctz(m);
-                m &= m - 1u;
-                const int j = w * 32 + b;
-                float power;
-                const float alpha = splat_alpha(s_xy[j], s_co[j], fpx, fpy, power);
-                const float Tn = T * (1.0f - alpha);
-                if (Tn < 1e-4f) {
-                    done = true;
-                    break;
-                }
-                const float4 c = s_rgb[j];
-                C0 = C0 + (c.x * alpha) * T;
-                C1 = C1 + (c.y * alpha) * T;
-                C2 = C2 + (c.z * alpha) * T;
-                T = Tn;
-                last = chunk * CHUNK + (uint32_t)j + 1u;
-                if (STATS) ++n_blend;
             }
         }
-        if (last_chunk) {
-            if (inside) {
-                const size_t o = (size_t)py * W + px;
-                const size_t plane = (size_t)W * H;
-                image[o] = C0 + T * bg0;
-                image[plane + o] = C1 + T * bg1;
-                image[2 * plane + o] = C2 + T * bg2;
-                final_T[o] = T;
-                n_contrib[o] = last;
-            }
-        } else {
-            st[0 * kThreads + tid] = T;
-            st[1 * kThreads + tid] = C0;
-            st[2 * kThreads + tid] = C1;
-            st[3 * kThreads + tid] = C2;
-            st[4 * kThreads + tid] = __uint_as_float(last);
-            st[5 * kThreads + tid] = done ? 1.0f : 0.0f;
-            __syncthreads();
-            if (tid == 0) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __hip_atomic_store(&ws.done_cnt[tile], chunk + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+        if (inside) {
+            const size_t o = (size_t)py * W + px;
+            const size_t plane = (size_t)W * H;
+            image[o] = C0 + T * bg0;
+            image[plane + o] = C1 + T * bg1;
+            image[2 * plane + o] = C2 + T * bg2;
+            final_T[o] = T;
+            n_contrib[o] = last;
         }
-        __syncthreads();  // LDS and s_item are reused by the next item
+        __syncthreads();  // LDS and s_item are reused by the next tile
     }
-    if (STATS) {
-        unsigned long long c[4] = {n_eval, n_exp, n_pass, n_blend};
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            unsigned long long v = c[k];
-#pragma unroll
-            for (int d = fgd::kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, fgd::kWave);
-            if (fgd::lane_id() == 0) atomicAdd(&frag_stats[k], v);
-        }
-    }
+    flush_stats<STATS, 4>(f, frag_stats);
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -291,16 +352,20 @@ int chunk_of(const fg_tune* tune)
     return tune->render_batch;
 }
 
-size_t carve(void* base, int64_t n_tiles, int64_t cap_pairs, int chunk, RenderWs* w, int64_t* max_items,
-             int64_t* max_slots)
+// Mask storage is capped; chunks beyond the cap compute their masks in the
+// tile's own workgroup (same results, less parallelism).
+constexpr int64_t kMaskStoreBytes = (int64_t)256 << 20;
+
+size_t carve(void* base, int64_t n_tiles, int64_t cap_pairs, int chunk, RenderWs* w, int64_t* max_mask_items)
 {
-    *max_items = n_tiles + (cap_pairs + chunk - 1) / chunk;
-    const int64_t by_pairs = cap_pairs / chunk + 1;
-    *max_slots = n_tiles < by_pairs ? n_tiles : by_pairs;
-    const size_t sizes[6] = {(size_t)n_tiles * 4, (size_t)n_tiles * 4, (size_t)n_tiles * 4, (size_t)*max_items * 4,
-                             64, (size_t)*max_slots * 6 * kThreads * 4};
-    void** dst[6] = {(void**)&w->nch, (void**)&w->slot, (void**)&w->done_cnt, (void**)&w->item_tile,
-                     (void**)&w->counters, (void**)&w->state};
+    const int64_t mask_bytes = (int64_t)(chunk / 32) * kThreads * 4;
+    const int64_t need = 2 * ((cap_pairs + chunk - 1) / chunk) + 1;
+    const int64_t cap = kMaskStoreBytes / mask_bytes;
+    *max_mask_items = need < cap ? need : cap;
+    const size_t sizes[6] = {(size_t)n_tiles * 4, (size_t)n_tiles * 4, (size_t)n_tiles * 4,
+                             (size_t)*max_mask_items * 4, 64, (size_t)*max_mask_items * (size_t)mask_bytes};
+    void** dst[6] = {(void**)&w->nch, (void**)&w->mfirst, (void**)&w->order, (void**)&w->mitem,
+                     (void**)&w->counters, (void**)&w->masks};
     size_t off = 0;
     for (int i = 0; i < 6; i++) {
         if (base) *dst[i] = (char*)base + off;
@@ -312,26 +377,29 @@ size_t carve(void* base, int64_t n_tiles, int64_t cap_pairs, int chunk, RenderWs
 template <int CHUNK>
 void launch(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
             const float bg[3], float* image, float* final_T, uint32_t* n_contrib, unsigned long long* frag_stats,
-            uint32_t* status, const RenderWs& w, int64_t n_tiles, int64_t max_items, int64_t max_slots,
-            hipStream_t s)
+            const RenderWs& w, int64_t n_tiles, int64_t max_mask_items, hipStream_t s)
 {
     const int Wt = (cam->width + 15) / 16;
     hipLaunchKernelGGL(k_chunk_count<CHUNK>, dim3((unsigned)((n_tiles + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                       s, ranges, n_tiles, w.nch, w.done_cnt);
-    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(1024), 0, s, w.nch, w.slot, w.item_tile, n_tiles, max_items,
-                       w.counters);
-    int64_t grid = max_items < 4096 ? max_items : 4096;
+                       s, ranges, n_tiles, w.nch);
+    hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kScanThreads), 0, s, w.nch, n_tiles, max_mask_items, w.mfirst,
+                       w.order, w.mitem, w.counters);
     const float2* xy = (const float2*)splats->xy;
     const float4* co = (const float4*)splats->conic_o;
     const float4* rgb = (const float4*)splats->rgb_depth;
-    if (frag_stats)
-        hipLaunchKernelGGL((k_render<CHUNK, true>), dim3((unsigned)grid), dim3(kThreads), 0, s, xy, co, rgb, vals,
-                           ranges, cam->width, cam->height, Wt, bg[0], bg[1], bg[2], w, max_slots, image, final_T,
-                           n_contrib, frag_stats, status);
-    else
-        hipLaunchKernelGGL((k_render<CHUNK, false>), dim3((unsigned)grid), dim3(kThreads), 0, s, xy, co, rgb, vals,
-                           ranges, cam->width, cam->height, Wt, bg[0], bg[1], bg[2], w, max_slots, image, final_T,
-                           n_contrib, frag_stats, status);
+    const unsigned gm = (unsigned)(max_mask_items < 4096 ? (max_mask_items < 1 ? 1 : max_mask_items) : 4096);
+    const unsigned gr = (unsigned)(n_tiles < 4096 ? n_tiles : 4096);
+    if (frag_stats) {
+        hipLaunchKernelGGL((k_masks<CHUNK, true>), dim3(gm), dim3(kThreads), 0, s, xy, co, vals, ranges, cam->width,
+                           cam->height, Wt, w, frag_stats);
+        hipLaunchKernelGGL((k_render<CHUNK, true>), dim3(gr), dim3(kThreads), 0, s, xy, co, rgb, vals, ranges, n_tiles,
+                           cam->width, cam->height, Wt, bg[0], bg[1], bg[2], w, image, final_T, n_contrib, frag_stats);
+    } else {
+        hipLaunchKernelGGL((k_masks<CHUNK, false>), dim3(gm), dim3(kThreads), 0, s, xy, co, vals, ranges, cam->width,
+                           cam->height, Wt, w, frag_stats);
+        hipLaunchKernelGGL((k_render<CHUNK, false>), dim3(gr), dim3(kThreads), 0, s, xy, co, rgb, vals, ranges, n_tiles,
+                           cam->width, cam->height, Wt, bg[0], bg[1], bg[2], w, image, final_T, n_contrib, frag_stats);
+    }
 }
 
 }  // namespace
@@ -341,8 +409,8 @@ extern "C" size_t fg_render_workspace_size(const fg_camera* cam, int64_t cap_pai
     if (!cam || cam->width <= 0 || cam->height <= 0 || cap_pairs < 0) return 0;
     const int64_t n_tiles = (int64_t)((cam->width + 15) / 16) * ((cam->height + 15) / 16);
     RenderWs w;
-    int64_t mi, ms;
-    return carve(nullptr, n_tiles, cap_pairs, chunk_of(tune), &w, &mi, &ms);
+    int64_t mi;
+    return carve(nullptr, n_tiles, cap_pairs, chunk_of(tune), &w, &mi);
 }
 
 extern "C" int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
@@ -350,7 +418,8 @@ extern "C" int fg_render(const fg_splats* splats, const uint32_t* vals, const ui
                          unsigned long long* frag_stats, uint32_t* status, void* ws, size_t ws_bytes,
                          const fg_tune* tune, void* stream)
 {
-    if (!splats || !ranges || !cam || !bg || !image || !final_T || !n_contrib || !status || cap_pairs < 0)
+    (void)status;
+    if (!splats || !ranges || !cam || !bg || !image || !final_T || !n_contrib || cap_pairs < 0)
         return FG_ERR_INVALID_ARG;
     if (cam->width <= 0 || cam->height <= 0) return FG_ERR_INVALID_ARG;
     const int chunk = chunk_of(tune);
@@ -358,15 +427,14 @@ extern "C" int fg_render(const fg_splats* splats, const uint32_t* vals, const ui
     const int64_t n_tiles = (int64_t)((cam->width + 15) / 16) * ((cam->height + 15) / 16);
     if (n_tiles >= ((int64_t)1 << 31)) return FG_ERR_UNSUPPORTED;
     RenderWs w;
-    int64_t max_items, max_slots;
-    if (!ws || ws_bytes < carve(nullptr, n_tiles, cap_pairs, chunk, &w, &max_items, &max_slots))
-        return FG_ERR_WORKSPACE;
-    carve(ws, n_tiles, cap_pairs, chunk, &w, &max_items, &max_slots);
+    int64_t max_mask_items;
+    if (!ws || ws_bytes < carve(nullptr, n_tiles, cap_pairs, chunk, &w, &max_mask_items)) return FG_ERR_WORKSPACE;
+    carve(ws, n_tiles, cap_pairs, chunk, &w, &max_mask_items);
     hipStream_t s = (hipStream_t)stream;
     switch (chunk) {
-        case 256: launch<256>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, status, w, n_tiles, max_items, max_slots, s); break;
-        case 1024: launch<1024>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, status, w, n_tiles, max_items, max_slots, s); break;
-        default: launch<512>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, status, w, n_tiles, max_items, max_slots, s); break;
+        case 256: launch<256>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles, max_mask_items, s); break;
+        case 1024: launch<1024>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles, max_mask_items, s); break;
+        default: launch<512>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles, max_mask_items, s); break;
     }
     return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
 }

@@ -50,13 +50,24 @@ class FgSplats(C.Structure):
                 ("tiles", C.c_void_p)]
 
 
+class FgParams(C.Structure):
+    _fields_ = [("m", C.c_int64), ("sh_degree", C.c_int32), ("pad", C.c_int32), ("mean", C.c_void_p),
+                ("log_scale", C.c_void_p), ("quat", C.c_void_p), ("logit", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class FgGrads(C.Structure):
+    _fields_ = [("mean", C.c_void_p), ("log_scale", C.c_void_p), ("quat", C.c_void_p), ("logit", C.c_void_p),
+                ("sh", C.c_void_p)]
+
+
 class FgTune(C.Structure):
     _fields_ = [("render_batch", C.c_int32), ("radix_bits", C.c_int32), ("reserved0", C.c_int32),
                 ("reserved1", C.c_int32)]
 
 
 EXPORTS = ["fg_filter_workspace_size", "fg_filter", "fg_preprocess", "fg_sort_workspace_size", "fg_sort",
-           "fg_render_workspace_size", "fg_render", "fg_status_string"]
+           "fg_render_workspace_size", "fg_render", "fg_activate", "fg_render_backward_workspace_size",
+           "fg_render_backward", "fg_status_string"]
 
 _lib = None
 
@@ -83,6 +94,12 @@ def lib():
         L.fg_render_workspace_size.restype = C.c_size_t
         L.fg_render_workspace_size.argtypes = [vp, i64, vp]
         L.fg_render.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, C.c_size_t, vp, vp]
+        L.fg_activate.restype = i32
+        L.fg_activate.argtypes = [vp, vp, vp, vp]
+        L.fg_render_backward_workspace_size.restype = C.c_size_t
+        L.fg_render_backward_workspace_size.argtypes = [i64]
+        L.fg_render_backward.restype = i32
+        L.fg_render_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
         L.fg_status_string.restype = C.c_char_p
         L.fg_status_string.argtypes = [i32]
         _lib = L
@@ -247,8 +264,8 @@ class FrameBuffers:
         _C.width, _C.height = width, height
         self.sort_ws = torch.empty(fg_sort_workspace_size(self.cap_sel, self.cap_pairs, _C), dtype=torch.uint8,
                                    device=device)
-        self.render_ws = torch.empty(fg_render_workspace_size(_C, self.cap_pairs, tune_struct(256)),
-                                     dtype=torch.uint8, device=device)
+        rw = max(fg_render_workspace_size(_C, self.cap_pairs, tune_struct(c)) for c in (256, 512, 1024))
+        self.render_ws = torch.empty(rw, dtype=torch.uint8, device=device)
         self.image = torch.empty((3, height, width), dtype=torch.float32, device=device)
         self.final_T = torch.empty((height, width), dtype=torch.float32, device=device)
         self.n_contrib = torch.empty((height, width), dtype=i32, device=device)
@@ -297,3 +314,29 @@ def read_counts(fb: FrameBuffers):
     """(n_sel, n_pairs, status) copied to the host (synchronises)."""
     c = fb.counts.cpu().numpy().view(np.uint32)
     return int(c[0]), int(c[1]), int(c[2])
+
+
+# ---------------------------------------------------------------------------
+# differentiable form
+# ---------------------------------------------------------------------------
+def params_struct(mean, log_scale, quat, logit, sh, sh_degree: int) -> FgParams:
+    return FgParams(m=int(logit.shape[0]), sh_degree=sh_degree, pad=0, mean=mean.data_ptr(),
+                    log_scale=log_scale.data_ptr(), quat=quat.data_ptr(), logit=logit.data_ptr(), sh=sh.data_ptr())
+
+
+def fg_activate(prm: FgParams, scale, opacity, stream=None):
+    _check(lib().fg_activate(_ref(prm), _p(scale), _p(opacity), _stream(stream)), "fg_activate")
+
+
+def fg_render_backward_workspace_size(cap_sel: int) -> int:
+    return int(lib().fg_render_backward_workspace_size(cap_sel))
+
+
+def fg_render_backward(prm: FgParams, cam, bg, sel_idx, n_sel, cap_sel: int, splats: Splats, vals, ranges, final_T,
+                       n_contrib, dL_dimage, grads: FgGrads, ws, stream=None):
+    cs, ss = camera_struct(cam), splats.struct()
+    bgv = (C.c_float * 3)(*[float(b) for b in bg])
+    _check(lib().fg_render_backward(_ref(prm), _ref(cs), C.cast(bgv, C.c_void_p), _p(sel_idx), _p(n_sel), cap_sel,
+                                    _ref(ss), _p(vals), _p(ranges), _p(final_T), _p(n_contrib), _p(dL_dimage),
+                                    _ref(grads), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "fg_render_backward")

@@ -1,0 +1,112 @@
+"""GPU parity of the differentiable form (fg_activate + frame + fg_render_backward).
+
+* forward: the image of the raw Gaussians equals the oracle's float32 frame
+  bit for bit (activation included);
+* gradients: against the float64 oracle gradient (the exact derivative of the
+  float32 forward's smooth piece, itself pinned by finite differences):
+  per parameter group ||g_gpu - g64|| / ||g64|| <= 1e-3, and elementwise
+  |g_gpu - g64| <= 1e-3 (|g64| + 1e-4 max|g64|) for elements with
+  |g64| > 1e-3 max|g64|; float32 atomics sum in a varying order, so the bar is
+  a tolerance, not bit equality;
+* central differences (h = 1e-3) of the float64 replayed loss at 64 sampled
+  parameters;
+* torch.autograd through FilterGSRender equals a direct backward call.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_23891_amd import diff, synth
+from tests.test_oracle_backward import make_params, perturbed
+
+pytestmark = pytest.mark.gpu
+GROUPS = ("mean", "log_scale", "quat", "logit", "sh")
+
+
+def to_dev(prm):
+    return [torch.from_numpy(a.copy()).cuda() for a in prm.keep]
+
+
+def gpu_fwd_bwd(prm, cam, w, tau=0.0, bg=(0.0, 0.0, 0.0)):
+    args = to_dev(prm)
+    r = diff.GaussianRenderer(prm.m, prm.sh_degree, cam.width, cam.height, cap_pairs=1 << 20)
+    img = r.forward(*args, cam, tau, bg).clone()
+    g = r.backward(*args, cam, torch.from_numpy(w.astype(np.float32)).cuda(), bg)
+    torch.cuda.synchronize()
+    return img.cpu().numpy(), {k: v.cpu().numpy().astype(np.float64) for k, v in zip(GROUPS, g)}, r
+
+
+def check_grads(g_gpu, g64, tol=1e-3):
+    report = {}
+    for k in GROUPS:
+        a, b = g_gpu[k], g64[k]
+        nb = np.linalg.norm(b)
+        rel = np.linalg.norm(a - b) / max(nb, 1e-30)
+        big = np.abs(b) > 1e-3 * np.abs(b).max()
+        el = (np.abs(a - b)[big] / (np.abs(b)[big] + 1e-4 * np.abs(b).max())).max() if big.any() else 0.0
+        report[k] = (rel, el)
+        assert rel <= tol, (k, rel)
+        assert el <= tol, (k, el)
+    return report
+
+
+@pytest.mark.parametrize("seed,m,size,tau", [(1, 300, (128, 96), 0.0), (5, 3000, (128, 128), 0.05),
+                                             (9, 1500, (200, 120), 1 / 255)])
+def test_backward_matches_float64_oracle(seed, m, size, tau):
+    prm, cam, rng = make_params(seed, m=m, width=size[0], height=size[1])
+    bg = (0.1, 0.2, 0.3)
+    fwd = oracle.forward32(prm, cam, tau, bg)
+    w = rng.normal(0, 1, (3, cam.height, cam.width))
+    img, g_gpu, _ = gpu_fwd_bwd(prm, cam, w, tau, bg)
+    assert np.array_equal(img, fwd["image"])
+    _, g64 = oracle.replay64(prm, cam, fwd, dL_dimage=w, bg=bg, want_image=False)
+    check_grads(g_gpu, g64)
+
+
+def test_backward_against_central_differences():
+    prm, cam, rng = make_params(11, m=400)
+    fwd = oracle.forward32(prm, cam)
+    w = rng.normal(0, 1, (3, cam.height, cam.width))
+    _, g_gpu, _ = gpu_fwd_bwd(prm, cam, w)
+    sel = fwd["sel_idx"]
+    rows = {"mean": 3, "log_scale": 3, "quat": 4}
+    scale = {k: np.abs(g_gpu[k]).max() for k in GROUPS}
+    h = 1e-3
+    n = 0
+    for group in GROUPS:
+        for _ in range(13 if group != "logit" else 12):
+            node = int(sel[rng.integers(0, sel.size)])
+            if group in rows:
+                idx = (int(rng.integers(0, rows[group])), node)
+            elif group == "logit":
+                idx = (node,)
+            else:
+                idx = (node, int(rng.integers(0, g_gpu["sh"].shape[1])), int(rng.integers(0, 3)))
+            pp, vp = perturbed(prm, group, idx, h)
+            pm, vm = perturbed(prm, group, idx, -h)
+            lp = float((oracle.replay64(pp, cam, fwd)[0] * w).sum())
+            lm = float((oracle.replay64(pm, cam, fwd)[0] * w).sum())
+            fd = (lp - lm) / (vp - vm)
+            a = g_gpu[group][idx]
+            assert abs(a - fd) <= 1e-3 * max(abs(fd), 1e-2 * scale[group]), (group, idx, a, fd)
+            n += 1
+    assert n == 64
+
+
+def test_autograd_function_and_l1_loss():
+    prm, cam, rng = make_params(3, m=500)
+    target = torch.from_numpy(rng.uniform(0, 1, (3, cam.height, cam.width)).astype(np.float32)).cuda()
+    args = [a.requires_grad_(True) for a in to_dev(prm)]
+    r = diff.GaussianRenderer(prm.m, prm.sh_degree, cam.width, cam.height, cap_pairs=1 << 20)
+    img = r.render(*args, cam)
+    loss = (img - target).abs().mean()
+    loss.backward()
+    dl = (torch.sign(img.detach() - target) / img.numel()).contiguous()
+    direct = r.backward(*[a.detach() for a in args], cam, dl)
+    for a, d in zip(args, direct):
+        assert torch.allclose(a.grad, d, rtol=1e-5, atol=1e-9 * float(d.abs().max()) + 1e-30)
+    # and the float64 oracle of the same L1 loss
+    fwd = oracle.forward32(prm, cam)
+    _, g64 = oracle.replay64(prm, cam, fwd, dL_dimage=dl.cpu().numpy().astype(np.float64), want_image=False)
+    check_grads({k: a.grad.cpu().numpy().astype(np.float64) for k, a in zip(GROUPS, args)}, g64)
