@@ -58,12 +58,69 @@ def filter_bytes(tree, small_words, n_sel):
     return (4 * N + 41 * span + span // 8 + 12 * leaves_tested + N // 8 + 4 * n_sel), leaves_tested
 
 
+def measure_fwd_bwd(torch):
+    """Differentiable forward + backward of 2M raw Gaussians (SH degree 3) at
+    1920x1080 against a seeded uniform target with an L1 loss: ms per view for
+    one view repeated and for a batch of 8 views (yaw -14..14 deg)."""
+    from paper_2603_23891_amd import diff, synth
+    t0 = time.time()
+    g = synth.flat_gaussians(2_000_000, seed=0)
+    log(f"fwd+bwd workload: 2M Gaussians generated in {time.time() - t0:.1f} s")
+    dev = [torch.from_numpy(a).cuda() for a in (g.mean, g.log_scale, g.quat, g.logit, g.sh)]
+    views = synth.city1m_yaw_views()
+    rng = np.random.default_rng(2)
+    target = torch.from_numpy(rng.uniform(0, 1, (3, 1080, 1920)).astype(np.float32)).cuda()
+    r = diff.GaussianRenderer(2_000_000, g.sh_degree, 1920, 1080, cap_pairs=24_000_000)
+    stream = torch.cuda.current_stream()
+
+    def step(cam):
+        img = r.forward(*dev, cam)
+        dl = torch.sign(img - target) / img.numel()
+        return r.backward(*dev, cam, dl)
+
+    for cam in views[:3]:
+        step(cam)
+    torch.cuda.synchronize()
+    from paper_2603_23891_amd import fg
+    n_sel = fg.read_counts(r.fb)[0]
+
+    def timed(cams):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(cams) + 1)]
+        ev[0].record(stream)
+        for i, cam in enumerate(cams):
+            step(cam)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        return [ev[i].elapsed_time(ev[i + 1]) for i in range(len(cams))]
+
+    one = timed([views[3]] * 10)
+    batch = timed(views)
+    # split of one view: forward vs backward
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(stream)
+    img = r.forward(*dev, views[3])
+    dl = torch.sign(img - target) / img.numel()
+    e[1].record(stream)
+    r.backward(*dev, views[3], dl)
+    e[2].record(stream)
+    torch.cuda.synchronize()
+    out = dict(one_view_ms=float(np.median(one)), batch8_ms_per_view=float(np.mean(batch)),
+               forward_ms=e[0].elapsed_time(e[1]), backward_ms=e[1].elapsed_time(e[2]), n_gaussians=2_000_000,
+               n_rendered_central_view=n_sel,
+               workload="2M raw Gaussians (city1m leaf law in view), SH3, 1920x1080, L1 loss vs seeded U[0,1] target")
+    log(f"fwd+bwd: {out['one_view_ms']:.3f} ms/view (1 view), {out['batch8_ms_per_view']:.3f} ms/view (batch of 8)")
+    del r, dev
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'Sharding').")
@@ -167,6 +224,8 @@ def main():
         roofline = dict(bound="hbm", kernel=dominant, achieved=d["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=d["frac"], traffic=None)
 
+    fwd_bwd = None if args.no_backward else measure_fwd_bwd(torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -195,7 +254,7 @@ def main():
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "fwd_bwd_ms_per_view": None,
+        "fwd_bwd_ms_per_view": fwd_bwd,
     }
     print(json.dumps(out), flush=True)
 

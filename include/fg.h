@@ -138,25 +138,29 @@ typedef struct fg_tune {
 
 /* ---- stage 1: traversal-free parallel filter (Sec. 3.2) ---------------- */
 
-/* Scratch bytes fg_filter needs for a tree of n_nodes nodes. */
-size_t fg_filter_workspace_size(int64_t n_nodes, int64_t n_internal_span);
+/* Scratch bytes fg_filter needs for a tree of n_nodes nodes and n_views views. */
+size_t fg_filter_workspace_size(int64_t n_nodes, int64_t n_internal_span, int32_t n_views);
 
-/* For every node n, independently:
+/* For every view v of cams[0 .. n_views) (a host array) and every node n,
+ * independently:
  *   F(n)     in-frustum test of the node centre (fg_camera);
  *   small(n) F(n) and R_2D = 3 sqrt(lambda_max(Sigma_2D)) <= tau_R, with
  *            Sigma_2D the EWA projection plus 0.3 px^2 on the diagonal
  *            (R&L filter, Sec. 3.2; tau_R = 3 in the paper);
  *   RL(n)    F(n) and (leaf(n) or small(n)) (leaf exemption);
  *   sel(n)   RL(n) and no ancestor a of n has RL(a) (Ancestor filter).
- * Outputs: sel_bits [ceil(N/32)] device words, bit n%32 of word n/32 = sel(n);
- * sel_idx [cap_sel] device, the selected node ids in ascending order;
- * *n_sel (device u32) the number selected; *status (device u32) is set to 0,
- * then FG_STATUS_SEL_OVERFLOW / FG_STATUS_BAD_PARENT as they occur.
- * Errors: FG_ERR_INVALID_ARG for null pointers or cap_sel < 0,
+ * Up to 8 views share one pass over the tree (each node's data is read once
+ * for all of them). Outputs per view v (device): sel_bits + v*ceil(N/32)
+ * words, bit n%32 of word n/32 = sel(n); sel_idx + v*cap_sel, the selected
+ * node ids in ascending order; n_sel[v] the number selected. *status
+ * (device u32) is set to 0, then FG_STATUS_SEL_OVERFLOW / FG_STATUS_BAD_PARENT
+ * as they occur.
+ * Errors: FG_ERR_INVALID_ARG for null pointers, n_views < 1 or cap_sel < 0,
  * FG_ERR_INVALID_TREE for n_nodes out of range, n_internal_span outside
  * [0, n_nodes] or max_depth outside 0..15, FG_ERR_WORKSPACE. */
-int fg_filter(const fg_tree* tree, const fg_camera* cam, float tau_R, uint32_t* sel_bits, uint32_t* sel_idx,
-              int64_t cap_sel, uint32_t* n_sel, uint32_t* status, void* ws, size_t ws_bytes, void* stream);
+int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float tau_R, uint32_t* sel_bits,
+              uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status, void* ws, size_t ws_bytes,
+              void* stream);
 
 /* ---- stage 2: projection and shrunk extents (Sec. 3.1, Sec. 3.3) -------- */
 

@@ -81,9 +81,9 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i64, f32, i32 = C.c_void_p, C.c_int64, C.c_float, C.c_int
         L.fg_filter_workspace_size.restype = C.c_size_t
-        L.fg_filter_workspace_size.argtypes = [i64, i64]
+        L.fg_filter_workspace_size.argtypes = [i64, i64, C.c_int32]
         L.fg_filter.restype = i32
-        L.fg_filter.argtypes = [vp, vp, f32, vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
+        L.fg_filter.argtypes = [vp, vp, C.c_int32, f32, vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
         L.fg_preprocess.restype = i32
         L.fg_preprocess.argtypes = [vp, vp, f32, vp, vp, i64, vp, vp, vp]
         L.fg_sort_workspace_size.restype = C.c_size_t
@@ -190,8 +190,8 @@ class Splats:
 # ---------------------------------------------------------------------------
 # the C-ABI, one function per entry point
 # ---------------------------------------------------------------------------
-def fg_filter_workspace_size(n_nodes: int, n_internal_span: int) -> int:
-    return int(lib().fg_filter_workspace_size(n_nodes, n_internal_span))
+def fg_filter_workspace_size(n_nodes: int, n_internal_span: int, n_views: int = 1) -> int:
+    return int(lib().fg_filter_workspace_size(n_nodes, n_internal_span, n_views))
 
 
 def fg_sort_workspace_size(cap_sel: int, cap_pairs: int, cam) -> int:
@@ -199,11 +199,15 @@ def fg_sort_workspace_size(cap_sel: int, cap_pairs: int, cam) -> int:
     return int(lib().fg_sort_workspace_size(cap_sel, cap_pairs, _ref(cs)))
 
 
-def fg_filter(tree: DeviceTree, cam, tau_R: float, sel_bits, sel_idx, cap_sel: int, n_sel, status, ws,
+def fg_filter(tree: DeviceTree, cams, tau_R: float, sel_bits, sel_idx, cap_sel: int, n_sel, status, ws,
               stream=None):
-    ts, cs = tree.struct(), camera_struct(cam)
-    _check(lib().fg_filter(_ref(ts), _ref(cs), C.c_float(tau_R), _p(sel_bits), _p(sel_idx), cap_sel, _p(n_sel),
-                           _p(status), _p(ws), ws.numel() * ws.element_size(), _stream(stream)), "fg_filter")
+    """cams: one camera or a sequence of cameras (node-major multi-view filter)."""
+    cams = list(cams) if isinstance(cams, (list, tuple)) else [cams]
+    ts = tree.struct()
+    arr = (FgCamera * len(cams))(*[camera_struct(c) for c in cams])
+    _check(lib().fg_filter(_ref(ts), C.cast(arr, C.c_void_p), len(cams), C.c_float(tau_R), _p(sel_bits),
+                           _p(sel_idx), cap_sel, _p(n_sel), _p(status), _p(ws), ws.numel() * ws.element_size(),
+                           _stream(stream)), "fg_filter")
 
 
 def fg_preprocess(tree: DeviceTree, cam, tau: float, sel_idx, n_sel, cap_sel: int, out: Splats, status,

@@ -461,3 +461,47 @@ def city20m_batch_views(n: int = 32) -> List[Camera]:
     res = [(1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)]
     return flythrough(n, seed=1, altitude=CITY_ALTITUDE, pitch_deg=CITY_PITCH_DEG, yaw_jitter_deg=15.0,
                       params=np.arange(n) * (8.0 / n), resolutions=res)
+
+
+# --------------------------------------------------------------------------
+# differentiable workload: raw Gaussian parameters
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class RawGaussians:
+    mean: np.ndarray       # f32 [3, M]
+    log_scale: np.ndarray  # f32 [3, M]
+    quat: np.ndarray       # f32 [4, M]
+    logit: np.ndarray      # f32 [M]
+    sh: np.ndarray         # f32 [M, K, 3]
+    sh_degree: int
+
+
+def flat_gaussians(n: int = 2_000_000, seed: int = 0) -> RawGaussians:
+    """n Gaussians with the city1m leaf law (thin blobs, log-scale N(-3.5, 0.5),
+    logits N(0, 1.5), SH degree 3 N(0, 0.3)), kept where their centre projects
+    into the city1m camera's image (drawn 3x over in the ground region that view
+    sees, x in [-80, 80], y in [-95, 25], z in [0, 8]; the first n kept in
+    Morton order), so all n are rendered by that view."""
+    spec = CitySpec(n_leaves=3 * n, box=(80.0, 60.0, 8.0), n_blobs=256, blob_sigma=(3.0, 3.0, 0.02),
+                    leaf_log_scale_mu=-3.5, seed=seed)
+    pos, log_s, quat, op, sh = city_leaves(spec)
+    pos[:, 1] -= 35.0
+    cam = city1m_camera()
+    R = np.asarray(cam.R, np.float64).reshape(3, 3)
+    pc = pos @ R.T + np.asarray(cam.t, np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = cam.fx * pc[:, 0] / pc[:, 2] + cam.cx
+        v = cam.fy * pc[:, 1] / pc[:, 2] + cam.cy
+    keep = np.nonzero((pc[:, 2] > 1.0) & (u >= 0) & (u < cam.width) & (v >= 0) & (v < cam.height))[0][:n]
+    if keep.size < n:
+        raise ValueError("too few candidate Gaussians in view")
+    logit = np.log(op[keep]) - np.log1p(-op[keep])
+    return RawGaussians(mean=pos[keep].T.astype(np.float32).copy(), log_scale=log_s[keep].T.astype(np.float32).copy(),
+                        quat=quat[keep].T.astype(np.float32).copy(), logit=logit.astype(np.float32),
+                        sh=np.ascontiguousarray(sh[keep]), sh_degree=spec.sh_degree)
+
+
+def city1m_yaw_views(yaws_deg=(-14, -10, -6, -2, 2, 6, 10, 14)) -> List[Camera]:
+    """The city1m view turned by each yaw offset (a batch of 8 views)."""
+    return [make_camera(yaw_pitch_rotation(math.pi / 2 + math.radians(d), math.radians(-30.0)), (0.0, -120.0, 30.0),
+                        1920, 1080) for d in yaws_deg]
