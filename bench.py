@@ -114,6 +114,63 @@ def measure_fwd_bwd(torch):
     return out
 
 
+def measure_batch(torch, dtree, tau_R, tau):
+    """32 fly-through views with yaw jitter and mixed resolutions (720p to
+    2160p, global tile ids) rendered as one batch: node-major filter, per-view
+    stages, the batch replayed as one HIP graph after autotuning the blend chunk
+    and radix digit width. Compared with the same 32 views rendered one by one,
+    eagerly, with the default knobs."""
+    from paper_2603_23891_amd import batch, fg, synth
+    cams = synth.city20m_batch_views(32)
+    px = np.array([c.width * c.height for c in cams], np.float64)
+    caps = [int(max(4_000_000, 4 * p)) for p in px]
+    br = batch.BatchedRenderer(dtree, cams, cap_sel=12_000_000, cap_pairs=caps)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        fn()
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        for _ in range(reps):
+            fn()
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        return e[0].elapsed_time(e[1]) / reps
+
+    # one view at a time, default knobs (each view's filter is its own call)
+    def one_by_one():
+        for v, cam in enumerate(cams):
+            vb = br.views[v]
+            sel = br.sel_idx[v * br.cap_sel:(v + 1) * br.cap_sel]
+            ns = br.n_sel[v:v + 1]
+            fg.fg_filter(dtree, cam, tau_R, br.sel_bits, sel, br.cap_sel, ns, br.status, br.filter_ws)
+            fg.fg_preprocess(dtree, cam, tau, sel, ns, br.cap_sel, vb.splats, br.status)
+            fg.fg_sort(vb.splats, ns, br.cap_sel, cam, vb.tile_keys, vb.vals, vb.cap_pairs, vb.n_pairs, vb.ranges,
+                       br.status, vb.sort_ws)
+            fg.fg_render(vb.splats, vb.vals, vb.ranges, cam, (0.0, 0.0, 0.0), vb.image, vb.final_T, vb.n_contrib,
+                         vb.cap_pairs, None, br.status, vb.render_ws)
+
+    single_ms = timed(one_by_one, 3)
+    eager_ms = timed(lambda: br.run(tau_R, tau), 3)
+    tuned = batch.autotune(br, tau_R, tau, chunks=(256, 512, 1024), radix_bits=(6, 7, 8), repeats=2)
+    br.capture(tau_R, tau)
+    graph_ms = timed(br.replay, 5)
+    ns, npairs, status = br.counts()
+    assert status == 0, f"batch status {status}"
+    out = dict(views=len(cams), megapixels=float(px.sum() / 1e6), tiles=int(sum(c.n_tiles for c in cams)),
+               one_by_one_ms=single_ms, batched_eager_ms=eager_ms, batched_graph_ms=graph_ms,
+               views_per_s=len(cams) / (graph_ms * 1e-3), ms_per_view=graph_ms / len(cams),
+               tuned=dict(render_batch=tuned["render_batch"], radix_bits=tuned["radix_bits"]),
+               n_sel_mean=float(ns.mean()), n_pairs_total=int(npairs.sum()),
+               workload="32 views of the 20M-node city, yaw jitter +-15 deg, resolutions 720p/1080p/1440p/2160p")
+    log(f"batch: {graph_ms:.2f} ms per 32-view graph ({out['views_per_s']:.0f} views/s), "
+        f"eager {eager_ms:.2f} ms, one by one {single_ms:.2f} ms, tuned {out['tuned']}")
+    del br
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +178,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'Sharding').")
@@ -224,6 +282,7 @@ def main():
         roofline = dict(bound="hbm", kernel=dominant, achieved=d["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=d["frac"], traffic=None)
 
+    batched = None if args.no_batch else measure_batch(torch, dtree, tau_R, tau)
     fwd_bwd = None if args.no_backward else measure_fwd_bwd(torch)
 
     cpu = None
@@ -254,6 +313,7 @@ def main():
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched_views": batched,
         "fwd_bwd_ms_per_view": fwd_bwd,
     }
     print(json.dumps(out), flush=True)
