@@ -104,8 +104,11 @@ def test_autograd_function_and_l1_loss():
     loss.backward()
     dl = (torch.sign(img.detach() - target) / img.numel()).contiguous()
     direct = r.backward(*[a.detach() for a in args], cam, dl)
+    # two runs of the backward: fp32 atomics add in a different order each
+    # time, so elements that cancel differ at the rounding level of the
+    # group's largest terms
     for a, d in zip(args, direct):
-        assert torch.allclose(a.grad, d, rtol=1e-5, atol=1e-9 * float(d.abs().max()) + 1e-30)
+        assert torch.allclose(a.grad, d, rtol=1e-5, atol=1e-6 * float(d.abs().max()) + 1e-30)
     # and the float64 oracle of the same L1 loss
     fwd = oracle.forward32(prm, cam)
     _, g64 = oracle.replay64(prm, cam, fwd, dL_dimage=dl.cpu().numpy().astype(np.float64), want_image=False)
