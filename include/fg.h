@@ -192,9 +192,11 @@ size_t fg_sort_workspace_size(int64_t cap_sel, int64_t cap_pairs, const fg_camer
  * full 64-bit key of entry k is tile_keys[k] << 32 | bits(depth[vals[k]]));
  * *n_pairs (device u32); ranges [n_tiles][2] = [start, end) of each of this
  * view's tiles in the sorted list ([0, 0) for an empty tile).
- * Method: exclusive prefix scan of the tile counts in depth order, key
- * emission, and stable LDS-staged LSD radix sorts (depth of the splats, then
- * tile ids of the pairs), which gives the (tile, depth, index) order.
+ * Method: the splats that cover a tile are packed in index order and
+ * stably radix-sorted by depth; an exclusive prefix scan of their tile counts
+ * in that order places their pairs (key emission), and a stable radix sort of
+ * the pairs by tile id gives the (tile, depth, index) order (LDS-staged LSD
+ * passes throughout).
  * Errors: FG_ERR_INVALID_ARG, FG_ERR_WORKSPACE; FG_STATUS_PAIR_OVERFLOW
  * on the device when the pairs exceed cap_pairs. */
 int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t cap_sel, const fg_camera* cam,

@@ -17,12 +17,11 @@ namespace fgd {
 constexpr int kWave = 64;
 constexpr int kTile = 16;
 
-// exp(x) for x <= 0, flushed to 0 below -87: Cody & Waite reduction
-// x = n ln2 + r (ln2 as a 16-bit head plus a tail), Taylor polynomial of
-// degree 7 for e^r in Horner form with fused multiply-adds, times 2^n.
-__device__ __forceinline__ float exp_neg(float x)
+// exp(x) for -87 <= x <= 0: Cody & Waite reduction x = n ln2 + r (ln2 as a
+// 16-bit head plus a tail), Taylor polynomial of degree 7 for e^r in Horner
+// form with fused multiply-adds, times 2^n.
+__device__ __forceinline__ float exp_neg_in_range(float x)
 {
-    if (x < -87.0f) return 0.0f;
     const float n = rintf(x * 1.44269504f);
     float r = fmaf(-n, 0.693145751953125f, x);
     r = fmaf(-n, 1.42860677e-06f, r);
@@ -35,6 +34,13 @@ __device__ __forceinline__ float exp_neg(float x)
     p = fmaf(p, r, 1.0f);
     p = fmaf(p, r, 1.0f);
     return ldexpf(p, (int)n);
+}
+
+// exp(x) for x <= 0, flushed to 0 below -87.
+__device__ __forceinline__ float exp_neg(float x)
+{
+    if (x < -87.0f) return 0.0f;
+    return exp_neg_in_range(x);
 }
 
 // ln(x) for x > 1: x = m 2^e with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s),

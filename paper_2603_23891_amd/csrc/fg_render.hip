@@ -244,6 +244,141 @@ __global__ __launch_bounds__(kThreads) void k_masks(const float2* __restrict__ x
     flush_stats<STATS, 3>(f, frag_stats);
 }
 
+// alpha of a fragment that passed the skip tests (so -5.6 <= power <= 0):
+// the same expressions as pass_masks, hence the same value.
+__device__ __forceinline__ float passed_alpha(float2 mm, float4 co, float fpx, float fpy)
+{
+    const float dx = mm.x - fpx;
+    const float dy = mm.y - fpy;
+    const float power = -0.5f * ((co.x * dx) * dx + (co.z * dy) * dy) - (co.y * dx) * dy;
+    const float alpha = co.w * fgd::exp_neg_in_range(power);
+    return alpha < 0.99f ? alpha : 0.99f;
+}
+
+struct PixelState {
+    float T, C0, C1, C2;
+    uint32_t last;
+    bool done;
+};
+
+// One blend step of Eq. (2) in list order: stop before a splat that would take
+// T below 1e-4, otherwise accumulate its colour and attenuate T.
+template <bool STATS>
+__device__ __forceinline__ void blend_step(PixelState& p, float alpha, float4 c, uint32_t pos, Frag& f)
+{
+    const float Tn = p.T * (1.0f - alpha);
+    if (Tn < 1e-4f) {
+        p.done = true;
+        return;
+    }
+    p.C0 = p.C0 + (c.x * alpha) * p.T;
+    p.C1 = p.C1 + (c.y * alpha) * p.T;
+    p.C2 = p.C2 + (c.z * alpha) * p.T;
+    p.T = Tn;
+    p.last = pos + 1u;
+    if (STATS) ++f.n_blend;
+}
+
+// Walks the marked splats of one staged chunk for this lane's pixel. mcol
+// points at the pixel's first mask word (words kThreads apart). Up to four
+// marked splats of one 64-splat mask word are taken at a time and their
+// alphas (independent of T) computed together, so their LDS reads and
+// arithmetic overlap; the blend steps then run strictly in list order.
+template <int CHUNK, bool STATS>
+__device__ __forceinline__ void walk(const uint32_t* mcol, const float2* s_xy, const float4* s_co,
+                                     const float4* s_rgb, float fpx, float fpy, uint32_t base, PixelState& p,
+                                     Frag& f)
+{
+    constexpr int kPairs = CHUNK / 64;
+    int w = -1;
+    unsigned long long m = 0ull;
+    while (!p.done) {
+        while (m == 0ull && ++w < kPairs)
+            m = (unsigned long long)mcol[(2 * w) * kThreads] |
+                ((unsigned long long)mcol[(2 * w + 1) * kThreads] << 32);
+        if (m == 0ull) break;
+        const int b = w << 6;
+        const int j0 = b + __builtin_ctzll(m);
+        m &= m - 1ull;
+        const bool v1 = m != 0ull;
+        const int j1 = v1 ? b + __builtin_ctzll(m) : j0;
+        m &= m - 1ull;
+        const bool v2 = m != 0ull;
+        const int j2 = v2 ? b + __builtin_ctzll(m) : j0;
+        m &= m - 1ull;
+        const bool v3 = m != 0ull;
+        const int j3 = v3 ? b + __builtin_ctzll(m) : j0;
+        m &= m - 1ull;
+        const float a0 = passed_alpha(s_xy[j0], s_co[j0], fpx, fpy);
+        const float a1 = passed_alpha(s_xy[j1], s_co[j1], fpx, fpy);
+        const float a2 = passed_alpha(s_xy[j2], s_co[j2], fpx, fpy);
+        const float a3 = passed_alpha(s_xy[j3], s_co[j3], fpx, fpy);
+        const float4 c0 = s_rgb[j0], c1 = s_rgb[j1], c2 = s_rgb[j2], c3 = s_rgb[j3];
+        blend_step<STATS>(p, a0, c0, base + (uint32_t)j0, f);
+        if (v1 && !p.done) blend_step<STATS>(p, a1, c1, base + (uint32_t)j1, f);
+        if (v2 && !p.done) blend_step<STATS>(p, a2, c2, base + (uint32_t)j2, f);
+        if (v3 && !p.done) blend_step<STATS>(p, a3, c3, base + (uint32_t)j3, f);
+    }
+}
+
+// Register copy of one chunk: the splat records this thread stages and the
+// mask words of its pixel (zero where the masks are computed in place).
+template <int CHUNK>
+struct ChunkRegs {
+    static constexpr int S = CHUNK / kThreads;
+    float2 xy[S];
+    float4 co[S];
+    float4 rgb[S];
+    uint32_t m[CHUNK / 32];
+};
+
+template <int CHUNK>
+__device__ __forceinline__ int chunk_count(uint32_t r0, uint32_t r1, uint32_t chunk)
+{
+    const uint32_t start = r0 + chunk * CHUNK;
+    return r1 > start ? (int)(r1 - start < (uint32_t)CHUNK ? r1 - start : (uint32_t)CHUNK) : 0;
+}
+
+template <int CHUNK>
+__device__ __forceinline__ void fetch_vals(const uint32_t* __restrict__ vals, uint32_t r0, uint32_t r1, uint32_t chunk,
+                                           uint32_t (&g)[ChunkRegs<CHUNK>::S])
+{
+    const int cnt = chunk_count<CHUNK>(r0, r1, chunk);
+    const uint32_t start = r0 + chunk * CHUNK;
+#pragma unroll
+    for (int k = 0; k < ChunkRegs<CHUNK>::S; k++) {
+        const int j = k * kThreads + (int)threadIdx.x;
+        g[k] = j < cnt ? vals[start + j] : 0u;
+    }
+}
+
+template <int CHUNK>
+__device__ __forceinline__ void fetch_chunk(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
+                                            const float4* __restrict__ rgb_depth, const uint32_t* __restrict__ masks,
+                                            uint32_t r0, uint32_t r1, uint32_t chunk,
+                                            const uint32_t (&g)[ChunkRegs<CHUNK>::S], uint32_t mf,
+                                            uint32_t n_mask_items, ChunkRegs<CHUNK>& R)
+{
+    const int cnt = chunk_count<CHUNK>(r0, r1, chunk);
+#pragma unroll
+    for (int k = 0; k < ChunkRegs<CHUNK>::S; k++) {
+        const int j = k * kThreads + (int)threadIdx.x;
+        if (j < cnt) {
+            R.xy[k] = xy[g[k]];
+            R.co[k] = conic_o[g[k]];
+            R.rgb[k] = rgb_depth[g[k]];
+        }
+    }
+    if (mf + chunk < n_mask_items) {
+        const uint32_t* src = masks + (size_t)(mf + chunk) * (CHUNK / 32 * kThreads);
+#pragma unroll
+        for (int w = 0; w < CHUNK / 32; w++) R.m[w] = src[w * kThreads + threadIdx.x];
+    } else {
+#pragma unroll
+        for (int w = 0; w < CHUNK / 32; w++) R.m[w] = 0u;
+    }
+}
+
 template <int CHUNK, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
                                                      const float4* __restrict__ rgb_depth,
@@ -263,83 +398,90 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
     const int tid = threadIdx.x;
     const uint32_t n_mask_items = ws.counters[2];
     Frag f = {0, 0, 0, 0};
+    if (tid == 0) s_item = atomicAdd(&ws.counters[0], 1u);
+    __syncthreads();
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(&ws.counters[0], 1u);
-        __syncthreads();
         const uint32_t item = s_item;
         if ((int64_t)item >= n_tiles) break;
         const uint32_t tile = ws.order[item];
         const uint32_t r0 = ranges[2 * tile], r1 = ranges[2 * tile + 1];
         const uint32_t nch = ws.nch[tile];
+        // Tiles are ordered heavy first, so a light tile is followed only by
+        // light ones: its workgroup claims the next tile now, hiding the
+        // atomic's latency. A heavy tile's workgroup does not, so no tile
+        // waits behind a long one.
+        uint32_t next_item = 0;
+        if (tid == 0 && nch <= 1) next_item = atomicAdd(&ws.counters[0], 1u);
         const uint32_t mf = nch > 1 ? ws.mfirst[tile] : 0u;
         const int tx = (int)(tile % (uint32_t)Wt), ty = (int)(tile / (uint32_t)Wt);
         const int px = tx * fgd::kTile + (tid % fgd::kTile);
         const int py = ty * fgd::kTile + (tid / fgd::kTile);
         const bool inside = px < W && py < H;
         const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
-        float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-        uint32_t last = 0;
-        bool done = !inside;
-        for (uint32_t chunk = 0; chunk < nch; chunk++) {
-            // a workgroup stops once every pixel of the tile has terminated
-            if (__syncthreads_count(done) == kThreads) break;
-            const uint32_t start = r0 + chunk * CHUNK;
-            const int cnt = r1 > start ? (int)(r1 - start < (uint32_t)CHUNK ? r1 - start : (uint32_t)CHUNK) : 0;
-            const bool stored = nch > 1 && mf + chunk < n_mask_items;
-            if (!stored)
-                for (int i = tid; i < kWords * kThreads; i += kThreads) s_mask[i] = 0u;
-            stage(xy, conic_o, rgb_depth, vals, start, cnt, s_xy, s_co, s_rgb);
-            uint32_t mreg[kWords];
-            if (stored) {
-                const uint32_t* src = ws.masks + (size_t)(mf + chunk) * (kWords * kThreads);
+        PixelState p = {1.0f, 0.0f, 0.0f, 0.0f, 0u, !inside};
+        if (nch <= 1) {
+            // light tile: one chunk, masks computed here
+            const int cnt = (int)(r1 - r0);
 #pragma unroll
-                for (int w = 0; w < kWords; w++) mreg[w] = src[w * kThreads + tid];
-            }
+            for (int w = 0; w < kWords; w++) s_mask[w * kThreads + tid] = 0u;
+            stage(xy, conic_o, rgb_depth, vals, r0, cnt, s_xy, s_co, s_rgb);
             __syncthreads();
-            if (!stored) {
-                pass_masks<STATS>(s_xy, s_co, cnt, tx, ty, W, H, s_mask, f);
-                __syncthreads();
-#pragma unroll
-                for (int w = 0; w < kWords; w++) mreg[w] = s_mask[w * kThreads + tid];
+            pass_masks<STATS>(s_xy, s_co, cnt, tx, ty, W, H, s_mask, f);
+            __syncthreads();
+            walk<CHUNK, STATS>(s_mask + tid, s_xy, s_co, s_rgb, fpx, fpy, 0u, p, f);
+        } else {
+            // heavy tile: while one chunk is walked, the next chunk's splat
+            // records and stored masks are loaded into registers, and the
+            // indices of the chunk after it
+            ChunkRegs<CHUNK> R;
+            uint32_t gnext[ChunkRegs<CHUNK>::S];
+            {
+                uint32_t g0[ChunkRegs<CHUNK>::S];
+                fetch_vals<CHUNK>(vals, r0, r1, 0u, g0);
+                fetch_chunk<CHUNK>(xy, conic_o, rgb_depth, ws.masks, r0, r1, 0u, g0, mf, n_mask_items, R);
+                fetch_vals<CHUNK>(vals, r0, r1, 1u, gnext);
             }
+            for (uint32_t chunk = 0; chunk < nch; chunk++) {
+                // a workgroup stops once every pixel of the tile has terminated
+                if (__syncthreads_count(p.done) == kThreads) break;
+                const int cnt = chunk_count<CHUNK>(r0, r1, chunk);
 #pragma unroll
-            for (int w = 0; w < kWords; w++) {
-                uint32_t m = mreg[w];
-                while (m != 0u && !done) {
-                    const int j = w * 32 + __builtin_ctz(m);
-                    m &= m - 1u;
-                    const float2 mm = s_xy[j];
-                    const float4 co = s_co[j];
-                    const float dx = mm.x - fpx;
-                    const float dy = mm.y - fpy;
-                    const float power = -0.5f * ((co.x * dx) * dx + (co.z * dy) * dy) - (co.y * dx) * dy;
-                    float alpha = co.w * fgd::exp_neg(power);
-                    alpha = alpha < 0.99f ? alpha : 0.99f;
-                    const float Tn = T * (1.0f - alpha);
-                    if (Tn < 1e-4f) {
-                        done = true;
-                        break;
+                for (int k = 0; k < ChunkRegs<CHUNK>::S; k++) {
+                    const int j = k * kThreads + tid;
+                    if (j < cnt) {
+                        s_xy[j] = R.xy[k];
+                        s_co[j] = R.co[k];
+                        s_rgb[j] = R.rgb[k];
                     }
-                    const float4 c = s_rgb[j];
-                    C0 = C0 + (c.x * alpha) * T;
-                    C1 = C1 + (c.y * alpha) * T;
-                    C2 = C2 + (c.z * alpha) * T;
-                    T = Tn;
-                    last = chunk * CHUNK + (uint32_t)j + 1u;
-                    if (STATS) ++f.n_blend;
                 }
+                // every lane reads only its own pixel's mask words (column tid)
+#pragma unroll
+                for (int w = 0; w < kWords; w++) s_mask[w * kThreads + tid] = R.m[w];
+                __syncthreads();
+                if (chunk + 1 < nch) {
+                    fetch_chunk<CHUNK>(xy, conic_o, rgb_depth, ws.masks, r0, r1, chunk + 1, gnext, mf, n_mask_items,
+                                       R);
+                    if (chunk + 2 < nch) fetch_vals<CHUNK>(vals, r0, r1, chunk + 2, gnext);
+                }
+                if (mf + chunk >= n_mask_items) {  // beyond the mask store: masks computed here
+                    pass_masks<STATS>(s_xy, s_co, cnt, tx, ty, W, H, s_mask, f);
+                    __syncthreads();
+                }
+                walk<CHUNK, STATS>(s_mask + tid, s_xy, s_co, s_rgb, fpx, fpy, chunk * CHUNK, p, f);
             }
         }
         if (inside) {
             const size_t o = (size_t)py * W + px;
             const size_t plane = (size_t)W * H;
-            image[o] = C0 + T * bg0;
-            image[plane + o] = C1 + T * bg1;
-            image[2 * plane + o] = C2 + T * bg2;
-            final_T[o] = T;
-            n_contrib[o] = last;
+            image[o] = p.C0 + p.T * bg0;
+            image[plane + o] = p.C1 + p.T * bg1;
+            image[2 * plane + o] = p.C2 + p.T * bg2;
+            final_T[o] = p.T;
+            n_contrib[o] = p.last;
         }
         __syncthreads();  // LDS and s_item are reused by the next tile
+        if (tid == 0) s_item = nch <= 1 ? next_item : atomicAdd(&ws.counters[0], 1u);
+        __syncthreads();
     }
     flush_stats<STATS, 4>(f, frag_stats);
 }

@@ -3,9 +3,10 @@
 // The required order is ascending (tile id, depth bits, splat index). It is
 // reached with two stable sorts instead of one sort of 64-bit keys:
 //
-//   1. the splats are radix-sorted by their 32-bit depth key (ties keep
-//      ascending splat index);
-//   2. an exclusive prefix scan of the tile counts, taken in that depth
+//   1. the splats that cover at least one tile are packed in index order
+//      (splats whose shrunk rectangle is empty emit nothing) and radix-sorted
+//      by their 32-bit depth key, so ties keep ascending splat index;
+//   2. an exclusive prefix scan of their tile counts, taken in that depth
 //      order, gives each splat its output offset, and the splat emits one
 //      (tile id, splat index) pair per tile of its rectangle;
 //   3. the pairs are radix-sorted by tile id only (ceil(log2 tiles) bits),
@@ -22,6 +23,11 @@
 //               bits, per-wave counts combined in LDS in item order), items
 //               staged through LDS in locally sorted order, then written out
 //               so that consecutive lanes write consecutive addresses.
+//
+// Block offsets of the packing and emission steps are exclusive sums over
+// the per-block counts of all earlier blocks, which every block adds up
+// itself (a few thousand L2-resident words), so no separate scan launch sits
+// between counting and writing.
 #include "fg_device.h"
 
 namespace {
@@ -219,14 +225,84 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_depth_pack(const float4* __restrict__ rgb_depth,
-                                                         const uint32_t* __restrict__ n_p, int64_t cap,
-                                                         uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval)
+// Sum of v[0 .. k) over the workgroup (every thread gets it).
+__device__ __forceinline__ unsigned long long block_prefix(const uint32_t* __restrict__ v, int64_t k,
+                                                           unsigned long long* s_red)
 {
+    unsigned long long x = 0;
+    for (int64_t i = threadIdx.x; i < k; i += kThreads) x += v[i];
+#pragma unroll
+    for (int d = fgd::kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, fgd::kWave);
+    if (fgd::lane_id() == 0) s_red[threadIdx.x / fgd::kWave] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) t += s_red[w];
+    __syncthreads();
+    return t;
+}
+
+// Per 2048 splats (index order): how many cover at least one tile. Also
+// clears the tile ranges of this view.
+__global__ __launch_bounds__(kThreads) void k_vis_count(const uint32_t* __restrict__ tiles,
+                                                        const uint32_t* __restrict__ n_p, int64_t cap,
+                                                        uint32_t* __restrict__ vcnt, uint32_t* __restrict__ ranges,
+                                                        int64_t n_tiles)
+{
+    __shared__ uint32_t s_wave[kWaves];
     const int64_t n = count_of(n_p, cap);
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        dkey[i] = __float_as_uint(rgb_depth[i].w);
-        dval[i] = (uint32_t)i;
+    const int64_t nblk = (n + kTileItems - 1) / kTileItems;
+    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < 2 * n_tiles; t += (int64_t)gridDim.x * kThreads)
+        ranges[t] = 0u;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int r = 0; r < kIPT; r++) {
+            const int64_t j = blk * kTileItems + r * kThreads + threadIdx.x;
+            if (j < n && tiles[j] != 0u) ++c;
+        }
+        uint32_t total;
+        block_excl_scan(c, s_wave, total);
+        if (threadIdx.x == 0) vcnt[blk] = total;
+    }
+}
+
+// Packs the splats that cover a tile, in index order: dkey = depth bits,
+// dval = splat index; *n_vis = their number.
+__global__ __launch_bounds__(kThreads) void k_vis_pack(const float4* __restrict__ rgb_depth,
+                                                       const uint32_t* __restrict__ tiles,
+                                                       const uint32_t* __restrict__ n_p, int64_t cap,
+                                                       const uint32_t* __restrict__ vcnt, uint32_t* __restrict__ dkey,
+                                                       uint32_t* __restrict__ dval, uint32_t* __restrict__ n_vis)
+{
+    __shared__ uint32_t s_wave[kWaves];
+    __shared__ unsigned long long s_red[kWaves];
+    const int64_t n = count_of(n_p, cap);
+    const int64_t nblk = (n + kTileItems - 1) / kTileItems;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const unsigned long long base = block_prefix(vcnt, blk, s_red);
+        const int64_t j0 = blk * kTileItems + (int64_t)threadIdx.x * kIPT;
+        uint32_t c = 0;
+        bool vis[kIPT];
+#pragma unroll
+        for (int r = 0; r < kIPT; r++) {
+            vis[r] = j0 + r < n && tiles[j0 + r] != 0u;
+            c += vis[r] ? 1u : 0u;
+        }
+        uint32_t total;
+        uint64_t off = base + block_excl_scan(c, s_wave, total);
+#pragma unroll
+        for (int r = 0; r < kIPT; r++) {
+            if (vis[r]) {
+                dkey[off] = __float_as_uint(rgb_depth[j0 + r].w);
+                dval[off] = (uint32_t)(j0 + r);
+                ++off;
+            }
+        }
+    }
+    if (blockIdx.x == 0) {
+        const unsigned long long t = block_prefix(vcnt, nblk, s_red);
+        if (threadIdx.x == 0) *n_vis = (uint32_t)t;
     }
 }
 
@@ -252,89 +328,77 @@ __global__ __launch_bounds__(kThreads) void k_count_reduce(const uint32_t* __res
     }
 }
 
-// One workgroup: exclusive scan of the block sums; n_pairs and overflow.
-__global__ __launch_bounds__(1024) void k_count_scan(uint32_t* __restrict__ bsum, const uint32_t* __restrict__ n_p,
-                                                     int64_t cap, int64_t cap_pairs, uint32_t* __restrict__ n_pairs,
-                                                     uint32_t* __restrict__ status)
-{
-    __shared__ unsigned long long part[1024];
-    const int64_t n = count_of(n_p, cap);
-    const int64_t nblk = (n + kEmitItems - 1) / kEmitItems;
-    const int t = threadIdx.x;
-    const int64_t per = (nblk + 1023) / 1024;
-    const int64_t lo = t * per;
-    const int64_t hi = lo + per < nblk ? lo + per : nblk;
-    unsigned long long s = 0;
-    for (int64_t i = lo; i < hi; i++) s += bsum[i];
-    part[t] = s;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const unsigned long long v = t >= d ? part[t - d] : 0ull;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    unsigned long long run = part[t] - s;
-    for (int64_t i = lo; i < hi; i++) {
-        const uint32_t v = bsum[i];
-        bsum[i] = (uint32_t)(run < 0xFFFFFFFFull ? run : 0xFFFFFFFFull);
-        run += v;
-    }
-    if (t == 1023) {
-        const unsigned long long total = part[1023];
-        *n_pairs = (uint32_t)(total < 0xFFFFFFFFull ? total : 0xFFFFFFFFull);
-        if ((long long)total > cap_pairs) atomicOr(status, FG_STATUS_PAIR_OVERFLOW);
-    }
-}
-
-// Per 2048 splats in depth order (8 consecutive per thread): offsets by a
-// block scan plus the block's scanned sum, then one (tile id, splat) pair per
-// covered tile, rows then columns.
+// Per 2048 splats in depth order: every splat's output offset (the block's
+// offset, summed from the earlier blocks' totals, plus an exclusive scan
+// within the block), then the block's pairs are written with thread k taking
+// output positions k, k + 256, ...: a binary search over the offsets finds
+// the splat, and the position within its rectangle (rows, then columns)
+// gives the tile. Block 0 also stores n_pairs and flags an overflow.
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles,
                                                    const ushort4* __restrict__ rect, const uint32_t* __restrict__ n_p,
                                                    int64_t cap, const uint32_t* __restrict__ bsum, int64_t cap_pairs,
                                                    int Wt, uint32_t tile_base, uint32_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals)
+                                                   uint32_t* __restrict__ vals, uint32_t* __restrict__ n_pairs,
+                                                   uint32_t* __restrict__ status)
 {
     __shared__ uint32_t s_wave[kWaves];
+    __shared__ unsigned long long s_red[kWaves];
+    __shared__ uint32_t s_off[kEmitItems + 1];
+    __shared__ uint32_t s_g[kEmitItems];
+    __shared__ ushort4 s_rect[kEmitItems];
     const int64_t n = count_of(n_p, cap);
     const int64_t nblk = (n + kEmitItems - 1) / kEmitItems;
+    const int tid = threadIdx.x;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const int64_t j0 = blk * kEmitItems + (int64_t)threadIdx.x * kEmitIPT;
-        uint32_t g[kEmitIPT], c[kEmitIPT];
-        uint32_t s = 0;
+        const unsigned long long base = block_prefix(bsum, blk, s_red);
+        const int64_t j0 = blk * kEmitItems + (int64_t)tid * kEmitIPT;
+        uint32_t c[kEmitIPT];
+        uint32_t sum = 0;
 #pragma unroll
         for (int r = 0; r < kEmitIPT; r++) {
             const int64_t j = j0 + r;
-            g[r] = j < n ? order[j] : 0u;
-            c[r] = j < n ? tiles[g[r]] : 0u;
-            s += c[r];
+            const uint32_t g = j < n ? order[j] : 0u;
+            c[r] = j < n ? tiles[g] : 0u;
+            s_g[tid * kEmitIPT + r] = g;
+            s_rect[tid * kEmitIPT + r] = j < n ? rect[g] : make_ushort4(0, 0, 0, 0);
+            sum += c[r];
         }
         uint32_t total;
-        int64_t off = (int64_t)bsum[blk] + block_excl_scan(s, s_wave, total);
+        uint32_t run = block_excl_scan(sum, s_wave, total);
 #pragma unroll
         for (int r = 0; r < kEmitIPT; r++) {
-            if (c[r]) {
-                const ushort4 q = rect[g[r]];
-                for (int ty = q.y; ty < q.w; ty++) {
-                    const uint32_t row = tile_base + (uint32_t)(ty * Wt);
-                    for (int tx = q.x; tx < q.z; tx++) {
-                        if (off < cap_pairs) {
-                            keys[off] = row + (uint32_t)tx;
-                            vals[off] = g[r];
-                        }
-                        ++off;
-                    }
-                }
+            s_off[tid * kEmitIPT + r] = run;
+            run += c[r];
+        }
+        if (tid == 0) s_off[kEmitItems] = total;
+        __syncthreads();
+        for (uint32_t o = tid; o < total; o += kThreads) {
+            // last splat k with s_off[k] <= o (splats with no tile share
+            // their successor's offset and are passed over)
+            int lo = 0, hi = kEmitItems;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_off[mid] <= o) lo = mid; else hi = mid;
+            }
+            const ushort4 q = s_rect[lo];
+            const uint32_t w = (uint32_t)(q.z - q.x);
+            const uint32_t local = o - s_off[lo];
+            const uint32_t ty = q.y + local / w, tx = q.x + local % w;
+            const unsigned long long dst = base + o;
+            if (dst < (unsigned long long)cap_pairs) {
+                keys[dst] = tile_base + ty * (uint32_t)Wt + tx;
+                vals[dst] = s_g[lo];
             }
         }
+        __syncthreads();
     }
-}
-
-__global__ void k_ranges_clear(uint32_t* __restrict__ ranges, int64_t n_tiles)
-{
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 2 * n_tiles; t += (int64_t)gridDim.x * blockDim.x)
-        ranges[t] = 0u;
+    if (blockIdx.x == 0) {
+        const unsigned long long t = block_prefix(bsum, nblk, s_red);
+        if (tid == 0) {
+            *n_pairs = (uint32_t)(t < 0xFFFFFFFFull ? t : 0xFFFFFFFFull);
+            if ((long long)t > cap_pairs) atomicOr(status, FG_STATUS_PAIR_OVERFLOW);
+        }
+    }
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_p, int64_t cap,
@@ -355,21 +419,21 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 int64_t tiles_for(int64_t n) { return (n + kTileItems - 1) / kTileItems; }
 
 struct SortWs {
-    uint32_t *dkey0, *dval0, *dkey1, *dval1, *bsum, *kalt, *valt, *hist, *digit_total;
+    uint32_t *dkey0, *dval0, *dkey1, *dval1, *bsum, *kalt, *valt, *hist, *digit_total, *vcnt, *n_vis;
 };
 
 size_t carve(void* base, int64_t cap_sel, int64_t cap_pairs, SortWs* w)
 {
     const int64_t ht = tiles_for(cap_sel > cap_pairs ? cap_sel : cap_pairs);
-    const size_t sizes[9] = {
-        (size_t)cap_sel * 4, (size_t)cap_sel * 4, (size_t)cap_sel * 4, (size_t)cap_sel * 4,
-        (size_t)((cap_sel + kEmitItems - 1) / kEmitItems + 1) * 4,
+    const size_t nblk = (size_t)((cap_sel + kTileItems - 1) / kTileItems + 1);
+    const size_t sizes[11] = {
+        (size_t)cap_sel * 4, (size_t)cap_sel * 4, (size_t)cap_sel * 4, (size_t)cap_sel * 4, nblk * 4,
         (size_t)cap_pairs * 4, (size_t)cap_pairs * 4,
-        (size_t)256 * (size_t)(ht + 1) * 4, (size_t)256 * 4};
-    uint32_t** dst[9] = {&w->dkey0, &w->dval0, &w->dkey1, &w->dval1, &w->bsum, &w->kalt, &w->valt, &w->hist,
-                         &w->digit_total};
+        (size_t)256 * (size_t)(ht + 1) * 4, (size_t)256 * 4, nblk * 4, 4};
+    uint32_t** dst[11] = {&w->dkey0, &w->dval0, &w->dkey1, &w->dval1, &w->bsum, &w->kalt, &w->valt, &w->hist,
+                          &w->digit_total, &w->vcnt, &w->n_vis};
     size_t off = 0;
-    for (int i = 0; i < 9; i++) {
+    for (int i = 0; i < 11; i++) {
         if (base) *dst[i] = (uint32_t*)((char*)base + off);
         off += align_up(sizes[i] + 4);
     }
@@ -436,37 +500,37 @@ extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t c
     const uint64_t max_tile = (uint64_t)cam->tile_base + (uint64_t)n_tiles - 1;
     if (max_tile > 0xFFFFFFFFull) return FG_ERR_UNSUPPORTED;
 
-    hipLaunchKernelGGL(k_ranges_clear, dim3((unsigned)((2 * n_tiles + 255) / 256 < 1024 ? (2 * n_tiles + 255) / 256 : 1024)),
-                       dim3(256), 0, s, ranges, n_tiles);
-    if (cap_sel == 0) {
-        hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(1024), 0, s, w.bsum, n_sel, cap_sel, cap_pairs, n_pairs, status);
-        return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
-    }
-    // 1. depth order of the splats (4 passes of 8 bits, result back in buffer 0)
-    int64_t g1 = (cap_sel + kThreads - 1) / kThreads;
-    if (g1 > 4096) g1 = 4096;
-    hipLaunchKernelGGL(k_depth_pack, dim3((unsigned)g1), dim3(kThreads), 0, s, (const float4*)splats->rgb_depth, n_sel,
-                       cap_sel, w.dkey0, w.dval0);
+    // 1. splats that cover a tile, packed in index order, then their depth
+    //    order (4 passes of 8 bits, result back in buffer 0)
+    int64_t gb = (cap_sel + kTileItems - 1) / kTileItems;
+    const int64_t gclr = (2 * n_tiles + kThreads - 1) / kThreads;
+    int64_t gc = gb > gclr ? gb : gclr;
+    if (gc > 4096) gc = 4096;
+    if (gc < 1) gc = 1;
+    if (gb > 4096) gb = 4096;
+    if (gb < 1) gb = 1;
+    hipLaunchKernelGGL(k_vis_count, dim3((unsigned)gc), dim3(kThreads), 0, s, splats->tiles, n_sel, cap_sel, w.vcnt,
+                       ranges, n_tiles);
+    hipLaunchKernelGGL(k_vis_pack, dim3((unsigned)gb), dim3(kThreads), 0, s, (const float4*)splats->rgb_depth,
+                       splats->tiles, n_sel, cap_sel, w.vcnt, w.dkey0, w.dval0, w.n_vis);
     for (int p = 0; p < 4; p++) {
         const bool even = (p % 2) == 0;
         radix_pass<8>(even ? w.dkey0 : w.dkey1, even ? w.dval0 : w.dval1, even ? w.dkey1 : w.dkey0,
-                      even ? w.dval1 : w.dval0, n_sel, cap_sel, 8 * p, w, s);
+                      even ? w.dval1 : w.dval0, w.n_vis, cap_sel, 8 * p, w, s);
     }
-    // 2. scan of the tile counts in depth order and key emission
-    int64_t ge = (cap_sel + kEmitItems - 1) / kEmitItems;
-    if (ge > 4096) ge = 4096;
-    hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)ge), dim3(kThreads), 0, s, w.dval0, splats->tiles, n_sel, cap_sel,
-                       w.bsum);
-    hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(1024), 0, s, w.bsum, n_sel, cap_sel, cap_pairs, n_pairs, status);
+    // 2. tile counts in depth order and key emission
+    hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)gb), dim3(kThreads), 0, s, w.dval0, splats->tiles, w.n_vis,
+                       cap_sel, w.bsum);
     int tile_bits = 1;
     while (tile_bits < 32 && (max_tile >> tile_bits) != 0) ++tile_bits;
     const int passes = (tile_bits + bits - 1) / bits;
     // emit into the buffer that the last pass will not write
-    uint32_t* ek = (passes % 2) ? w.kalt : tile_keys;
-    uint32_t* ev = (passes % 2) ? w.valt : vals;
+    uint32_t* ek = cap_pairs == 0 ? nullptr : (passes % 2) ? w.kalt : tile_keys;
+    uint32_t* ev = cap_pairs == 0 ? nullptr : (passes % 2) ? w.valt : vals;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)gb), dim3(kThreads), 0, s, w.dval0, splats->tiles,
+                       (const ushort4*)splats->rect, w.n_vis, cap_sel, w.bsum, cap_pairs, Wt, cam->tile_base, ek, ev,
+                       n_pairs, status);
     if (cap_pairs > 0) {
-        hipLaunchKernelGGL(k_emit, dim3((unsigned)ge), dim3(kThreads), 0, s, w.dval0, splats->tiles,
-                           (const ushort4*)splats->rect, n_sel, cap_sel, w.bsum, cap_pairs, Wt, cam->tile_base, ek, ev);
         // 3. stable sort of the pairs by tile id
         uint32_t *ka = ek, *va = ev, *kb = (ek == tile_keys) ? w.kalt : tile_keys, *vb = (ev == vals) ? w.valt : vals;
         for (int p = 0; p < passes; p++) {

@@ -98,8 +98,14 @@ def check_view(g, o):
 
 
 def snapshot(br):
-    return [torch.cat([vb.image.reshape(-1).view(torch.int32), vb.n_contrib.reshape(-1), vb.vals[:1 << 16],
-                       vb.ranges.reshape(-1)]).clone() for vb in br.views] + [br.n_sel.clone()]
+    """Every output a batch defines: images, contributor counts, the sorted
+    values up to n_pairs (the rest of the buffer is never written), ranges."""
+    out = []
+    for vb in br.views:
+        n = int(vb.n_pairs.item())
+        out.append(torch.cat([vb.image.reshape(-1).view(torch.int32), vb.n_contrib.reshape(-1), vb.vals[:n],
+                              vb.ranges.reshape(-1), vb.n_pairs]).clone())
+    return out + [br.n_sel.clone()]
 
 
 def test_batched_renderer_parity_and_graph(dtree):
