@@ -58,6 +58,18 @@ def filter_bytes(tree, small_words, n_sel):
     return (4 * N + 41 * span + span // 8 + 12 * leaves_tested + N // 8 + 4 * n_sel), leaves_tested
 
 
+def sort_bytes(n_sel, n_vis, n_pairs, tile_passes, n_tiles):
+    """Algorithmic bytes of the sort stage: tile counts read twice per
+    selected splat (visibility count and pack); per tile-covering splat its
+    depth read, the packed (key, value) written, 4 radix passes of 20 B
+    (4 B histogram read, 8 B read and 8 B written by the scatter), the tile
+    count and index read for the scan (8 B) and index, count and rectangle
+    read for the emission (16 B); per pair 8 B emitted, 20 B per tile radix
+    pass and 4 B read for the ranges; 8 B of ranges per tile."""
+    return (8 * n_sel + n_vis * (4 + 8 + 4 * 20 + 8 + 16) + n_pairs * (8 + 20 * tile_passes + 4)
+            + 8 * n_tiles)
+
+
 def measure_fwd_bwd(torch):
     """Differentiable forward + backward of 2M raw Gaussians (SH degree 3) at
     1920x1080 against a seeded uniform target with an L1 loss: ms per view for
@@ -250,10 +262,12 @@ def main():
         s = stats.cpu().numpy().astype(np.float64)
         n_tiles = cams[k].n_tiles
         passes = int(np.ceil(max(1, int(n_tiles - 1).bit_length()) / 8))
-        sbytes = n_sel * (12 + 4 * 20 + 8 + 16) + n_pairs * (8 + 20 * passes + 4) + 8 * n_tiles
+        # splats that cover a tile: the only ones the depth sort and emission touch
+        n_vis = int(torch.count_nonzero(fb.splats.tiles[:min(n_sel, fb.cap_sel)]).item())
+        sbytes = sort_bytes(n_sel, n_vis, n_pairs, passes, n_tiles)
         pbytes = 292 * n_sel
         ops = OPS_EVAL * s[0] + OPS_EXP * s[1] + OPS_PASS * s[2] + OPS_BLEND * s[3]
-        counts.append(dict(n_sel=n_sel, n_pairs=n_pairs, leaves_tested=leaves_tested, frags_eval=int(s[0]),
+        counts.append(dict(n_sel=n_sel, n_vis=n_vis, n_pairs=n_pairs, leaves_tested=leaves_tested, frags_eval=int(s[0]),
                            frags_blended=int(s[3])))
         tot["filter"] += fbytes
         tot["preprocess"] += pbytes
@@ -306,7 +320,8 @@ def main():
         "config": {"workload": "city20m fly-through: 20,000,003-node LoD tree (17.5M leaves, 8 levels, SH3), "
                                "64 frames 1920x1080 at 40 m altitude, pitch -20 deg",
                    "tau_R": tau_R, "tau": tau, "lambda_G": synth.LAMBDA_G,
-                   "n_sel_mean": float(np.mean(cnt["n_sel"])), "n_pairs_mean": float(np.mean(cnt["n_pairs"])),
+                   "n_sel_mean": float(np.mean(cnt["n_sel"])), "n_vis_mean": float(np.mean(cnt["n_vis"])),
+                   "n_pairs_mean": float(np.mean(cnt["n_pairs"])),
                    "n_pairs_max": int(np.max(cnt["n_pairs"]))},
         "stage_ms": {n: dict(median=pct(st[n], 50), p95=pct(st[n], 95)) for n in stage_names},
         "frame_ms_events": dict(median=pct(frame_ms, 50), p95=pct(frame_ms, 95)),

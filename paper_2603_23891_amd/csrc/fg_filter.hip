@@ -33,10 +33,11 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRounds = 8;                    // nodes per thread in k_select
+constexpr int kRounds = 16;                   // nodes per thread in k_select
 constexpr int kTileNodes = kBlock * kRounds;  // nodes per k_select workgroup
 constexpr int kWaves = kBlock / fgd::kWave;
 constexpr int kMaxViews = 8;                  // views per pass over the tree
+static_assert((kRounds * kWaves) % 64 == 0, "group offsets are scanned 64 at a time");
 
 // look-back descriptor: state in bits 63..62 (0 none, 1 aggregate, 2 prefix), value in bits 31..0
 constexpr unsigned long long kAgg = 1ull << 62;
@@ -241,20 +242,25 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
     if (tid < fgd::kWave) {
         for (int v = 0; v < nv; v++) {
             unsigned long long* dv = desc + (int64_t)v * n_tiles;
-            // exclusive offsets of the (round, wave) groups in node order ...
+            // exclusive offsets of the (round, wave) groups in node order, a
+            // wave scan over 64 groups at a time ...
             uint32_t agg = 0;
-            if (tid == 0) {
-                uint32_t run = 0;
-                for (int i = 0; i < kRounds * kWaves; i++) {
-                    const uint32_t c = s_off[v][i];
-                    s_off[v][i] = run;
-                    run += c;
+            const int lane = fgd::lane_id();
+#pragma unroll
+            for (int g0 = 0; g0 < kRounds * kWaves; g0 += fgd::kWave) {
+                const uint32_t c = s_off[v][g0 + lane];
+                uint32_t x = c;
+#pragma unroll
+                for (int d = 1; d < fgd::kWave; d <<= 1) {
+                    const uint32_t y = __shfl_up(x, d, fgd::kWave);
+                    if (lane >= d) x += y;
                 }
-                agg = run;
+                s_off[v][g0 + lane] = agg + x - c;
+                agg += __shfl(x, fgd::kWave - 1, fgd::kWave);
+            }
+            if (tid == 0)
                 __hip_atomic_store(&dv[tile], (tile == 0 ? kPre : kAgg) | agg, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-            }
-            agg = __shfl(agg, 0, fgd::kWave);
             // ... then the look-back, 64 predecessors per step: lane i reads the
             // descriptor of tile j - i; the nearest "prefix" lane ends the walk
             // once no lane up to it is still unpublished.
@@ -262,7 +268,6 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
             if (tile > 0) {
                 int64_t j = tile - 1;
                 uint32_t spins = 0;
-                const int lane = fgd::lane_id();
                 for (;;) {
                     const int64_t idx = j - lane;
                     const unsigned long long d =

@@ -9,19 +9,21 @@
 // it. The blend therefore runs in two launches:
 //
 //   k_masks   every chunk of CHUNK splats of a "heavy" tile (more than CHUNK
-//             splats) is one work item: its splat records are staged in LDS
-//             and each splat marks, in per-pixel bit masks, the pixels where
-//             its alpha passes the skip tests (splat-parallel, see pass_masks);
-//             the masks go to global memory. All chunks run in parallel.
+//             splats) is one work item: per-pixel bit masks of the splats
+//             whose alpha passes the skip tests there go to global memory.
+//             All chunks run in parallel.
 //   k_render  one workgroup per tile (heavy tiles first, tiles claimed from an
 //             atomic ticket): one pixel per lane walks the tile's splats in
 //             list order, chunk by chunk, visiting only the marked ones and
-//             recomputing alpha with the same function, so every value and
+//             recomputing alpha with the same expressions, so every value and
 //             decision is bit-identical to one sequential pass. Light tiles
 //             compute their single chunk's masks in place.
 //
-// The launch boundary orders the mask writes before their reads; no
-// workgroup ever waits for another.
+// Masks are computed over the (splat, pixel) pairs inside a conservative box
+// per splat (the pixels where its skip test can pass), split evenly over the
+// threads, so few large splats and many small ones balance alike. The launch
+// boundary orders the mask writes before their reads; no workgroup ever
+// waits for another.
 #include "fg_device.h"
 
 namespace {
@@ -33,6 +35,10 @@ constexpr int kScanThreads = 256;
 // splat is skipped either way: testing this first avoids evaluating the
 // exponential without changing any result.
 constexpr float kSkipPower = -5.6f;
+
+// Light tiles with fewer splats than this balance their mask work over
+// (splat, pixel) pairs; larger ones give each thread whole splats.
+constexpr int kPairSplats = 128;
 
 struct RenderWs {
     uint32_t* nch;        // [n_tiles] chunks per tile
@@ -137,64 +143,198 @@ __global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __res
     }
 }
 
-// Stage splats [start, start + cnt) of the sorted list into LDS.
-__device__ __forceinline__ void stage(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
-                                      const float4* __restrict__ rgb_depth, const uint32_t* __restrict__ vals,
-                                      uint32_t start, int cnt, float2* s_xy, float4* s_co, float4* s_rgb)
-{
-    for (int j = threadIdx.x; j < cnt; j += kThreads) {
-        const uint32_t g = vals[start + j];
-        s_xy[j] = xy[g];
-        s_co[j] = conic_o[g];
-        if (s_rgb) s_rgb[j] = rgb_depth[g];
-    }
-}
+// Conservative box, in tile-relative pixel coordinates (inclusive), of the
+// pixels where a splat's power can reach -5.6: d^T Q d <= 11.2 has
+// half-widths sqrt(11.2 Sigma_xx) and sqrt(11.2 Sigma_yy) (Sigma = Q^-1),
+// widened here by 1% + 1 px and clipped to the tile and the image. Every pixel
+// outside it has power < -5.6 and is skipped by the test of Eq. (2) anyway.
+// Packed x0 | x1 << 8 | y0 << 16 | y1 << 24; kNoBox (x0 > x1) when empty.
+constexpr uint32_t kNoBox = 1u;
 
-// Splat-parallel skip tests: each lane takes one staged splat and tests only
-// the pixels of the tile inside a conservative box around its power >= -5.6
-// ellipse (d^T Q d <= 11.2, half-widths sqrt(11.2 Sigma_xx) and
-// sqrt(11.2 Sigma_yy) widened by 1% + 1 px); every pixel outside the box has
-// power < -5.6 and would be skipped by the same test. Inside the box the
-// tests are the per-pixel ones of Eq. (2), bit for bit. s_mask [word][pixel]
-// must be zero on entry.
-template <bool STATS>
-__device__ __forceinline__ void pass_masks(const float2* s_xy, const float4* s_co, int cnt, int tx, int ty, int W,
-                                           int H, uint32_t* s_mask, Frag& f)
+__device__ __forceinline__ uint32_t splat_box(float2 mm, float4 co, int tx, int ty, int W, int H)
 {
     const float tx0 = (float)(tx * fgd::kTile), ty0 = (float)(ty * fgd::kTile);
     const float tx1 = fminf(tx0 + 15.0f, (float)(W - 1)), ty1 = fminf(ty0 + 15.0f, (float)(H - 1));
+    float bx0 = tx0, bx1 = tx1, by0 = ty0, by1 = ty1;
+    const float qdet = co.x * co.z - co.y * co.y;
+    if (qdet > 0.0f) {
+        const float ex = sqrtf(11.2f * co.z / qdet) * 1.01f + 1.0f;
+        const float ey = sqrtf(11.2f * co.x / qdet) * 1.01f + 1.0f;
+        bx0 = fmaxf(bx0, floorf(mm.x - ex - 0.5f));
+        bx1 = fminf(bx1, ceilf(mm.x + ex - 0.5f));
+        by0 = fmaxf(by0, floorf(mm.y - ey - 0.5f));
+        by1 = fminf(by1, ceilf(mm.y + ey - 0.5f));
+    }
+    if (!(bx0 <= bx1 && by0 <= by1)) return kNoBox;
+    const uint32_t x0 = (uint32_t)((int)bx0 - tx * fgd::kTile), x1 = (uint32_t)((int)bx1 - tx * fgd::kTile);
+    const uint32_t y0 = (uint32_t)((int)by0 - ty * fgd::kTile), y1 = (uint32_t)((int)by1 - ty * fgd::kTile);
+    return x0 | (x1 << 8) | (y0 << 16) | (y1 << 24);
+}
+
+// Stage splats [start, start + cnt) of the sorted list into LDS, with their
+// boxes on this tile.
+__device__ __forceinline__ void stage(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
+                                      const float4* __restrict__ rgb_depth, const uint32_t* __restrict__ vals,
+                                      uint32_t start, int cnt, int tx, int ty, int W, int H, float2* s_xy,
+                                      float4* s_co, float4* s_rgb, uint32_t* s_box)
+{
     for (int j = threadIdx.x; j < cnt; j += kThreads) {
+        const uint32_t g = vals[start + j];
+        const float2 mm = xy[g];
+        const float4 co = conic_o[g];
+        s_xy[j] = mm;
+        s_co[j] = co;
+        if (s_rgb) s_rgb[j] = rgb_depth[g];
+        s_box[j] = splat_box(mm, co, tx, ty, W, H);
+    }
+}
+
+// The skip tests of Eq. (2) for one pixel inside the splat's box: false if
+// power > 0 or power < -5.6 (then alpha < 1/255 since opacity <= 1) or alpha
+// < 1/255; otherwise alpha = min(0.99, opacity exp(power)).
+template <bool STATS>
+__device__ __forceinline__ bool pixel_alpha(float2 mm, float4 co, float fpx, float fpy, float& alpha, Frag& f)
+{
+    const float dx = mm.x - fpx;
+    const float dy = mm.y - fpy;
+    const float power = -0.5f * ((co.x * dx) * dx + (co.z * dy) * dy) - (co.y * dx) * dy;
+    if (STATS) ++f.n_eval;
+    if (power > 0.0f || power < kSkipPower) return false;
+    if (STATS) ++f.n_exp;
+    float a = co.w * fgd::exp_neg_in_range(power);
+    a = a < 0.99f ? a : 0.99f;
+    if (a < 1.0f / 255.0f) return false;
+    if (STATS) ++f.n_pass;
+    alpha = a;
+    return true;
+}
+
+__device__ __forceinline__ uint32_t box_area(uint32_t b)
+{
+    const int x0 = (int)(b & 255u), x1 = (int)((b >> 8) & 255u);
+    const int y0 = (int)((b >> 16) & 255u), y1 = (int)(b >> 24);
+    return x0 <= x1 ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
+}
+
+// Exclusive prefix of the staged splats' box areas: s_pref[j] = sum of the
+// areas of splats [0, j), s_pref[cnt] = their total. One thread per S
+// consecutive splats; ends with a barrier.
+template <int CHUNK>
+__device__ __forceinline__ void area_prefix(const uint32_t* s_box, int cnt, uint32_t* s_pref, uint32_t* s_wave)
+{
+    constexpr int S = CHUNK / kThreads;
+    const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
+    uint32_t a[S], sum = 0;
+#pragma unroll
+    for (int k = 0; k < S; k++) {
+        const int j = tid * S + k;
+        a[k] = j < cnt ? box_area(s_box[j]) : 0u;
+        sum += a[k];
+    }
+    uint32_t x = sum;
+#pragma unroll
+    for (int d = 1; d < fgd::kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, fgd::kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == fgd::kWave - 1) s_wave[wave] = x;
+    __syncthreads();
+    uint32_t run = x - sum, total = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / fgd::kWave; w++) {
+        const uint32_t t = s_wave[w];
+        if (w < wave) run += t;
+        total += t;
+    }
+#pragma unroll
+    for (int k = 0; k < S; k++) {
+        const int j = tid * S + k;
+        if (j < cnt) s_pref[j] = run;
+        run += a[k];
+    }
+    if (tid == 0) s_pref[cnt] = total;
+    __syncthreads();
+}
+
+// Pass masks of the staged splats by (splat, pixel) pairs: the pairs inside
+// the splats' boxes, in splat order and rows then columns within a box, are
+// split into equal runs of consecutive pairs, one per thread, so a few large
+// splats and many small ones cost the same per thread. A pair that passes
+// the skip tests sets bit j of its pixel's mask word j/32 (s_mask
+// [word][pixel], zero on entry). Needs area_prefix first.
+template <bool STATS>
+__device__ __forceinline__ void pair_masks(const float2* s_xy, const float4* s_co, const uint32_t* s_box,
+                                           const uint32_t* s_pref, int cnt, int tx, int ty, uint32_t* s_mask,
+                                           Frag& f)
+{
+    const uint32_t total = s_pref[cnt];
+    const uint32_t per = (total + kThreads - 1) / kThreads;
+    uint32_t q = (uint32_t)threadIdx.x * per;
+    const uint32_t qend = q + per < total ? q + per : total;
+    if (q >= qend) return;
+    // the splat holding pair q: the last j with s_pref[j] <= q
+    int lo = 0, hi = cnt;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_pref[mid] <= q) lo = mid; else hi = mid;
+    }
+    int j = lo;
+    uint32_t b = s_box[j];
+    int x0 = (int)(b & 255u), x1 = (int)((b >> 8) & 255u), y0 = (int)((b >> 16) & 255u), y1 = (int)(b >> 24);
+    const uint32_t local = q - s_pref[j];
+    const int w0 = x1 - x0 + 1;
+    int ly = y0 + (int)(local / (uint32_t)w0), lx = x0 + (int)(local % (uint32_t)w0);
+    float2 mm = s_xy[j];
+    float4 co = s_co[j];
+    for (;;) {
+        float alpha;
+        if (pixel_alpha<STATS>(mm, co, (float)(tx * fgd::kTile + lx) + 0.5f, (float)(ty * fgd::kTile + ly) + 0.5f,
+                               alpha, f))
+            atomicOr(&s_mask[(j >> 5) * kThreads + ly * fgd::kTile + lx], 1u << (j & 31));
+        if (++q >= qend) break;
+        if (++lx > x1) {
+            lx = x0;
+            if (++ly > y1) {  // next splat with a non-empty box
+                do {
+                    ++j;
+                } while (s_pref[j + 1] == s_pref[j]);
+                b = s_box[j];
+                x0 = (int)(b & 255u);
+                x1 = (int)((b >> 8) & 255u);
+                y0 = (int)((b >> 16) & 255u);
+                y1 = (int)(b >> 24);
+                lx = x0;
+                ly = y0;
+                mm = s_xy[j];
+                co = s_co[j];
+            }
+        }
+    }
+}
+
+// Splat-parallel pass masks: each thread takes whole staged splats and tests
+// the pixels of its box (pixel_alpha), setting bit j of the pixel's mask word
+// j/32 (s_mask [word][pixel], zero on entry). Suits many small splats; a few
+// large ones are better served by pair_masks.
+template <bool STATS>
+__device__ __forceinline__ void splat_masks(const float2* s_xy, const float4* s_co, const uint32_t* s_box, int cnt,
+                                            int tx, int ty, uint32_t* s_mask, Frag& f)
+{
+    for (int j = threadIdx.x; j < cnt; j += kThreads) {
+        const uint32_t b = s_box[j];
+        const int x0 = (int)(b & 255u), x1 = (int)((b >> 8) & 255u);
+        const int y0 = (int)((b >> 16) & 255u), y1 = (int)(b >> 24);
+        if (x0 > x1) continue;
         const float2 mm = s_xy[j];
         const float4 co = s_co[j];
-        float bx0 = tx0, bx1 = tx1, by0 = ty0, by1 = ty1;
-        const float qdet = co.x * co.z - co.y * co.y;
-        if (qdet > 0.0f) {
-            const float ex = sqrtf(11.2f * co.z / qdet) * 1.01f + 1.0f;
-            const float ey = sqrtf(11.2f * co.x / qdet) * 1.01f + 1.0f;
-            bx0 = fmaxf(bx0, floorf(mm.x - ex - 0.5f));
-            bx1 = fminf(bx1, ceilf(mm.x + ex - 0.5f));
-            by0 = fmaxf(by0, floorf(mm.y - ey - 0.5f));
-            by1 = fminf(by1, ceilf(mm.y + ey - 0.5f));
-        }
-        if (!(bx0 <= bx1 && by0 <= by1)) continue;
-        const int ix0 = (int)bx0, ix1 = (int)bx1, iy0 = (int)by0, iy1 = (int)by1;
         const uint32_t bit = 1u << (j & 31);
         uint32_t* mrow = s_mask + (j >> 5) * kThreads;
-        for (int py = iy0; py <= iy1; py++) {
-            const float fy = (float)py + 0.5f;
-            for (int px = ix0; px <= ix1; px++) {
-                const float fx = (float)px + 0.5f;
-                const float dx = mm.x - fx;
-                const float dy = mm.y - fy;
-                const float power = -0.5f * ((co.x * dx) * dx + (co.z * dy) * dy) - (co.y * dx) * dy;
-                if (STATS) ++f.n_eval;
-                if (power > 0.0f || power < kSkipPower) continue;
-                if (STATS) ++f.n_exp;
-                float alpha = co.w * fgd::exp_neg(power);
-                alpha = alpha < 0.99f ? alpha : 0.99f;
-                if (alpha < 1.0f / 255.0f) continue;
-                if (STATS) ++f.n_pass;
-                atomicOr(&mrow[(py - ty * fgd::kTile) * fgd::kTile + (px - tx * fgd::kTile)], bit);
+        for (int ly = y0; ly <= y1; ly++) {
+            const float fy = (float)(ty * fgd::kTile + ly) + 0.5f;
+            for (int lx = x0; lx <= x1; lx++) {
+                float alpha;
+                if (pixel_alpha<STATS>(mm, co, (float)(tx * fgd::kTile + lx) + 0.5f, fy, alpha, f))
+                    atomicOr(&mrow[ly * fgd::kTile + lx], bit);
             }
         }
     }
@@ -214,6 +354,9 @@ __device__ __forceinline__ void flush_stats(const Frag& f, unsigned long long* f
     }
 }
 
+// Pass masks of the chunks of heavy tiles, one chunk per work item (their
+// splats are mostly small: splat-parallel); masks go to global memory
+// [word][pixel].
 template <int CHUNK, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_masks(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
                                                     const uint32_t* __restrict__ vals,
@@ -223,8 +366,10 @@ __global__ __launch_bounds__(kThreads) void k_masks(const float2* __restrict__ x
     constexpr int kWords = CHUNK / 32;
     __shared__ float2 s_xy[CHUNK];
     __shared__ float4 s_co[CHUNK];
+    __shared__ uint32_t s_box[CHUNK];
     __shared__ uint32_t s_mask[kWords * kThreads];
     Frag f = {0, 0, 0, 0};
+    const int tid = threadIdx.x;
     const uint32_t n_items = ws.counters[2];
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const uint32_t tile = ws.mitem[item];
@@ -232,20 +377,23 @@ __global__ __launch_bounds__(kThreads) void k_masks(const float2* __restrict__ x
         const uint32_t r0 = ranges[2 * tile], r1 = ranges[2 * tile + 1];
         const uint32_t start = r0 + chunk * CHUNK;
         const int cnt = (int)(r1 - start < (uint32_t)CHUNK ? r1 - start : (uint32_t)CHUNK);
-        for (int i = threadIdx.x; i < kWords * kThreads; i += kThreads) s_mask[i] = 0u;
-        stage(xy, conic_o, nullptr, vals, start, cnt, s_xy, s_co, nullptr);
+        const int tx = (int)(tile % (uint32_t)Wt), ty = (int)(tile / (uint32_t)Wt);
+#pragma unroll
+        for (int w = 0; w < kWords; w++) s_mask[w * kThreads + tid] = 0u;
+        stage(xy, conic_o, nullptr, vals, start, cnt, tx, ty, W, H, s_xy, s_co, nullptr, s_box);
         __syncthreads();
-        pass_masks<STATS>(s_xy, s_co, cnt, (int)(tile % (uint32_t)Wt), (int)(tile / (uint32_t)Wt), W, H, s_mask, f);
+        splat_masks<STATS>(s_xy, s_co, s_box, cnt, tx, ty, s_mask, f);
         __syncthreads();
         uint32_t* out = ws.masks + (size_t)item * (kWords * kThreads);
-        for (int i = threadIdx.x; i < kWords * kThreads; i += kThreads) out[i] = s_mask[i];
+#pragma unroll
+        for (int w = 0; w < kWords; w++) out[w * kThreads + tid] = s_mask[w * kThreads + tid];
         __syncthreads();
     }
     flush_stats<STATS, 3>(f, frag_stats);
 }
 
 // alpha of a fragment that passed the skip tests (so -5.6 <= power <= 0):
-// the same expressions as pass_masks, hence the same value.
+// the same expressions as pixel_alpha, hence the same value.
 __device__ __forceinline__ float passed_alpha(float2 mm, float4 co, float fpx, float fpy)
 {
     const float dx = mm.x - fpx;
@@ -367,6 +515,10 @@ __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ xy, const
             R.xy[k] = xy[g[k]];
             R.co[k] = conic_o[g[k]];
             R.rgb[k] = rgb_depth[g[k]];
+        } else {
+            R.xy[k] = make_float2(0.0f, 0.0f);
+            R.co[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            R.rgb[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
     }
     if (mf + chunk < n_mask_items) {
@@ -394,8 +546,13 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
     __shared__ float4 s_co[CHUNK];
     __shared__ float4 s_rgb[CHUNK];
     __shared__ uint32_t s_mask[kWords * kThreads];
+    __shared__ uint32_t s_box[CHUNK];
+    __shared__ uint32_t s_pref[CHUNK + 1];
+    __shared__ uint32_t s_wave[kThreads / fgd::kWave];
+    __shared__ uint32_t s_done[kThreads / fgd::kWave];
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
+    const int lx = tid % fgd::kTile, ly = tid / fgd::kTile;
     const uint32_t n_mask_items = ws.counters[2];
     Frag f = {0, 0, 0, 0};
     if (tid == 0) s_item = atomicAdd(&ws.counters[0], 1u);
@@ -414,8 +571,8 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
         if (tid == 0 && nch <= 1) next_item = atomicAdd(&ws.counters[0], 1u);
         const uint32_t mf = nch > 1 ? ws.mfirst[tile] : 0u;
         const int tx = (int)(tile % (uint32_t)Wt), ty = (int)(tile / (uint32_t)Wt);
-        const int px = tx * fgd::kTile + (tid % fgd::kTile);
-        const int py = ty * fgd::kTile + (tid / fgd::kTile);
+        const int px = tx * fgd::kTile + lx;
+        const int py = ty * fgd::kTile + ly;
         const bool inside = px < W && py < H;
         const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
         PixelState p = {1.0f, 0.0f, 0.0f, 0.0f, 0u, !inside};
@@ -424,9 +581,14 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
             const int cnt = (int)(r1 - r0);
 #pragma unroll
             for (int w = 0; w < kWords; w++) s_mask[w * kThreads + tid] = 0u;
-            stage(xy, conic_o, rgb_depth, vals, r0, cnt, s_xy, s_co, s_rgb);
+            stage(xy, conic_o, rgb_depth, vals, r0, cnt, tx, ty, W, H, s_xy, s_co, s_rgb, s_box);
             __syncthreads();
-            pass_masks<STATS>(s_xy, s_co, cnt, tx, ty, W, H, s_mask, f);
+            if (cnt < kPairSplats) {
+                area_prefix<CHUNK>(s_box, cnt, s_pref, s_wave);
+                pair_masks<STATS>(s_xy, s_co, s_box, s_pref, cnt, tx, ty, s_mask, f);
+            } else {
+                splat_masks<STATS>(s_xy, s_co, s_box, cnt, tx, ty, s_mask, f);
+            }
             __syncthreads();
             walk<CHUNK, STATS>(s_mask + tid, s_xy, s_co, s_rgb, fpx, fpy, 0u, p, f);
         } else {
@@ -443,8 +605,12 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
             }
             for (uint32_t chunk = 0; chunk < nch; chunk++) {
                 // a workgroup stops once every pixel of the tile has terminated
-                if (__syncthreads_count(p.done) == kThreads) break;
+                const bool wave_done = __ballot(!p.done) == 0ull;  // the whole wave votes
+                if (fgd::lane_id() == 0) s_done[tid / fgd::kWave] = wave_done ? 1u : 0u;
+                __syncthreads();
+                if (s_done[0] & s_done[1] & s_done[2] & s_done[3]) break;
                 const int cnt = chunk_count<CHUNK>(r0, r1, chunk);
+                const bool stored = mf + chunk < n_mask_items;
 #pragma unroll
                 for (int k = 0; k < ChunkRegs<CHUNK>::S; k++) {
                     const int j = k * kThreads + tid;
@@ -452,9 +618,11 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
                         s_xy[j] = R.xy[k];
                         s_co[j] = R.co[k];
                         s_rgb[j] = R.rgb[k];
+                        if (!stored) s_box[j] = splat_box(R.xy[k], R.co[k], tx, ty, W, H);
                     }
                 }
-                // every lane reads only its own pixel's mask words (column tid)
+                // every lane writes only its own pixel's mask words (column tid);
+                // zero where the masks are computed here
 #pragma unroll
                 for (int w = 0; w < kWords; w++) s_mask[w * kThreads + tid] = R.m[w];
                 __syncthreads();
@@ -463,8 +631,8 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
                                        R);
                     if (chunk + 2 < nch) fetch_vals<CHUNK>(vals, r0, r1, chunk + 2, gnext);
                 }
-                if (mf + chunk >= n_mask_items) {  // beyond the mask store: masks computed here
-                    pass_masks<STATS>(s_xy, s_co, cnt, tx, ty, W, H, s_mask, f);
+                if (!stored) {  // beyond the mask store: masks computed here
+                    splat_masks<STATS>(s_xy, s_co, s_box, cnt, tx, ty, s_mask, f);
                     __syncthreads();
                 }
                 walk<CHUNK, STATS>(s_mask + tid, s_xy, s_co, s_rgb, fpx, fpy, chunk * CHUNK, p, f);
