@@ -409,63 +409,75 @@ struct PixelState {
     bool done;
 };
 
-// One blend step of Eq. (2) in list order: stop before a splat that would take
-// T below 1e-4, otherwise accumulate its colour and attenuate T.
+// One blend step of Eq. (2) in list order, for a lane whose step is valid
+// and whose pixel has not stopped: stop before a splat that would take T
+// below 1e-4, otherwise accumulate its colour and attenuate T. Written with
+// selects rather than branches (the kept values are the same expressions),
+// so the four steps of a group run without divergent control flow.
 template <bool STATS>
-__device__ __forceinline__ void blend_step(PixelState& p, float alpha, float4 c, uint32_t pos, Frag& f)
+__device__ __forceinline__ void blend_step(PixelState& p, bool valid, float alpha, float4 c, uint32_t pos, Frag& f)
 {
     const float Tn = p.T * (1.0f - alpha);
-    if (Tn < 1e-4f) {
-        p.done = true;
-        return;
-    }
-    p.C0 = p.C0 + (c.x * alpha) * p.T;
-    p.C1 = p.C1 + (c.y * alpha) * p.T;
-    p.C2 = p.C2 + (c.z * alpha) * p.T;
-    p.T = Tn;
-    p.last = pos + 1u;
-    if (STATS) ++f.n_blend;
+    const bool live = valid && !p.done;
+    const bool stop = Tn < 1e-4f;
+    const bool take = live && !stop;
+    const float n0 = p.C0 + (c.x * alpha) * p.T;
+    const float n1 = p.C1 + (c.y * alpha) * p.T;
+    const float n2 = p.C2 + (c.z * alpha) * p.T;
+    p.C0 = take ? n0 : p.C0;
+    p.C1 = take ? n1 : p.C1;
+    p.C2 = take ? n2 : p.C2;
+    p.T = take ? Tn : p.T;
+    p.last = take ? pos + 1u : p.last;
+    p.done = p.done || (live && stop);
+    if (STATS) f.n_blend += take ? 1u : 0u;
 }
 
 // Walks the marked splats of one staged chunk for this lane's pixel. mcol
-// points at the pixel's first mask word (words kThreads apart). Up to four
-// marked splats of one 64-splat mask word are taken at a time and their
-// alphas (independent of T) computed together, so their LDS reads and
-// arithmetic overlap; the blend steps then run strictly in list order.
+// points at the pixel's first mask word (words kThreads apart). A summary
+// bit per 64-splat pair of words, read first, sends the lane straight to the
+// non-empty words. Up to four marked splats of one such word are taken at a
+// time and their alphas (independent of T) computed together, so their LDS
+// reads and arithmetic overlap; the blend steps then run strictly in list
+// order.
 template <int CHUNK, bool STATS>
 __device__ __forceinline__ void walk(const uint32_t* mcol, const float2* s_xy, const float4* s_co,
                                      const float4* s_rgb, float fpx, float fpy, uint32_t base, PixelState& p,
                                      Frag& f)
 {
     constexpr int kPairs = CHUNK / 64;
-    int w = -1;
-    unsigned long long m = 0ull;
-    while (!p.done) {
-        while (m == 0ull && ++w < kPairs)
-            m = (unsigned long long)mcol[(2 * w) * kThreads] |
-                ((unsigned long long)mcol[(2 * w + 1) * kThreads] << 32);
-        if (m == 0ull) break;
-        const int b = w << 6;
-        const int j0 = b + __builtin_ctzll(m);
-        m &= m - 1ull;
-        const bool v1 = m != 0ull;
-        const int j1 = v1 ? b + __builtin_ctzll(m) : j0;
-        m &= m - 1ull;
-        const bool v2 = m != 0ull;
-        const int j2 = v2 ? b + __builtin_ctzll(m) : j0;
-        m &= m - 1ull;
-        const bool v3 = m != 0ull;
-        const int j3 = v3 ? b + __builtin_ctzll(m) : j0;
-        m &= m - 1ull;
-        const float a0 = passed_alpha(s_xy[j0], s_co[j0], fpx, fpy);
-        const float a1 = passed_alpha(s_xy[j1], s_co[j1], fpx, fpy);
-        const float a2 = passed_alpha(s_xy[j2], s_co[j2], fpx, fpy);
-        const float a3 = passed_alpha(s_xy[j3], s_co[j3], fpx, fpy);
-        const float4 c0 = s_rgb[j0], c1 = s_rgb[j1], c2 = s_rgb[j2], c3 = s_rgb[j3];
-        blend_step<STATS>(p, a0, c0, base + (uint32_t)j0, f);
-        if (v1 && !p.done) blend_step<STATS>(p, a1, c1, base + (uint32_t)j1, f);
-        if (v2 && !p.done) blend_step<STATS>(p, a2, c2, base + (uint32_t)j2, f);
-        if (v3 && !p.done) blend_step<STATS>(p, a3, c3, base + (uint32_t)j3, f);
+    uint32_t summary = 0;
+#pragma unroll
+    for (int k = 0; k < kPairs; k++)
+        summary |= ((mcol[(2 * k) * kThreads] | mcol[(2 * k + 1) * kThreads]) != 0u ? 1u : 0u) << k;
+    while (summary != 0u && !p.done) {
+        const int k = __builtin_ctz(summary);
+        summary &= summary - 1u;
+        unsigned long long m = (unsigned long long)mcol[(2 * k) * kThreads] |
+                               ((unsigned long long)mcol[(2 * k + 1) * kThreads] << 32);
+        const int b = k << 6;
+        while (m != 0ull && !p.done) {
+            const int j0 = b + __builtin_ctzll(m);
+            m &= m - 1ull;
+            const bool v1 = m != 0ull;
+            const int j1 = v1 ? b + __builtin_ctzll(m) : j0;
+            m &= m - 1ull;
+            const bool v2 = m != 0ull;
+            const int j2 = v2 ? b + __builtin_ctzll(m) : j0;
+            m &= m - 1ull;
+            const bool v3 = m != 0ull;
+            const int j3 = v3 ? b + __builtin_ctzll(m) : j0;
+            m &= m - 1ull;
+            const float a0 = passed_alpha(s_xy[j0], s_co[j0], fpx, fpy);
+            const float a1 = passed_alpha(s_xy[j1], s_co[j1], fpx, fpy);
+            const float a2 = passed_alpha(s_xy[j2], s_co[j2], fpx, fpy);
+            const float a3 = passed_alpha(s_xy[j3], s_co[j3], fpx, fpy);
+            const float4 c0 = s_rgb[j0], c1 = s_rgb[j1], c2 = s_rgb[j2], c3 = s_rgb[j3];
+            blend_step<STATS>(p, true, a0, c0, base + (uint32_t)j0, f);
+            blend_step<STATS>(p, v1, a1, c1, base + (uint32_t)j1, f);
+            blend_step<STATS>(p, v2, a2, c2, base + (uint32_t)j2, f);
+            blend_step<STATS>(p, v3, a3, c3, base + (uint32_t)j3, f);
+        }
     }
 }
 
