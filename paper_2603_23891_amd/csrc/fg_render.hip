@@ -29,7 +29,7 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kScanThreads = 256;
+constexpr int kScanThreads = 1024;
 
 // exp(power) <= exp(-5.6) < 1/255 for power < -5.6, so with opacity <= 1 the
 // splat is skipped either way: testing this first avoids evaluating the

@@ -38,6 +38,7 @@ constexpr int kTileItems = kThreads * kIPT;  // 2048
 constexpr int kWaves = kThreads / fgd::kWave;
 constexpr int kEmitIPT = 8;
 constexpr int kEmitItems = kThreads * kEmitIPT;  // 2048
+constexpr int kEmitRun = 8;                       // consecutive pairs per thread
 
 __device__ __forceinline__ int64_t count_of(const uint32_t* p, int64_t cap)
 {
@@ -372,22 +373,39 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
         }
         if (tid == 0) s_off[kEmitItems] = total;
         __syncthreads();
-        for (uint32_t o = tid; o < total; o += kThreads) {
-            // last splat k with s_off[k] <= o (splats with no tile share
-            // their successor's offset and are passed over)
+        // runs of kEmitRun consecutive outputs per thread: one binary search
+        // per run (the last splat k with s_off[k] <= o; splats with no tile
+        // share their successor's offset and are passed over), then step
+        // through the rectangle, rows then columns
+        for (uint32_t o0 = (uint32_t)tid * kEmitRun; o0 < total; o0 += (uint32_t)kThreads * kEmitRun) {
             int lo = 0, hi = kEmitItems;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                if (s_off[mid] <= o) lo = mid; else hi = mid;
+                if (s_off[mid] <= o0) lo = mid; else hi = mid;
             }
-            const ushort4 q = s_rect[lo];
-            const uint32_t w = (uint32_t)(q.z - q.x);
-            const uint32_t local = o - s_off[lo];
-            const uint32_t ty = q.y + local / w, tx = q.x + local % w;
-            const unsigned long long dst = base + o;
-            if (dst < (unsigned long long)cap_pairs) {
-                keys[dst] = tile_base + ty * (uint32_t)Wt + tx;
-                vals[dst] = s_g[lo];
+            ushort4 q = s_rect[lo];
+            uint32_t w = (uint32_t)(q.z - q.x);
+            const uint32_t local = o0 - s_off[lo];
+            uint32_t ty = q.y + local / w, tx = q.x + local % w;
+            const int n = total - o0 < (uint32_t)kEmitRun ? (int)(total - o0) : kEmitRun;
+            for (int r = 0; r < n; r++) {
+                const unsigned long long dst = base + o0 + (uint32_t)r;
+                if (dst < (unsigned long long)cap_pairs) {
+                    keys[dst] = tile_base + ty * (uint32_t)Wt + tx;
+                    vals[dst] = s_g[lo];
+                }
+                if (r + 1 < n && ++tx == q.z) {
+                    tx = q.x;
+                    if (++ty == q.w) {  // next splat with a tile (one exists: r + 1 < n)
+                        do {
+                            ++lo;
+                        } while (s_off[lo + 1] == s_off[lo]);
+                        q = s_rect[lo];
+                        w = (uint32_t)(q.z - q.x);
+                        tx = q.x;
+                        ty = q.y;
+                    }
+                }
             }
         }
         __syncthreads();
