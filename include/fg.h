@@ -221,10 +221,12 @@ size_t fg_render_workspace_size(const fg_camera* cam, int64_t cap_pairs, const f
  * parallel (a first launch writes per-pixel pass masks); the transmittance
  * chain still runs in list order, so results are those of one sequential
  * pass.
- * frag_stats: NULL, or 4 device counters that the call adds to (the caller
+ * frag_stats: NULL, or 8 device counters that the call adds to (the caller
  * zeroes them): [0] (pixel, splat) tests evaluated, [1] tests that reach the
  * exponential (-5.6 <= power <= 0), [2] tests with alpha >= 1/255, [3] splats
- * blended. Results do not depend on whether counting is on.
+ * blended, counted in the blend kernel; [4..6] the same three test counts
+ * made by the mask kernel for chunks of long ranges ([7] stays 0). Results do
+ * not depend on whether counting is on.
  * status is reserved (not written). Errors: FG_ERR_INVALID_ARG,
  * FG_ERR_WORKSPACE. */
 int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
@@ -287,6 +289,19 @@ int fg_render_backward(const fg_params* p, const fg_camera* cam, const float bg[
 
 /* Text for an FG_* return code. */
 const char* fg_status_string(int code);
+
+/* ---- measurement hooks -------------------------------------------------- */
+
+/* Timing of the blend kernel. fg_timing(1) clears the record and makes each
+ * later fg_render call record a HIP event pair around its blend kernel
+ * (k_render) on that call's stream, up to 4096 calls; fg_timing(0) stops
+ * recording. Events are created on first use (not per call) and kept until
+ * the process ends. Do not enable during stream capture.
+ * fg_timing_read waits for the last recorded event and returns the summed
+ * durations in milliseconds and the number of calls recorded since
+ * fg_timing(1). Errors: FG_ERR_HIP. */
+int fg_timing(int enable);
+int fg_timing_read(double* total_ms, int32_t* count);
 
 #ifdef __cplusplus
 }

@@ -67,7 +67,7 @@ class FgTune(C.Structure):
 
 EXPORTS = ["fg_filter_workspace_size", "fg_filter", "fg_preprocess", "fg_sort_workspace_size", "fg_sort",
            "fg_render_workspace_size", "fg_render", "fg_activate", "fg_render_backward_workspace_size",
-           "fg_render_backward", "fg_status_string"]
+           "fg_render_backward", "fg_status_string", "fg_timing", "fg_timing_read"]
 
 _lib = None
 
@@ -102,6 +102,10 @@ def lib():
         L.fg_render_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
         L.fg_status_string.restype = C.c_char_p
         L.fg_status_string.argtypes = [i32]
+        L.fg_timing.restype = i32
+        L.fg_timing.argtypes = [i32]
+        L.fg_timing_read.restype = i32
+        L.fg_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         _lib = L
     return _lib
 
@@ -344,3 +348,14 @@ def fg_render_backward(prm: FgParams, cam, bg, sel_idx, n_sel, cap_sel: int, spl
                                     _ref(ss), _p(vals), _p(ranges), _p(final_T), _p(n_contrib), _p(dL_dimage),
                                     _ref(grads), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
            "fg_render_backward")
+
+
+def fg_timing(enable: bool):
+    _check(lib().fg_timing(1 if enable else 0), "fg_timing")
+
+
+def fg_timing_read():
+    """(summed blend-kernel milliseconds, number of timed fg_render calls)."""
+    ms, n = C.c_double(0.0), C.c_int32(0)
+    _check(lib().fg_timing_read(C.byref(ms), C.byref(n)), "fg_timing_read")
+    return ms.value, int(n.value)

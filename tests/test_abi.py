@@ -1,0 +1,98 @@
+"""The C-ABI boundary without a GPU: libfg.so loads, exports every function
+include/fg.h declares (and the binding lists exactly those), and its host-only
+paths behave as documented: status strings, workspace sizes, argument
+rejection before any device work, and the timing hooks with nothing recorded.
+No kernel is launched here.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2603_23891_amd import fg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fg.h")
+
+FG_OK, FG_ERR_INVALID_ARG, FG_ERR_UNSUPPORTED, FG_ERR_WORKSPACE = 0, -1, -3, -4
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fg_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return fg.lib()
+
+
+def test_header_declares_the_path_entry_points():
+    names = declared_functions()
+    for n in ("fg_filter", "fg_preprocess", "fg_sort", "fg_render", "fg_activate", "fg_render_backward"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_lists_exactly_the_declared_symbols():
+    assert sorted(fg.EXPORTS) == declared_functions()
+
+
+def test_status_strings(lib):
+    for code, text in [(0, b"ok"), (-1, b"invalid argument"), (-4, b"workspace too small"), (99, b"unknown status")]:
+        assert lib.fg_status_string(code) == text
+
+
+def cam_1080p(tile_base=0):
+    class Cam:
+        R = np.eye(3, dtype=np.float32).reshape(9)
+        t = np.zeros(3, np.float32)
+        campos = np.zeros(3, np.float32)
+        fx = fy = 1662.8
+        cx, cy = 960.0, 540.0
+        width, height = 1920, 1080
+        znear, kx, ky = 0.2, 1.3, 1.3
+    Cam.tile_base = tile_base
+    return Cam
+
+
+def test_workspace_sizes_are_monotone_and_reject_bad_sizes():
+    a = fg.fg_filter_workspace_size(1000, 100, 1)
+    b = fg.fg_filter_workspace_size(100000, 10000, 1)
+    c = fg.fg_filter_workspace_size(100000, 10000, 8)
+    assert 0 < a < b < c
+    cam = cam_1080p()
+    s1 = fg.fg_sort_workspace_size(1000, 5000, cam)
+    s2 = fg.fg_sort_workspace_size(100000, 500000, cam)
+    assert 0 < s1 < s2
+    assert fg.fg_sort_workspace_size(-1, 5, cam) == 0
+    r = [fg.fg_render_workspace_size(cam, 1 << 20, fg.tune_struct(k)) for k in (256, 512, 1024)]
+    assert all(x > 0 for x in r)
+    assert fg.fg_render_workspace_size(cam, -1) == 0
+    assert fg.lib().fg_render_backward_workspace_size(1000) >= 1000 * 9 * 4
+
+
+def test_entry_points_reject_missing_arguments_on_the_host(lib):
+    cam = fg.camera_struct(cam_1080p())
+    # null inputs are refused before any device work
+    assert lib.fg_filter(None, None, 1, C.c_float(3.0), None, None, 0, None, None, None, 0, None) == FG_ERR_INVALID_ARG
+    assert lib.fg_preprocess(None, C.byref(cam), C.c_float(0.0), None, None, 0, None, None, None) == FG_ERR_INVALID_ARG
+    assert lib.fg_sort(None, None, 0, C.byref(cam), None, None, 0, None, None, None, None, 0, None,
+                       None) == FG_ERR_INVALID_ARG
+    bg = (C.c_float * 3)(0.0, 0.0, 0.0)
+    assert lib.fg_render(None, None, None, C.byref(cam), C.cast(bg, C.c_void_p), None, None, None, 0, None, None,
+                         None, 0, None, None) == FG_ERR_INVALID_ARG
+
+
+def test_timing_hooks_with_nothing_recorded(lib):
+    ms, n = C.c_double(-1.0), C.c_int32(-1)
+    assert lib.fg_timing_read(C.byref(ms), C.byref(n)) == FG_OK
+    assert n.value == 0 and ms.value == 0.0
+    assert lib.fg_timing_read(None, None) == FG_ERR_INVALID_ARG
