@@ -270,7 +270,9 @@ def main():
         # splats that cover a tile: the only ones the depth sort and emission touch
         n_vis = int(torch.count_nonzero(fb.splats.tiles[:min(n_sel, fb.cap_sel)]).item())
         sbytes = sort_bytes(n_sel, n_vis, n_pairs, passes, n_tiles)
-        pbytes = 292 * n_sel
+        # per selected node: index, mean, scale, quaternion, opacity read (48 B)
+        # and the splat record written (52 B); SH (192 B) only where it reaches a tile
+        pbytes = 100 * n_sel + 192 * n_vis
         # counters [0..3]: blend kernel (tests, exponentials, passes, blends);
         # [4..6]: the mask kernel's tests for chunks of long ranges
         blend_ops = OPS_EVAL * s[0] + OPS_EXP * s[1] + OPS_PASS * s[2] + OPS_BLEND * s[3]

@@ -346,21 +346,6 @@ static void preprocess_one(const fgo_tree* t, const fgo_camera* c, float tau, in
     o->opacity = op;
     float lam = lambda_max(a, b, cc);
     o->lambda = lam;
-    /* view-dependent colour: 0.5 + sum_k sh_k Y_k(d), clamped below at 0 */
-    float dx = mx - c->campos[0], dy = my - c->campos[1], dz = mz - c->campos[2];
-    float len = sqrtf((dx * dx + dy * dy) + dz * dz);
-    float Y[16];
-    sh_basis(t->sh_degree, dx / len, dy / len, dz / len, Y);
-    int K = (t->sh_degree + 1) * (t->sh_degree + 1);
-    const float* sh = t->sh + (size_t)g * (size_t)K * 3;
-    float rgb[3];
-    for (int ch = 0; ch < 3; ch++) {
-        float acc = Y[0] * sh[ch];
-        for (int k = 1; k < K; k++) acc = acc + Y[k] * sh[k * 3 + ch];
-        acc = acc + 0.5f;
-        rgb[ch] = acc < 0.0f ? 0.0f : acc;
-    }
-    o->r = rgb[0]; o->g = rgb[1]; o->b = rgb[2];
     /* radius: 3 sigma, shrunk by the opacity threshold tau */
     float r3 = 3.0f * sqrtf(lam);
     float r;
@@ -391,6 +376,23 @@ static void preprocess_one(const fgo_tree* t, const fgo_camera* c, float tau, in
     o->x0 = (int32_t)x0; o->x1 = (int32_t)x1;
     o->y0 = (int32_t)y0; o->y1 = (int32_t)y1;
     o->tiles = (uint32_t)((o->x1 - o->x0) * (o->y1 - o->y0));
+    /* view-dependent colour, only for a splat that reaches a tile (one that
+       reaches none is never blended; its colour stays 0):
+       0.5 + sum_k sh_k Y_k(d), clamped below at 0 */
+    float dx = mx - c->campos[0], dy = my - c->campos[1], dz = mz - c->campos[2];
+    float len = sqrtf((dx * dx + dy * dy) + dz * dz);
+    float Y[16];
+    sh_basis(t->sh_degree, dx / len, dy / len, dz / len, Y);
+    int K = (t->sh_degree + 1) * (t->sh_degree + 1);
+    const float* sh = t->sh + (size_t)g * (size_t)K * 3;
+    float rgb[3];
+    for (int ch = 0; ch < 3; ch++) {
+        float acc = Y[0] * sh[ch];
+        for (int k = 1; k < K; k++) acc = acc + Y[k] * sh[k * 3 + ch];
+        acc = acc + 0.5f;
+        rgb[ch] = acc < 0.0f ? 0.0f : acc;
+    }
+    o->r = rgb[0]; o->g = rgb[1]; o->b = rgb[2];
 }
 
 void fgo_preprocess(const fgo_tree* t, const fgo_camera* c, float tau, const uint32_t* sel_idx, int64_t n_sel,

@@ -72,34 +72,6 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(fg_tree tree, fgd::Cam ca
             xyo.y = (cam.fy * y) / z + cam.cy;
             rgbd.w = z;
             const float lam = fgd::lambda_max(a, b, c);
-            // view-dependent colour
-            const float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
-            const float len = sqrtf((dx * dx + dy * dy) + dz * dz);
-            float Y[16];
-            sh_basis<D>(dx / len, dy / len, dz / len, Y);
-            const float* shp = tree.sh + (size_t)g * (K * 3);
-            float coef[K * 3];
-            if constexpr ((K * 3) % 4 == 0) {
-                const float4* s4 = reinterpret_cast<const float4*>(shp);
-#pragma unroll
-                for (int k = 0; k < K * 3 / 4; k++) {
-                    const float4 v = s4[k];
-                    coef[4 * k] = v.x; coef[4 * k + 1] = v.y; coef[4 * k + 2] = v.z; coef[4 * k + 3] = v.w;
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < K * 3; k++) coef[k] = shp[k];
-            }
-            float rgb[3];
-#pragma unroll
-            for (int ch = 0; ch < 3; ch++) {
-                float acc = Y[0] * coef[ch];
-#pragma unroll
-                for (int k = 1; k < K; k++) acc = acc + Y[k] * coef[k * 3 + ch];
-                acc = acc + 0.5f;
-                rgb[ch] = acc < 0.0f ? 0.0f : acc;
-            }
-            rgbd.x = rgb[0]; rgbd.y = rgb[1]; rgbd.z = rgb[2];
             // tile-set radius: 3 sigma, shrunk where alpha decays to tau
             const float r3 = 3.0f * sqrtf(lam);
             float r;
@@ -129,6 +101,37 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(fg_tree tree, fgd::Cam ca
                                         (unsigned short)y1);
                     tiles = (uint32_t)((x1 - x0) * (y1 - y0));
                 }
+            }
+            if (tiles != 0u) {
+                // view-dependent colour, only for a splat that reaches a tile (one
+                // that reaches none is never blended; its colour stays 0)
+                const float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
+                const float len = sqrtf((dx * dx + dy * dy) + dz * dz);
+                float Y[16];
+                sh_basis<D>(dx / len, dy / len, dz / len, Y);
+                const float* shp = tree.sh + (size_t)g * (K * 3);
+                float coef[K * 3];
+                if constexpr ((K * 3) % 4 == 0) {
+                    const float4* s4 = reinterpret_cast<const float4*>(shp);
+#pragma unroll
+                    for (int k = 0; k < K * 3 / 4; k++) {
+                        const float4 v = s4[k];
+                        coef[4 * k] = v.x; coef[4 * k + 1] = v.y; coef[4 * k + 2] = v.z; coef[4 * k + 3] = v.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < K * 3; k++) coef[k] = shp[k];
+                }
+                float rgb[3];
+#pragma unroll
+                for (int ch = 0; ch < 3; ch++) {
+                    float acc = Y[0] * coef[ch];
+#pragma unroll
+                    for (int k = 1; k < K; k++) acc = acc + Y[k] * coef[k * 3 + ch];
+                    acc = acc + 0.5f;
+                    rgb[ch] = acc < 0.0f ? 0.0f : acc;
+                }
+                rgbd.x = rgb[0]; rgbd.y = rgb[1]; rgbd.z = rgb[2];
             }
         }
         reinterpret_cast<float2*>(out.xy)[i] = make_float2(xyo.x, xyo.y);

@@ -175,3 +175,23 @@ def test_pair_count_monotone_in_tau():
               for tau in [0.0, 1 / 255, 0.01, 0.03, 0.1, 0.3, 0.9]]
     assert all(a >= b for a, b in zip(counts, counts[1:])), counts
     assert counts[-1] < counts[0]
+
+
+def test_colour_only_for_splats_that_reach_a_tile():
+    """A splat whose shrunk extent is empty (opacity <= tau: r = 0) emits no
+    pair and is never blended; its colour is not evaluated (stays 0) while
+    its 2D mean, conic, opacity and depth are still set. With tau below the
+    opacity the same splat reaches tiles and gets its degree-0 colour."""
+    cam = synth.tiny_camera(25)
+    rgb = np.array([[0.2, 0.6, 0.9]])
+    sh = ((rgb - 0.5) / synth.Y00)[:, None, :]
+    tree = flat_tree([[0, 0, 0]], [[0.1] * 3], [[1, 0, 0, 0]], [0.3], sh)
+    off = oracle.preprocess(tree, cam, 0.5, np.array([0], np.uint32))[0]
+    assert off["tiles"] == 0 and off["radius"] == 0.0
+    assert off["r"] == 0.0 and off["g"] == 0.0 and off["b"] == 0.0
+    assert off["A"] > 0 and off["C"] > 0 and off["opacity"] == np.float32(0.3) and off["depth"] > 0
+    on = oracle.preprocess(tree, cam, 0.1, np.array([0], np.uint32))[0]
+    assert on["tiles"] > 0
+    assert np.abs(np.array([on["r"], on["g"], on["b"]]) - rgb[0]).max() < 1e-6
+    for k in ("u", "v", "A", "B", "C", "depth"):
+        assert on[k] == off[k]
