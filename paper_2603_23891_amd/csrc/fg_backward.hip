@@ -11,9 +11,11 @@
 //                  skip tests as in the forward (recomputed bit for bit), so
 //                  no per-splat alphas are stored: the transmittance before
 //                  splat k is recovered as T_k = T_{k+1} / (1 - alpha_k) from
-//                  the stored final T. Per splat, the gradients w.r.t. its 2D
-//                  mean, conic, opacity and colour are summed over the wave
-//                  (shuffles) and added with one atomic per wave.
+//                  the stored final T. A conservative box per splat (pixels
+//                  where its power can reach -5.6) lets a wave pass over
+//                  splats that miss its rows. Per splat, the gradients w.r.t.
+//                  its 2D mean, conic, opacity and colour are summed over the
+//                  wave (DPP permutes) and added with one atomic per value.
 //   k_project_bwd  one thread per selected Gaussian: the chain from those
 //                  splat gradients to the raw parameters (SH coefficients, the
 //                  mean through the 2D mean, the Jacobian and the view
@@ -47,11 +49,25 @@ __global__ void k_zero(float* __restrict__ p, int64_t n)
         p[i] = 0.0f;
 }
 
+// Sum over the 64 lanes, returned in every lane: DPP quad and row permutes
+// give each row of 16 lanes its sum, four lane reads add the rows.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
 __device__ __forceinline__ float wave_sum(float v)
 {
-#pragma unroll
-    for (int d = fgd::kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, fgd::kWave);
-    return v;
+    v = v + dpp_mov<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v = v + dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v = v + dpp_mov<0x141>(v);  // row_half_mirror
+    v = v + dpp_mov<0x140>(v);  // row_mirror
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
 }
 
 __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restrict__ xy,
@@ -69,12 +85,16 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
     __shared__ float4 s_co[kBatch];
     __shared__ float4 s_rgb[kBatch];
     __shared__ uint32_t s_g[kBatch];
+    __shared__ uint32_t s_box[kBatch];
     __shared__ uint32_t s_max;
     const int tile = blockIdx.x;
     const int tid = threadIdx.x;
     const int tx = tile % Wt, ty = tile / Wt;
-    const int px = tx * fgd::kTile + (tid % fgd::kTile);
-    const int py = ty * fgd::kTile + (tid / fgd::kTile);
+    const int lx = tid % fgd::kTile, ly = tid / fgd::kTile;
+    const int lane = fgd::lane_id();
+    const int wy0 = (tid / fgd::kWave) * (fgd::kWave / fgd::kTile);  // first pixel row of this wave
+    const int px = tx * fgd::kTile + lx;
+    const int py = ty * fgd::kTile + ly;
     const bool inside = px < W && py < H;
     const uint32_t r0 = ranges[2 * tile];
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
@@ -100,16 +120,30 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
         if (tid < cnt) {
             const uint32_t g = vals[r0 + begin + tid];
             s_g[tid] = g;
-            s_xy[tid] = xy[g];
-            s_co[tid] = conic_o[g];
+            const float2 mm = xy[g];
+            const float4 co = conic_o[g];
+            s_xy[tid] = mm;
+            s_co[tid] = co;
             s_rgb[tid] = rgb_depth[g];
+            s_box[tid] = fgd::splat_box(mm, co, tx, ty, W, H);
         }
         __syncthreads();
+        uint32_t boxes = fgd::kNoBox;  // lane l: box of splat (window base) + l
         for (int jj = cnt - 1; jj >= 0; jj--) {
+            // boxes are read 64 at a time, one per lane, and tested as scalars:
+            // a splat whose box misses the wave's rows is passed over (every
+            // pixel outside the box has power < -5.6, so it blended nowhere there)
+            const int wbase = jj & ~(fgd::kWave - 1);
+            if (jj == cnt - 1 || (jj & (fgd::kWave - 1)) == fgd::kWave - 1)
+                boxes = wbase + lane < cnt ? s_box[wbase + lane] : fgd::kNoBox;
+            const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)boxes, jj - wbase);
+            const int bx0 = (int)(b & 255u), bx1 = (int)((b >> 8) & 255u);
+            const int by0 = (int)((b >> 16) & 255u), by1 = (int)(b >> 24);
+            if (bx0 > bx1 || by1 < wy0 || by0 > wy0 + 3) continue;
             const uint32_t pos = (uint32_t)(begin + jj);
             float gr[kNG] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             bool hit = false;
-            if (pos < last) {
+            if (pos < last && lx >= bx0 && lx <= bx1 && ly >= by0 && ly <= by1) {
                 const float2 m = s_xy[jj];
                 const float4 co = s_co[jj];
                 const float dx = m.x - fpx;
@@ -151,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
 #pragma unroll
                 for (int k = 0; k < kNG; k++) {
                     const float v = wave_sum(gr[k]);
-                    if (fgd::lane_id() == 0 && v != 0.0f) atomicAdd(&dst[k], v);
+                    if (lane == k && v != 0.0f) atomicAdd(&dst[k], v);
                 }
             }
         }

@@ -143,33 +143,8 @@ __global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __res
     }
 }
 
-// Conservative box, in tile-relative pixel coordinates (inclusive), of the
-// pixels where a splat's power can reach -5.6: d^T Q d <= 11.2 has
-// half-widths sqrt(11.2 Sigma_xx) and sqrt(11.2 Sigma_yy) (Sigma = Q^-1),
-// widened here by 1% + 1 px and clipped to the tile and the image. Every pixel
-// outside it has power < -5.6 and is skipped by the test of Eq. (2) anyway.
-// Packed x0 | x1 << 8 | y0 << 16 | y1 << 24; kNoBox (x0 > x1) when empty.
-constexpr uint32_t kNoBox = 1u;
-
-__device__ __forceinline__ uint32_t splat_box(float2 mm, float4 co, int tx, int ty, int W, int H)
-{
-    const float tx0 = (float)(tx * fgd::kTile), ty0 = (float)(ty * fgd::kTile);
-    const float tx1 = fminf(tx0 + 15.0f, (float)(W - 1)), ty1 = fminf(ty0 + 15.0f, (float)(H - 1));
-    float bx0 = tx0, bx1 = tx1, by0 = ty0, by1 = ty1;
-    const float qdet = co.x * co.z - co.y * co.y;
-    if (qdet > 0.0f) {
-        const float ex = sqrtf(11.2f * co.z / qdet) * 1.01f + 1.0f;
-        const float ey = sqrtf(11.2f * co.x / qdet) * 1.01f + 1.0f;
-        bx0 = fmaxf(bx0, floorf(mm.x - ex - 0.5f));
-        bx1 = fminf(bx1, ceilf(mm.x + ex - 0.5f));
-        by0 = fmaxf(by0, floorf(mm.y - ey - 0.5f));
-        by1 = fminf(by1, ceilf(mm.y + ey - 0.5f));
-    }
-    if (!(bx0 <= bx1 && by0 <= by1)) return kNoBox;
-    const uint32_t x0 = (uint32_t)((int)bx0 - tx * fgd::kTile), x1 = (uint32_t)((int)bx1 - tx * fgd::kTile);
-    const uint32_t y0 = (uint32_t)((int)by0 - ty * fgd::kTile), y1 = (uint32_t)((int)by1 - ty * fgd::kTile);
-    return x0 | (x1 << 8) | (y0 << 16) | (y1 << 24);
-}
+using fgd::kNoBox;
+using fgd::splat_box;
 
 // Stage splats [start, start + cnt) of the sorted list into LDS, with their
 // boxes on this tile.
