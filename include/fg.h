@@ -95,7 +95,8 @@ typedef struct fg_tree {
     const float* scale;      /* [3][N] linear (activated) scales */
     const float* quat;       /* [4][N] rotation (w, x, y, z), any non-zero norm */
     const float* opacity;    /* [N] activated opacity; nodes outside (0, 1] emit nothing */
-    const float* sh;         /* [N][(D+1)^2][3] coefficient-major, RGB-minor */
+    const float* sh;         /* [N][(D+1)^2][3] coefficient-major, RGB-minor;
+                                16-byte aligned (read 16 bytes at a time) */
     const int32_t* parent;   /* [N] parent index (< own index), -1 for a root */
     const uint8_t* flags;    /* [N] bit 0: leaf. Read only for index < n_internal_span */
 } fg_tree;
@@ -246,7 +247,7 @@ typedef struct fg_params {
     const float* log_scale;  /* [3][M] */
     const float* quat;       /* [4][M] (w, x, y, z), any non-zero norm */
     const float* logit;      /* [M] */
-    const float* sh;         /* [M][(D+1)^2][3] */
+    const float* sh;         /* [M][(D+1)^2][3], 16-byte aligned */
 } fg_params;
 
 /* Gradients of a scalar loss w.r.t. the raw parameters, same shapes as
@@ -256,7 +257,7 @@ typedef struct fg_grads {
     float* log_scale;
     float* quat;
     float* logit;
-    float* sh;
+    float* sh;               /* 16-byte aligned */
 } fg_grads;
 
 /* scale [3][M] = exp(log_scale), opacity [M] = 1 / (1 + exp(-logit)), with the

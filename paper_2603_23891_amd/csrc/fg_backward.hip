@@ -282,16 +282,47 @@ __global__ __launch_bounds__(256) void k_project_bwd(fg_params prm, fgd::Cam cam
         const float dir[3] = {dx0 / len, dy0 / len, dz0 / len};
         float Yb[16], dY[48];
         sh_basis_and_grad<D>(dir[0], dir[1], dir[2], Yb, dY);
+        // the K x 3 coefficients are read once and the gradients written in
+        // memory order, 16 bytes at a time where K x 3 is a multiple of 4
         const float* sh = prm.sh + (size_t)g * (K * 3);
-        float dd[3] = {0.f, 0.f, 0.f};
+        float* dsh = out.sh + (size_t)g * (K * 3);
+        float coef[K * 3];
+        if constexpr ((K * 3) % 4 == 0) {
+            const float4* s4 = reinterpret_cast<const float4*>(sh);
+#pragma unroll
+            for (int q = 0; q < K * 3 / 4; q++) {
+                const float4 v = s4[q];
+                coef[4 * q] = v.x; coef[4 * q + 1] = v.y; coef[4 * q + 2] = v.z; coef[4 * q + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < K * 3; q++) coef[q] = sh[q];
+        }
+        float grv[3];
+#pragma unroll
         for (int ch = 0; ch < 3; ch++) {
             float acc = 0.5f;
-            for (int k = 0; k < K; k++) acc += Yb[k] * sh[k * 3 + ch];
-            const float gr = acc < 0.0f ? 0.0f : grgb[ch];
-            for (int k = 0; k < K; k++) {
-                out.sh[((size_t)g * K + k) * 3 + ch] = gr * Yb[k];
-                for (int a = 0; a < 3; a++) dd[a] += gr * sh[k * 3 + ch] * dY[k * 3 + a];
-            }
+#pragma unroll
+            for (int k = 0; k < K; k++) acc += Yb[k] * coef[k * 3 + ch];
+            grv[ch] = acc < 0.0f ? 0.0f : grgb[ch];
+        }
+        if constexpr ((K * 3) % 4 == 0) {
+            float4* d4 = reinterpret_cast<float4*>(dsh);
+#pragma unroll
+            for (int q = 0; q < K * 3 / 4; q++)
+                d4[q] = make_float4(grv[(4 * q) % 3] * Yb[(4 * q) / 3], grv[(4 * q + 1) % 3] * Yb[(4 * q + 1) / 3],
+                                    grv[(4 * q + 2) % 3] * Yb[(4 * q + 2) / 3], grv[(4 * q + 3) % 3] * Yb[(4 * q + 3) / 3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < K * 3; q++) dsh[q] = grv[q % 3] * Yb[q / 3];
+        }
+        float dd[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) {
+#pragma unroll
+            for (int k = 0; k < K; k++)
+#pragma unroll
+                for (int a = 0; a < 3; a++) dd[a] += grv[ch] * coef[k * 3 + ch] * dY[k * 3 + a];
         }
         const float ddot = dd[0] * dir[0] + dd[1] * dir[1] + dd[2] * dir[2];
         for (int a = 0; a < 3; a++) dmu[a] += (dd[a] - dir[a] * ddot) / len;
