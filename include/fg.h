@@ -133,7 +133,10 @@ typedef struct fg_splats {
 typedef struct fg_tune {
     int32_t render_batch;  /* splats per blend work item (chunk): 256, 512 or 1024 (default 512) */
     int32_t radix_bits;    /* digit width of the pair sort: 4..8 (default 8) */
-    int32_t reserved0;
+    int32_t save_state;    /* 1: fg_render keeps, for every chunk of a long range, each pixel's
+                              (T, C) after that chunk in its workspace (sized for it by
+                              fg_render_workspace_size with the same tune), which
+                              fg_render_backward reads; 0: not kept (default) */
     int32_t reserved1;
 } fg_tune;
 
@@ -281,12 +284,20 @@ size_t fg_render_backward_workspace_size(int64_t cap_sel);
  * opacity or position; the tile rectangle and shrink radius are piecewise
  * constant and pass none. Gradients are summed with float32 atomics, so the
  * summation order (and the last bits) vary between runs.
+ * image, render_ws (render_ws_bytes), cap_pairs, tune: that frame's image and
+ * the workspace, pair capacity and tune its fg_render call used. When tune
+ * has save_state, the chunks of long ranges are walked in parallel, each
+ * from the state the forward kept after it (T, and the colour behind as image
+ * minus the colour accumulated so far); otherwise, or if render_ws or image is
+ * NULL, every tile is walked whole from final_T.
  * Errors: FG_ERR_INVALID_ARG, FG_ERR_UNSUPPORTED (sh_degree > 3),
  * FG_ERR_WORKSPACE. */
 int fg_render_backward(const fg_params* p, const fg_camera* cam, const float bg[3], const uint32_t* sel_idx,
                        const uint32_t* n_sel, int64_t cap_sel, const fg_splats* splats, const uint32_t* vals,
                        const uint32_t* ranges, const float* final_T, const uint32_t* n_contrib,
-                       const float* dL_dimage, const fg_grads* out, void* ws, size_t ws_bytes, void* stream);
+                       const float* image, const void* render_ws, size_t render_ws_bytes, int64_t cap_pairs,
+                       const fg_tune* tune, const float* dL_dimage, const fg_grads* out, void* ws,
+                       size_t ws_bytes, void* stream);
 
 /* Text for an FG_* return code. */
 const char* fg_status_string(int code);

@@ -4,24 +4,30 @@
 //   k_activate     scale = exp(log_scale), opacity = 1 / (1 + exp(-logit)),
 //                  with the library's exponential (so the CPU reference sees
 //                  the same activated values).
-//   k_render_bwd   one workgroup per 16x16 tile, one pixel per lane, walking
-//                  the tile's splats back to front from the last contributor.
-//                  A splat was blended by a pixel exactly when its position is
+//   k_render_bwd   one pixel per lane, walking splats back to front. A
+//                  splat was blended by a pixel exactly when its position is
 //                  below the pixel's contributor count and it passes the same
 //                  skip tests as in the forward (recomputed bit for bit), so
 //                  no per-splat alphas are stored: the transmittance before
-//                  splat k is recovered as T_k = T_{k+1} / (1 - alpha_k) from
-//                  the stored final T. A conservative box per splat (pixels
-//                  where its power can reach -5.6) lets a wave pass over
-//                  splats that miss its rows. Per splat, the gradients w.r.t.
-//                  its 2D mean, conic, opacity and colour are summed over the
-//                  wave (DPP permutes) and added with one atomic per value.
+//                  splat k is recovered as T_k = T_{k+1} / (1 - alpha_k).
+//                  Work items are whole tiles (walked from the final T) and,
+//                  when the forward saved its per-chunk state, the chunks of
+//                  long ranges, each walked from the (T, colour) the forward
+//                  had after that chunk, so a long range no longer runs on
+//                  one workgroup. A conservative box per splat (pixels where
+//                  its power can reach -5.6) lets a wave pass over splats
+//                  that miss its rows. Per splat, the gradients w.r.t. its 2D
+//                  mean, conic, opacity and colour are summed over the wave
+//                  (DPP permutes) and added with one atomic per value.
 //   k_project_bwd  one thread per selected Gaussian: the chain from those
 //                  splat gradients to the raw parameters (SH coefficients, the
 //                  mean through the 2D mean, the Jacobian and the view
 //                  direction, log-scales and the rotation through its
 //                  normalisation, opacity logits).
 #include "fg_device.h"
+#include "fg_render_ws.h"
+
+#include <cstdint>
 
 namespace {
 
@@ -70,15 +76,27 @@ __device__ __forceinline__ float wave_sum(float v)
     return (r0 + r1) + (r2 + r3);
 }
 
+// Chunk items of long ranges (from the forward's saved state) and whole
+// tiles; see the header comment.
+struct BwdView {
+    const uint32_t* nch;
+    const uint32_t* mfirst;
+    const uint32_t* mitem;
+    const uint32_t* n_items;  // device count of chunk items; null: no saved state
+    const float* state;
+    int chunk;
+};
+
 __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restrict__ xy,
                                                          const float4* __restrict__ conic_o,
                                                          const float4* __restrict__ rgb_depth,
                                                          const uint32_t* __restrict__ vals,
                                                          const uint32_t* __restrict__ ranges, int W, int H, int Wt,
-                                                         float bg0, float bg1, float bg2,
+                                                         int64_t n_tiles, float bg0, float bg1, float bg2,
                                                          const float* __restrict__ final_T,
                                                          const uint32_t* __restrict__ n_contrib,
-                                                         const float* __restrict__ dL_dimage,
+                                                         const float* __restrict__ image,
+                                                         const float* __restrict__ dL_dimage, BwdView view,
                                                          float* __restrict__ gacc)
 {
     __shared__ float2 s_xy[kBatch];
@@ -87,105 +105,141 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
     __shared__ uint32_t s_g[kBatch];
     __shared__ uint32_t s_box[kBatch];
     __shared__ uint32_t s_max;
-    const int tile = blockIdx.x;
     const int tid = threadIdx.x;
-    const int tx = tile % Wt, ty = tile / Wt;
     const int lx = tid % fgd::kTile, ly = tid / fgd::kTile;
     const int lane = fgd::lane_id();
     const int wy0 = (tid / fgd::kWave) * (fgd::kWave / fgd::kTile);  // first pixel row of this wave
-    const int px = tx * fgd::kTile + lx;
-    const int py = ty * fgd::kTile + ly;
-    const bool inside = px < W && py < H;
-    const uint32_t r0 = ranges[2 * tile];
-    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
-    const size_t o = (size_t)py * W + px, plane = (size_t)W * H;
-    const uint32_t last = inside ? n_contrib[o] : 0u;
-    float T = inside ? final_T[o] : 1.0f;
-    float G0 = 0.f, G1 = 0.f, G2 = 0.f;
-    if (inside) {
-        G0 = dL_dimage[o];
-        G1 = dL_dimage[plane + o];
-        G2 = dL_dimage[2 * plane + o];
-    }
-    float S0 = T * bg0, S1 = T * bg1, S2 = T * bg2;  // colour behind the current splat
-    if (tid == 0) s_max = 0u;
-    __syncthreads();
-    atomicMax(&s_max, last);
-    __syncthreads();
-    const uint32_t n = s_max;  // positions [0, n) of the range hold every blended splat
-    for (int64_t end = n; end > 0; end -= kBatch) {
-        const int64_t begin = end - kBatch > 0 ? end - kBatch : 0;
-        const int cnt = (int)(end - begin);
-        __syncthreads();
-        if (tid < cnt) {
-            const uint32_t g = vals[r0 + begin + tid];
-            s_g[tid] = g;
-            const float2 mm = xy[g];
-            const float4 co = conic_o[g];
-            s_xy[tid] = mm;
-            s_co[tid] = co;
-            s_rgb[tid] = rgb_depth[g];
-            s_box[tid] = fgd::splat_box(mm, co, tx, ty, W, H);
+    const size_t plane = (size_t)W * H;
+    const int64_t n_chunk_items = view.n_items ? (int64_t)*view.n_items : 0;
+    for (int64_t item = blockIdx.x; item < n_chunk_items + n_tiles; item += gridDim.x) {
+        // work item: a chunk of a long range, or a whole tile
+        uint32_t tile;
+        int64_t lo = 0, hi_cap;
+        int64_t citem = -1;
+        if (item < n_chunk_items) {
+            tile = view.mitem[item];
+            const uint32_t nch = view.nch[tile];
+            if ((int64_t)view.mfirst[tile] + nch > n_chunk_items) continue;  // tile item walks it whole
+            lo = (int64_t)(item - view.mfirst[tile]) * view.chunk;
+            hi_cap = lo + view.chunk;
+            citem = item;
+        } else {
+            tile = (uint32_t)(item - n_chunk_items);
+            if (view.n_items && view.nch[tile] > 1 &&
+                (int64_t)view.mfirst[tile] + view.nch[tile] <= n_chunk_items)
+                continue;  // walked by its chunk items
+            hi_cap = INT64_MAX;
         }
+        const int tx = (int)(tile % (uint32_t)Wt), ty = (int)(tile / (uint32_t)Wt);
+        const int px = tx * fgd::kTile + lx;
+        const int py = ty * fgd::kTile + ly;
+        const bool inside = px < W && py < H;
+        const uint32_t r0 = ranges[2 * tile];
+        const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+        const size_t o = (size_t)py * W + px;
+        const uint32_t last = inside ? n_contrib[o] : 0u;
+        float G0 = 0.f, G1 = 0.f, G2 = 0.f;
+        if (inside) {
+            G0 = dL_dimage[o];
+            G1 = dL_dimage[plane + o];
+            G2 = dL_dimage[2 * plane + o];
+        }
+        // T after the walked span and the colour behind it (later splats and
+        // background): from final_T for a whole tile, from the state saved
+        // after the chunk (colour behind = image - colour accumulated so far)
+        float T, S0, S1, S2;
+        if (citem < 0) {
+            T = inside ? final_T[o] : 1.0f;
+            S0 = T * bg0; S1 = T * bg1; S2 = T * bg2;
+        } else {
+            const float* st = view.state + (size_t)citem * (4 * kThreads);
+            T = st[tid];
+            S0 = inside ? image[o] - st[kThreads + tid] : 0.0f;
+            S1 = inside ? image[plane + o] - st[2 * kThreads + tid] : 0.0f;
+            S2 = inside ? image[2 * plane + o] - st[3 * kThreads + tid] : 0.0f;
+        }
+        __syncthreads();  // LDS of the previous item
+        if (tid == 0) s_max = 0u;
         __syncthreads();
-        uint32_t boxes = fgd::kNoBox;  // lane l: box of splat (window base) + l
-        for (int jj = cnt - 1; jj >= 0; jj--) {
-            // boxes are read 64 at a time, one per lane, and tested as scalars:
-            // a splat whose box misses the wave's rows is passed over (every
-            // pixel outside the box has power < -5.6, so it blended nowhere there)
-            const int wbase = jj & ~(fgd::kWave - 1);
-            if (jj == cnt - 1 || (jj & (fgd::kWave - 1)) == fgd::kWave - 1)
-                boxes = wbase + lane < cnt ? s_box[wbase + lane] : fgd::kNoBox;
-            const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)boxes, jj - wbase);
-            const int bx0 = (int)(b & 255u), bx1 = (int)((b >> 8) & 255u);
-            const int by0 = (int)((b >> 16) & 255u), by1 = (int)(b >> 24);
-            if (bx0 > bx1 || by1 < wy0 || by0 > wy0 + 3) continue;
-            const uint32_t pos = (uint32_t)(begin + jj);
-            float gr[kNG] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            bool hit = false;
-            if (pos < last && lx >= bx0 && lx <= bx1 && ly >= by0 && ly <= by1) {
-                const float2 m = s_xy[jj];
-                const float4 co = s_co[jj];
-                const float dx = m.x - fpx;
-                const float dy = m.y - fpy;
-                const float power = -0.5f * ((co.x * dx) * dx + (co.z * dy) * dy) - (co.y * dx) * dy;
-                if (!(power > 0.0f || power < kSkipPower)) {
-                    const float e = fgd::exp_neg(power);
-                    const float araw = co.w * e;
-                    const float alpha = araw < 0.99f ? araw : 0.99f;
-                    if (alpha >= 1.0f / 255.0f) {
-                        hit = true;
-                        const float4 c = s_rgb[jj];
-                        const float one_m = 1.0f - alpha;
-                        const float Tk = T / one_m;
-                        const float w = alpha * Tk;
-                        gr[6] = G0 * w;
-                        gr[7] = G1 * w;
-                        gr[8] = G2 * w;
-                        const float dLda = (G0 * (c.x * Tk - S0 / one_m) + G1 * (c.y * Tk - S1 / one_m)) +
-                                           G2 * (c.z * Tk - S2 / one_m);
-                        S0 = S0 + c.x * w;
-                        S1 = S1 + c.y * w;
-                        S2 = S2 + c.z * w;
-                        T = Tk;
-                        if (araw < 0.99f) {
-                            const float dLdp = dLda * alpha;
-                            gr[5] = dLda * e;
-                            gr[0] = dLdp * (-(co.x * dx + co.y * dy));
-                            gr[1] = dLdp * (-(co.z * dy + co.y * dx));
-                            gr[2] = dLdp * (-0.5f * (dx * dx));
-                            gr[3] = dLdp * (-(dx * dy));
-                            gr[4] = dLdp * (-0.5f * (dy * dy));
+        atomicMax(&s_max, last);
+        __syncthreads();
+        // positions [0, s_max) of the range hold every blended splat
+        const int64_t hi = hi_cap < (int64_t)s_max ? hi_cap : (int64_t)s_max;
+        for (int64_t end = hi; end > lo; end -= kBatch) {
+            const int64_t begin = end - kBatch > lo ? end - kBatch : lo;
+            const int cnt = (int)(end - begin);
+            __syncthreads();
+            if (tid < cnt) {
+                const uint32_t g = vals[r0 + begin + tid];
+                s_g[tid] = g;
+                const float2 mm = xy[g];
+                const float4 co = conic_o[g];
+                s_xy[tid] = mm;
+                s_co[tid] = co;
+                s_rgb[tid] = rgb_depth[g];
+                s_box[tid] = fgd::splat_box(mm, co, tx, ty, W, H);
+            }
+            __syncthreads();
+            uint32_t boxes = fgd::kNoBox;  // lane l: box of splat (window base) + l
+            for (int jj = cnt - 1; jj >= 0; jj--) {
+                // boxes are read 64 at a time, one per lane, and tested as
+                // scalars: a splat whose box misses the wave's rows is passed
+                // over (every pixel outside the box has power < -5.6, so it
+                // blended nowhere there)
+                const int wbase = jj & ~(fgd::kWave - 1);
+                if (jj == cnt - 1 || (jj & (fgd::kWave - 1)) == fgd::kWave - 1)
+                    boxes = wbase + lane < cnt ? s_box[wbase + lane] : fgd::kNoBox;
+                const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)boxes, jj - wbase);
+                const int bx0 = (int)(b & 255u), bx1 = (int)((b >> 8) & 255u);
+                const int by0 = (int)((b >> 16) & 255u), by1 = (int)(b >> 24);
+                if (bx0 > bx1 || by1 < wy0 || by0 > wy0 + 3) continue;
+                const uint32_t pos = (uint32_t)(begin + jj);
+                float gr[kNG] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                bool hit = false;
+                if (pos < last && lx >= bx0 && lx <= bx1 && ly >= by0 && ly <= by1) {
+                    const float2 m = s_xy[jj];
+                    const float4 co = s_co[jj];
+                    const float dx = m.x - fpx;
+                    const float dy = m.y - fpy;
+                    const float power = -0.5f * ((co.x * dx) * dx + (co.z * dy) * dy) - (co.y * dx) * dy;
+                    if (!(power > 0.0f || power < kSkipPower)) {
+                        const float e = fgd::exp_neg(power);
+                        const float araw = co.w * e;
+                        const float alpha = araw < 0.99f ? araw : 0.99f;
+                        if (alpha >= 1.0f / 255.0f) {
+                            hit = true;
+                            const float4 c = s_rgb[jj];
+                            const float one_m = 1.0f - alpha;
+                            const float Tk = T / one_m;
+                            const float w = alpha * Tk;
+                            gr[6] = G0 * w;
+                            gr[7] = G1 * w;
+                            gr[8] = G2 * w;
+                            const float dLda = (G0 * (c.x * Tk - S0 / one_m) + G1 * (c.y * Tk - S1 / one_m)) +
+                                               G2 * (c.z * Tk - S2 / one_m);
+                            S0 = S0 + c.x * w;
+                            S1 = S1 + c.y * w;
+                            S2 = S2 + c.z * w;
+                            T = Tk;
+                            if (araw < 0.99f) {
+                                const float dLdp = dLda * alpha;
+                                gr[5] = dLda * e;
+                                gr[0] = dLdp * (-(co.x * dx + co.y * dy));
+                                gr[1] = dLdp * (-(co.z * dy + co.y * dx));
+                                gr[2] = dLdp * (-0.5f * (dx * dx));
+                                gr[3] = dLdp * (-(dx * dy));
+                                gr[4] = dLdp * (-0.5f * (dy * dy));
+                            }
                         }
                     }
                 }
-            }
-            if (__ballot(hit)) {
-                float* dst = gacc + (size_t)s_g[jj] * kNG;
+                if (__ballot(hit)) {
+                    float* dst = gacc + (size_t)s_g[jj] * kNG;
 #pragma unroll
-                for (int k = 0; k < kNG; k++) {
-                    const float v = wave_sum(gr[k]);
-                    if (lane == k && v != 0.0f) atomicAdd(&dst[k], v);
+                    for (int k = 0; k < kNG; k++) {
+                        const float v = wave_sum(gr[k]);
+                        if (lane == k && v != 0.0f) atomicAdd(&dst[k], v);
+                    }
                 }
             }
         }
@@ -415,8 +469,10 @@ extern "C" size_t fg_render_backward_workspace_size(int64_t cap_sel)
 extern "C" int fg_render_backward(const fg_params* p, const fg_camera* cam, const float bg[3], const uint32_t* sel_idx,
                                   const uint32_t* n_sel, int64_t cap_sel, const fg_splats* splats,
                                   const uint32_t* vals, const uint32_t* ranges, const float* final_T,
-                                  const uint32_t* n_contrib, const float* dL_dimage, const fg_grads* out, void* ws,
-                                  size_t ws_bytes, void* stream)
+                                  const uint32_t* n_contrib, const float* image, const void* render_ws,
+                                  size_t render_ws_bytes, int64_t cap_pairs, const fg_tune* tune,
+                                  const float* dL_dimage, const fg_grads* out, void* ws, size_t ws_bytes,
+                                  void* stream)
 {
     if (!p || !cam || !bg || !n_sel || !splats || !ranges || !final_T || !n_contrib || !dL_dimage || !out ||
         cap_sel < 0)
@@ -438,9 +494,17 @@ extern "C" int fg_render_backward(const fg_params* p, const fg_camera* cam, cons
     hipLaunchKernelGGL(k_zero, dim3(zb), dim3(256), 0, s, out->sh, (int64_t)K * 3 * m);
     if (cap_sel == 0 || m == 0) return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
     const int Wt = (cam->width + 15) / 16, Ht = (cam->height + 15) / 16;
-    hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)(Wt * Ht)), dim3(kThreads), 0, s, (const float2*)splats->xy,
+    const int64_t n_tiles = (int64_t)Wt * Ht;
+    BwdView view = {nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+    fgr::RenderWsView rv;
+    if (image && fgr::render_ws_view(render_ws, render_ws_bytes, cam, cap_pairs, tune, &rv))
+        view = {rv.nch, rv.mfirst, rv.mitem, rv.counters, rv.state, rv.chunk};
+    int64_t gb = n_tiles + (view.n_items ? rv.max_items : 0);
+    if (gb > 8192) gb = 8192;
+    hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)gb), dim3(kThreads), 0, s, (const float2*)splats->xy,
                        (const float4*)splats->conic_o, (const float4*)splats->rgb_depth, vals, ranges, cam->width,
-                       cam->height, Wt, bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimage, gacc);
+                       cam->height, Wt, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib, image, dL_dimage, view,
+                       gacc);
     const fgd::Cam c = fgd::make_cam(*cam);
     int64_t blocks = (cap_sel + 255) / 256;
     if (blocks > 4096) blocks = 4096;

@@ -25,6 +25,7 @@
 // boundary orders the mask writes before their reads; no workgroup ever
 // waits for another.
 #include "fg_device.h"
+#include "fg_render_ws.h"
 
 namespace {
 
@@ -47,6 +48,7 @@ struct RenderWs {
     uint32_t* mitem;      // [max_mask_items] mask item -> tile
     uint32_t* counters;   // [0] ticket, [1] heavy tiles, [2] mask items (clamped)
     uint32_t* masks;      // [max_mask_items][CHUNK/32][256]
+    float* state;         // with save_state: [max_mask_items][4][256] T, C0, C1, C2 after each chunk; else null
 };
 
 struct Frag {
@@ -623,6 +625,13 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
                     __syncthreads();
                 }
                 walk<CHUNK, STATS>(s_mask + tid, s_xy, s_co, s_rgb, fpx, fpy, chunk * CHUNK, p, f);
+                if (ws.state && stored) {  // per-pixel state after this chunk, for the backward
+                    float* st = ws.state + (size_t)(mf + chunk) * (4 * kThreads);
+                    st[tid] = p.T;
+                    st[kThreads + tid] = p.C0;
+                    st[2 * kThreads + tid] = p.C1;
+                    st[3 * kThreads + tid] = p.C2;
+                }
             }
         }
         if (inside) {
@@ -653,23 +662,29 @@ int chunk_of(const fg_tune* tune)
 // tile's own workgroup (same results, less parallelism).
 constexpr int64_t kMaskStoreBytes = (int64_t)256 << 20;
 
-size_t carve(void* base, int64_t n_tiles, int64_t cap_pairs, int chunk, RenderWs* w, int64_t* max_mask_items)
+size_t carve(void* base, int64_t n_tiles, int64_t cap_pairs, int chunk, bool save_state, RenderWs* w,
+             int64_t* max_mask_items)
 {
     const int64_t mask_bytes = (int64_t)(chunk / 32) * kThreads * 4;
     const int64_t need = 2 * ((cap_pairs + chunk - 1) / chunk) + 1;
     const int64_t cap = kMaskStoreBytes / mask_bytes;
     *max_mask_items = need < cap ? need : cap;
-    const size_t sizes[6] = {(size_t)n_tiles * 4, (size_t)n_tiles * 4, (size_t)n_tiles * 4,
-                             (size_t)*max_mask_items * 4, 64, (size_t)*max_mask_items * (size_t)mask_bytes};
-    void** dst[6] = {(void**)&w->nch, (void**)&w->mfirst, (void**)&w->order, (void**)&w->mitem,
-                     (void**)&w->counters, (void**)&w->masks};
+    const size_t state_bytes = save_state ? (size_t)*max_mask_items * 4 * kThreads * 4 : 0;
+    const size_t sizes[7] = {(size_t)n_tiles * 4, (size_t)n_tiles * 4, (size_t)n_tiles * 4,
+                             (size_t)*max_mask_items * 4, 64, (size_t)*max_mask_items * (size_t)mask_bytes,
+                             state_bytes};
+    void** dst[7] = {(void**)&w->nch, (void**)&w->mfirst, (void**)&w->order, (void**)&w->mitem,
+                     (void**)&w->counters, (void**)&w->masks, (void**)&w->state};
     size_t off = 0;
-    for (int i = 0; i < 6; i++) {
+    for (int i = 0; i < 7; i++) {
         if (base) *dst[i] = (char*)base + off;
         off += align_up(sizes[i] + 4);
     }
+    if (base && !save_state) w->state = nullptr;
     return off;
 }
+
+bool save_of(const fg_tune* tune) { return tune && tune->save_state; }
 
 // Blend-kernel timing (measurement hooks).
 constexpr int kMaxTimed = 4096;
@@ -723,7 +738,7 @@ extern "C" size_t fg_render_workspace_size(const fg_camera* cam, int64_t cap_pai
     const int64_t n_tiles = (int64_t)((cam->width + 15) / 16) * ((cam->height + 15) / 16);
     RenderWs w;
     int64_t mi;
-    return carve(nullptr, n_tiles, cap_pairs, chunk_of(tune), &w, &mi);
+    return carve(nullptr, n_tiles, cap_pairs, chunk_of(tune), save_of(tune), &w, &mi);
 }
 
 extern "C" int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
@@ -741,8 +756,10 @@ extern "C" int fg_render(const fg_splats* splats, const uint32_t* vals, const ui
     if (n_tiles >= ((int64_t)1 << 31)) return FG_ERR_UNSUPPORTED;
     RenderWs w;
     int64_t max_mask_items;
-    if (!ws || ws_bytes < carve(nullptr, n_tiles, cap_pairs, chunk, &w, &max_mask_items)) return FG_ERR_WORKSPACE;
-    carve(ws, n_tiles, cap_pairs, chunk, &w, &max_mask_items);
+    const bool save = save_of(tune);
+    if (!ws || ws_bytes < carve(nullptr, n_tiles, cap_pairs, chunk, save, &w, &max_mask_items))
+        return FG_ERR_WORKSPACE;
+    carve(ws, n_tiles, cap_pairs, chunk, save, &w, &max_mask_items);
     hipStream_t s = (hipStream_t)stream;
     switch (chunk) {
         case 256: launch<256>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles, max_mask_items, s); break;
@@ -751,6 +768,31 @@ extern "C" int fg_render(const fg_splats* splats, const uint32_t* vals, const ui
     }
     return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
 }
+
+namespace fgr {
+
+bool render_ws_view(const void* ws, size_t ws_bytes, const fg_camera* cam, int64_t cap_pairs, const fg_tune* tune,
+                    RenderWsView* v)
+{
+    if (!ws || !cam || !v || !save_of(tune) || cam->width <= 0 || cam->height <= 0 || cap_pairs < 0) return false;
+    const int chunk = chunk_of(tune);
+    if (chunk != 256 && chunk != 512 && chunk != 1024) return false;
+    const int64_t n_tiles = (int64_t)((cam->width + 15) / 16) * ((cam->height + 15) / 16);
+    RenderWs w;
+    int64_t mi;
+    if (ws_bytes < carve(nullptr, n_tiles, cap_pairs, chunk, true, &w, &mi)) return false;
+    carve(const_cast<void*>(ws), n_tiles, cap_pairs, chunk, true, &w, &mi);
+    v->nch = w.nch;
+    v->mfirst = w.mfirst;
+    v->mitem = w.mitem;
+    v->counters = w.counters + 2;
+    v->state = w.state;
+    v->chunk = chunk;
+    v->max_items = mi;
+    return true;
+}
+
+}  // namespace fgr
 
 extern "C" int fg_timing(int enable)
 {

@@ -40,7 +40,10 @@ class GaussianRenderer:
     def __init__(self, m: int, sh_degree: int, width: int, height: int, cap_pairs: int, device="cuda"):
         self.m, self.sh_degree = m, sh_degree
         self.tree = _FlatTree(m, sh_degree, device)
-        self.fb = fg.FrameBuffers(self.tree, width, height, cap_sel=m, cap_pairs=cap_pairs, device=device)
+        # the forward keeps per-chunk state for the backward's parallel walk
+        self.tune = fg.tune_struct(save_state=True)
+        self.fb = fg.FrameBuffers(self.tree, width, height, cap_sel=m, cap_pairs=cap_pairs, device=device,
+                                  save_state=True)
         self.bwd_ws = torch.empty(fg.fg_render_backward_workspace_size(m), dtype=torch.uint8, device=device)
 
     def forward(self, mean, log_scale, quat, logit, sh, cam, tau: float = 0.0, bg=(0.0, 0.0, 0.0)):
@@ -48,7 +51,7 @@ class GaussianRenderer:
         t.mean, t.quat, t.sh = mean, quat, sh
         prm = fg.params_struct(mean, log_scale, quat, logit, sh, self.sh_degree)
         fg.fg_activate(prm, t.scale, t.opacity)
-        fg.render_frame(t, cam, self.fb, tau_R=3.0e38, tau=tau, bg=bg)
+        fg.render_frame(t, cam, self.fb, tau_R=3.0e38, tau=tau, bg=bg, tune=self.tune)
         return self.fb.image
 
     def backward(self, mean, log_scale, quat, logit, sh, cam, grad_image, bg=(0.0, 0.0, 0.0)):
@@ -57,7 +60,8 @@ class GaussianRenderer:
         grads = fg.FgGrads(*[x.data_ptr() for x in g])
         fb = self.fb
         fg.fg_render_backward(prm, cam, bg, fb.sel_idx, fb.n_sel, fb.cap_sel, fb.splats, fb.vals, fb.ranges,
-                              fb.final_T, fb.n_contrib, grad_image.contiguous(), grads, self.bwd_ws)
+                              fb.final_T, fb.n_contrib, fb.image, fb.render_ws, fb.cap_pairs, self.tune,
+                              grad_image.contiguous(), grads, self.bwd_ws)
         return g
 
     def render(self, mean, log_scale, quat, logit, sh, cam, tau: float = 0.0, bg=(0.0, 0.0, 0.0)):

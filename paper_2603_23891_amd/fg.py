@@ -61,7 +61,7 @@ class FgGrads(C.Structure):
 
 
 class FgTune(C.Structure):
-    _fields_ = [("render_batch", C.c_int32), ("radix_bits", C.c_int32), ("reserved0", C.c_int32),
+    _fields_ = [("render_batch", C.c_int32), ("radix_bits", C.c_int32), ("save_state", C.c_int32),
                 ("reserved1", C.c_int32)]
 
 
@@ -99,7 +99,8 @@ def lib():
         L.fg_render_backward_workspace_size.restype = C.c_size_t
         L.fg_render_backward_workspace_size.argtypes = [i64]
         L.fg_render_backward.restype = i32
-        L.fg_render_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.fg_render_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, i64, vp,
+                                         vp, vp, vp, C.c_size_t, vp]
         L.fg_status_string.restype = C.c_char_p
         L.fg_status_string.argtypes = [i32]
         L.fg_timing.restype = i32
@@ -141,8 +142,8 @@ def camera_struct(cam) -> FgCamera:
     return c
 
 
-def tune_struct(render_batch: int = 0, radix_bits: int = 0) -> FgTune:
-    return FgTune(render_batch=render_batch, radix_bits=radix_bits, reserved0=0, reserved1=0)
+def tune_struct(render_batch: int = 0, radix_bits: int = 0, save_state: bool = False) -> FgTune:
+    return FgTune(render_batch=render_batch, radix_bits=radix_bits, save_state=1 if save_state else 0, reserved1=0)
 
 
 # ---------------------------------------------------------------------------
@@ -250,7 +251,8 @@ def fg_render(splats: Splats, vals, ranges, cam, bg: Sequence[float], image, fin
 class FrameBuffers:
     """All buffers of one view; capacities are fixed at construction."""
 
-    def __init__(self, tree: DeviceTree, width: int, height: int, cap_sel: int, cap_pairs: int, device="cuda"):
+    def __init__(self, tree: DeviceTree, width: int, height: int, cap_sel: int, cap_pairs: int, device="cuda",
+                 save_state: bool = False):
         self.width, self.height = width, height
         self.cap_sel, self.cap_pairs = int(cap_sel), int(cap_pairs)
         N = tree.n_nodes
@@ -272,7 +274,8 @@ class FrameBuffers:
         _C.width, _C.height = width, height
         self.sort_ws = torch.empty(fg_sort_workspace_size(self.cap_sel, self.cap_pairs, _C), dtype=torch.uint8,
                                    device=device)
-        rw = max(fg_render_workspace_size(_C, self.cap_pairs, tune_struct(c)) for c in (256, 512, 1024))
+        rw = max(fg_render_workspace_size(_C, self.cap_pairs, tune_struct(c, save_state=save_state))
+                 for c in (256, 512, 1024))
         self.render_ws = torch.empty(rw, dtype=torch.uint8, device=device)
         self.image = torch.empty((3, height, width), dtype=torch.float32, device=device)
         self.final_T = torch.empty((height, width), dtype=torch.float32, device=device)
@@ -341,12 +344,16 @@ def fg_render_backward_workspace_size(cap_sel: int) -> int:
 
 
 def fg_render_backward(prm: FgParams, cam, bg, sel_idx, n_sel, cap_sel: int, splats: Splats, vals, ranges, final_T,
-                       n_contrib, dL_dimage, grads: FgGrads, ws, stream=None):
+                       n_contrib, image, render_ws, cap_pairs: int, tune: Optional[FgTune], dL_dimage,
+                       grads: FgGrads, ws, stream=None):
     cs, ss = camera_struct(cam), splats.struct()
     bgv = (C.c_float * 3)(*[float(b) for b in bg])
+    rws_bytes = render_ws.numel() * render_ws.element_size() if render_ws is not None else 0
     _check(lib().fg_render_backward(_ref(prm), _ref(cs), C.cast(bgv, C.c_void_p), _p(sel_idx), _p(n_sel), cap_sel,
-                                    _ref(ss), _p(vals), _p(ranges), _p(final_T), _p(n_contrib), _p(dL_dimage),
-                                    _ref(grads), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
+                                    _ref(ss), _p(vals), _p(ranges), _p(final_T), _p(n_contrib), _p(image),
+                                    _p(render_ws), rws_bytes, cap_pairs, _ref(tune) if tune is not None else None,
+                                    _p(dL_dimage), _ref(grads), _p(ws), ws.numel() * ws.element_size(),
+                                    _stream(stream)),
            "fg_render_backward")
 
 
