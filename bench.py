@@ -218,7 +218,7 @@ def main():
     fb = fg.FrameBuffers(dtree, W, H, cap_sel=8_000_000, cap_pairs=48_000_000)
     stream = torch.cuda.current_stream()
 
-    def frame(cam, stats=None, ev=None):
+    def frame(cam, stats=None, ev=None, tune=None):
         if ev: ev[0].record(stream)
         fg.filter_stage(dtree, cam, fb, tau_R)
         if ev: ev[1].record(stream)
@@ -226,7 +226,7 @@ def main():
         if ev: ev[2].record(stream)
         fg.sort_stage(cam, fb)
         if ev: ev[3].record(stream)
-        fg.render_stage(cam, fb, frag_stats=stats)
+        fg.render_stage(cam, fb, frag_stats=stats, tune=tune)
         if ev: ev[4].record(stream)
 
     for k in range(args.warmup):
@@ -235,16 +235,19 @@ def main():
     K = args.steps
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
     torch.cuda.synchronize()
-    fg.fg_timing(True)  # the library records events around its blend kernel
+    # events the library records on its stream right around its blend kernel
+    bev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for a, b in bev:  # create the underlying events
+        a.record(stream)
+        b.record(stream)
+    tunes = [fg.tune_struct(blend_events=e) for e in bev]
+    torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(K):
-        frame(cams[k % 64], ev=evs[k])
+        frame(cams[k % 64], ev=evs[k], tune=tunes[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    blend_ms_total, blend_calls = fg.fg_timing_read()
-    fg.fg_timing(False)
-    assert blend_calls == K
-    blend_ms = blend_ms_total / K
+    blend_ms = float(np.mean([a.elapsed_time(b) for a, b in bev]))
     fps = K / wall
     stage_names = ["filter", "preprocess", "sort", "render"]
     st = {n: [evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(K)] for i, n in enumerate(stage_names)}

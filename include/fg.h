@@ -138,6 +138,9 @@ typedef struct fg_tune {
                               fg_render_workspace_size with the same tune), which
                               fg_render_backward reads; 0: not kept (default) */
     int32_t reserved1;
+    void* blend_events[2]; /* NULL, NULL: none; else two caller-owned hipEvent_t that fg_render
+                              records on its stream right before and right after its blend
+                              kernel (k_render), for timing that kernel alone */
 } fg_tune;
 
 /* ---- stage 1: traversal-free parallel filter (Sec. 3.2) ---------------- */
@@ -302,18 +305,6 @@ int fg_render_backward(const fg_params* p, const fg_camera* cam, const float bg[
 /* Text for an FG_* return code. */
 const char* fg_status_string(int code);
 
-/* ---- measurement hooks -------------------------------------------------- */
-
-/* Timing of the blend kernel. fg_timing(1) clears the record and makes each
- * later fg_render call record a HIP event pair around its blend kernel
- * (k_render) on that call's stream, up to 4096 calls; fg_timing(0) stops
- * recording. Events are created on first use (not per call) and kept until
- * the process ends. Do not enable during stream capture.
- * fg_timing_read waits for the last recorded event and returns the summed
- * durations in milliseconds and the number of calls recorded since
- * fg_timing(1). Errors: FG_ERR_HIP. */
-int fg_timing(int enable);
-int fg_timing_read(double* total_ms, int32_t* count);
 
 #ifdef __cplusplus
 }

@@ -44,7 +44,7 @@ class BatchedRenderer:
     """Renders V views of one device-resident tree per call of ``run``."""
 
     def __init__(self, tree: fg.DeviceTree, cams: Sequence, cap_sel: int, cap_pairs: Sequence[int] | int,
-                 device="cuda"):
+                 device="cuda", n_streams: int = 4):
         self.tree, self.cams = tree, list(cams)
         V = len(self.cams)
         self.cap_sel = int(cap_sel)
@@ -60,20 +60,32 @@ class BatchedRenderer:
         self.views = [ViewBuffers(c, self.cap_sel, caps[i], device) for i, c in enumerate(self.cams)]
         self.graph: Optional[torch.cuda.CUDAGraph] = None
         self.tune = fg.tune_struct()
+        # views run on n_streams streams (default priority) after the shared
+        # filter, so one view's long blend tail overlaps other views' work
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, n_streams))]
 
     def run(self, tau_R: float = 3.0, tau: float = 0.0, bg=(0.0, 0.0, 0.0), tune: Optional[fg.FgTune] = None):
-        """Enqueue the whole batch on the current stream (no host synchronisation)."""
+        """Enqueue the whole batch (no host synchronisation): the node-major
+        filter on the current stream, then the views' projection, sort and
+        blend spread over the batch's streams, which the current stream joins
+        at the end. Graph capture records the fork and join."""
         tune = tune or self.tune
+        main = torch.cuda.current_stream()
         fg.fg_filter(self.tree, self.cams, tau_R, self.sel_bits, self.sel_idx, self.cap_sel, self.n_sel,
-                     self.status, self.filter_ws)
+                     self.status, self.filter_ws, stream=main)
+        for st in self.streams:
+            st.wait_stream(main)
         for v, (cam, vb) in enumerate(zip(self.cams, self.views)):
+            st = self.streams[v % len(self.streams)]
             sel = self.sel_idx[v * self.cap_sel:(v + 1) * self.cap_sel]
             nsel = self.n_sel[v:v + 1]
-            fg.fg_preprocess(self.tree, cam, tau, sel, nsel, self.cap_sel, vb.splats, self.status)
+            fg.fg_preprocess(self.tree, cam, tau, sel, nsel, self.cap_sel, vb.splats, self.status, stream=st)
             fg.fg_sort(vb.splats, nsel, self.cap_sel, cam, vb.tile_keys, vb.vals, vb.cap_pairs, vb.n_pairs,
-                       vb.ranges, self.status, vb.sort_ws, tune)
+                       vb.ranges, self.status, vb.sort_ws, tune, stream=st)
             fg.fg_render(vb.splats, vb.vals, vb.ranges, cam, bg, vb.image, vb.final_T, vb.n_contrib, vb.cap_pairs,
-                         None, self.status, vb.render_ws, tune)
+                         None, self.status, vb.render_ws, tune, stream=st)
+        for st in self.streams:
+            main.wait_stream(st)
 
     def capture(self, tau_R: float = 3.0, tau: float = 0.0, bg=(0.0, 0.0, 0.0),
                 tune: Optional[fg.FgTune] = None) -> torch.cuda.CUDAGraph:

@@ -686,20 +686,10 @@ size_t carve(void* base, int64_t n_tiles, int64_t cap_pairs, int chunk, bool sav
 
 bool save_of(const fg_tune* tune) { return tune && tune->save_state; }
 
-// Blend-kernel timing (measurement hooks).
-constexpr int kMaxTimed = 4096;
-struct Timing {
-    bool on = false;
-    int n = 0;
-    hipEvent_t ev[2 * kMaxTimed] = {};
-    bool created = false;
-};
-Timing g_timing;
-
 template <int CHUNK>
 void launch(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
             const float bg[3], float* image, float* final_T, uint32_t* n_contrib, unsigned long long* frag_stats,
-            const RenderWs& w, int64_t n_tiles, int64_t max_mask_items, hipStream_t s)
+            const RenderWs& w, int64_t n_tiles, int64_t max_mask_items, const fg_tune* tune, hipStream_t s)
 {
     const int Wt = (cam->width + 15) / 16;
     hipLaunchKernelGGL(k_chunk_count<CHUNK>, dim3((unsigned)((n_tiles + kThreads - 1) / kThreads)), dim3(kThreads), 0,
@@ -719,14 +709,11 @@ void launch(const fg_splats* splats, const uint32_t* vals, const uint32_t* range
     } else {
         hipLaunchKernelGGL((k_masks<CHUNK, false>), dim3(gm), dim3(kThreads), 0, s, xy, co, vals, ranges, cam->width,
                            cam->height, Wt, w, frag_stats);
-        const bool timed = g_timing.on && g_timing.n < kMaxTimed;
-        if (timed) (void)hipEventRecord(g_timing.ev[2 * g_timing.n], s);
+        const bool timed = tune && tune->blend_events[0] && tune->blend_events[1];
+        if (timed) (void)hipEventRecord((hipEvent_t)tune->blend_events[0], s);
         hipLaunchKernelGGL((k_render<CHUNK, false>), dim3(gr), dim3(kThreads), 0, s, xy, co, rgb, vals, ranges, n_tiles,
                            cam->width, cam->height, Wt, bg[0], bg[1], bg[2], w, image, final_T, n_contrib, frag_stats);
-        if (timed) {
-            (void)hipEventRecord(g_timing.ev[2 * g_timing.n + 1], s);
-            ++g_timing.n;
-        }
+        if (timed) (void)hipEventRecord((hipEvent_t)tune->blend_events[1], s);
     }
 }
 
@@ -762,9 +749,12 @@ extern "C" int fg_render(const fg_splats* splats, const uint32_t* vals, const ui
     carve(ws, n_tiles, cap_pairs, chunk, save, &w, &max_mask_items);
     hipStream_t s = (hipStream_t)stream;
     switch (chunk) {
-        case 256: launch<256>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles, max_mask_items, s); break;
-        case 1024: launch<1024>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles, max_mask_items, s); break;
-        default: launch<512>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles, max_mask_items, s); break;
+        case 256: launch<256>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
+                                max_mask_items, tune, s); break;
+        case 1024: launch<1024>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
+                                max_mask_items, tune, s); break;
+        default: launch<512>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
+                                max_mask_items, tune, s); break;
     }
     return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
 }
@@ -793,33 +783,6 @@ bool render_ws_view(const void* ws, size_t ws_bytes, const fg_camera* cam, int64
 }
 
 }  // namespace fgr
-
-extern "C" int fg_timing(int enable)
-{
-    if (enable && !g_timing.created) {
-        for (int i = 0; i < 2 * kMaxTimed; i++)
-            if (hipEventCreate(&g_timing.ev[i]) != hipSuccess) return FG_ERR_HIP;
-        g_timing.created = true;
-    }
-    g_timing.on = enable != 0;
-    if (enable) g_timing.n = 0;
-    return FG_OK;
-}
-
-extern "C" int fg_timing_read(double* total_ms, int32_t* count)
-{
-    if (!total_ms || !count) return FG_ERR_INVALID_ARG;
-    *total_ms = 0.0;
-    *count = g_timing.n;
-    if (g_timing.n == 0) return FG_OK;
-    if (hipEventSynchronize(g_timing.ev[2 * g_timing.n - 1]) != hipSuccess) return FG_ERR_HIP;
-    for (int i = 0; i < g_timing.n; i++) {
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, g_timing.ev[2 * i], g_timing.ev[2 * i + 1]) != hipSuccess) return FG_ERR_HIP;
-        *total_ms += ms;
-    }
-    return FG_OK;
-}
 
 extern "C" const char* fg_status_string(int code)
 {

@@ -62,12 +62,12 @@ class FgGrads(C.Structure):
 
 class FgTune(C.Structure):
     _fields_ = [("render_batch", C.c_int32), ("radix_bits", C.c_int32), ("save_state", C.c_int32),
-                ("reserved1", C.c_int32)]
+                ("reserved1", C.c_int32), ("blend_events", C.c_void_p * 2)]
 
 
 EXPORTS = ["fg_filter_workspace_size", "fg_filter", "fg_preprocess", "fg_sort_workspace_size", "fg_sort",
            "fg_render_workspace_size", "fg_render", "fg_activate", "fg_render_backward_workspace_size",
-           "fg_render_backward", "fg_status_string", "fg_timing", "fg_timing_read"]
+           "fg_render_backward", "fg_status_string"]
 
 _lib = None
 
@@ -103,10 +103,6 @@ def lib():
                                          vp, vp, vp, C.c_size_t, vp]
         L.fg_status_string.restype = C.c_char_p
         L.fg_status_string.argtypes = [i32]
-        L.fg_timing.restype = i32
-        L.fg_timing.argtypes = [i32]
-        L.fg_timing_read.restype = i32
-        L.fg_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         _lib = L
     return _lib
 
@@ -142,8 +138,14 @@ def camera_struct(cam) -> FgCamera:
     return c
 
 
-def tune_struct(render_batch: int = 0, radix_bits: int = 0, save_state: bool = False) -> FgTune:
-    return FgTune(render_batch=render_batch, radix_bits=radix_bits, save_state=1 if save_state else 0, reserved1=0)
+def tune_struct(render_batch: int = 0, radix_bits: int = 0, save_state: bool = False, blend_events=None) -> FgTune:
+    """blend_events: None, or two recorded torch.cuda.Event (timing enabled)
+    that fg_render records around its blend kernel."""
+    t = FgTune(render_batch=render_batch, radix_bits=radix_bits, save_state=1 if save_state else 0, reserved1=0)
+    if blend_events is not None:
+        t.blend_events[0] = blend_events[0].cuda_event
+        t.blend_events[1] = blend_events[1].cuda_event
+    return t
 
 
 # ---------------------------------------------------------------------------
@@ -355,14 +357,3 @@ def fg_render_backward(prm: FgParams, cam, bg, sel_idx, n_sel, cap_sel: int, spl
                                     _p(dL_dimage), _ref(grads), _p(ws), ws.numel() * ws.element_size(),
                                     _stream(stream)),
            "fg_render_backward")
-
-
-def fg_timing(enable: bool):
-    _check(lib().fg_timing(1 if enable else 0), "fg_timing")
-
-
-def fg_timing_read():
-    """(summed blend-kernel milliseconds, number of timed fg_render calls)."""
-    ms, n = C.c_double(0.0), C.c_int32(0)
-    _check(lib().fg_timing_read(C.byref(ms), C.byref(n)), "fg_timing_read")
-    return ms.value, int(n.value)

@@ -1,7 +1,7 @@
 """The C-ABI boundary without a GPU: libfg.so loads, exports every function
 include/fg.h declares (and the binding lists exactly those), and its host-only
 paths behave as documented: status strings, workspace sizes, argument
-rejection before any device work, and the timing hooks with nothing recorded.
+rejection before any device work, and the tune struct's layout.
 No kernel is launched here.
 """
 import ctypes as C
@@ -91,8 +91,9 @@ def test_entry_points_reject_missing_arguments_on_the_host(lib):
                          None, 0, None, None) == FG_ERR_INVALID_ARG
 
 
-def test_timing_hooks_with_nothing_recorded(lib):
-    ms, n = C.c_double(-1.0), C.c_int32(-1)
-    assert lib.fg_timing_read(C.byref(ms), C.byref(n)) == FG_OK
-    assert n.value == 0 and ms.value == 0.0
-    assert lib.fg_timing_read(None, None) == FG_ERR_INVALID_ARG
+def test_tune_struct_layout():
+    """fg_tune as the header lays it out: four int32 then two event handles."""
+    t = fg.tune_struct(512, 7, True)
+    assert C.sizeof(t) == 16 + 2 * C.sizeof(C.c_void_p)
+    assert (t.render_batch, t.radix_bits, t.save_state) == (512, 7, 1)
+    assert t.blend_events[0] is None and t.blend_events[1] is None
