@@ -1,0 +1,67 @@
+"""GPU parity at the benchmark's full size, in the launch configuration the
+bench times: the 20,000,003-node city tree at 1920x1080 with the calibrated
+GTC threshold and the bench's capacities (frames of the fly-through), and two
+views of the 32-view batch (720p and 2160p, global tile ids) through the
+batched renderer. Same bar as the small cases: selection, splats, keys,
+ranges and contributor counts bit-exact, colours within 1e-4.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_23891_amd import batch, fg, synth
+from tests.gpu_util import assert_frame_parity, read_frame
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def city():
+    tree = synth.city_tree(synth.CITY20M)
+    with open(os.path.join(ROOT, "tests", "golden", "city_tau.json")) as f:
+        tau = float(json.load(f)["city20m"]["tau"])
+    return tree, fg.DeviceTree(tree), tau
+
+
+@pytest.mark.parametrize("frame", [0, 32])
+def test_flythrough_frame_full_size(city, frame):
+    tree, dtree, tau = city
+    cam = synth.city20m_frames(64)[frame]
+    fb = fg.FrameBuffers(dtree, cam.width, cam.height, cap_sel=8_000_000, cap_pairs=48_000_000)
+    fg.render_frame(dtree, cam, fb, synth.TAU_R, tau)
+    torch.cuda.synchronize()
+    g = read_frame(fb, tree.n_nodes)
+    o = oracle.render_frame(tree, cam, synth.TAU_R, tau)
+    assert o["sel_idx"].size > 100_000 and o["keys"].size > 100_000
+    assert_frame_parity(g, o)
+
+
+def test_batch_views_full_size(city):
+    tree, dtree, tau = city
+    views = synth.city20m_batch_views(32)
+    pick = [min(range(32), key=lambda v: views[v].width), max(range(32), key=lambda v: views[v].width)]
+    cams = [views[v] for v in pick]  # keep their global tile ids
+    assert cams[0].width == 1280 and cams[1].width == 3840
+    br = batch.BatchedRenderer(dtree, cams, cap_sel=12_000_000, cap_pairs=[8_000_000, 40_000_000])
+    br.run(synth.TAU_R, tau)
+    torch.cuda.synchronize()
+    ns, npairs, status = br.counts()
+    assert status == 0
+    u32 = lambda t: t.cpu().numpy().view(np.uint32)
+    for v, cam in enumerate(cams):
+        o = oracle.render_frame(tree, cam, synth.TAU_R, tau)
+        vb = br.views[v]
+        assert ns[v] == o["sel_idx"].size
+        assert np.array_equal(u32(br.sel_idx)[v * br.cap_sel: v * br.cap_sel + ns[v]], o["sel_idx"])
+        assert npairs[v] == o["keys"].size
+        n = int(npairs[v])
+        assert np.array_equal(u32(vb.tile_keys)[:n], (o["keys"] >> np.uint64(32)).astype(np.uint32))
+        assert np.array_equal(u32(vb.vals)[:n], o["vals"])
+        assert np.array_equal(u32(vb.ranges).reshape(-1, 2), o["ranges"])
+        assert np.abs(vb.image.cpu().numpy() - o["image"]).max() <= 1e-4
+        assert np.array_equal(u32(vb.n_contrib), o["n_contrib"])
