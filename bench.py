@@ -34,6 +34,27 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 OPS_EVAL, OPS_EXP, OPS_PASS, OPS_BLEND = 12, 16, 3, 9
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_render_city20m_flythrough_1080p_hbm.md")
+
+
+def measured_traffic():
+    """HBM bytes per k_render launch from the committed FETCH_SIZE/WRITE_SIZE
+    counter summary (scaled by the copy-kernel calibration recorded there), or
+    None when the kernel's sources have changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = dict(l.split(": ", 1) for l in open(TRAFFIC_SUMMARY).read().splitlines() if ": " in l)
+        h = hashlib.sha256()
+        for s in fields["kernel_sources"].split():
+            with open(os.path.join(ROOT, s), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != fields["kernel_source_sha256"].strip():
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -191,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy three times (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'Sharding').")
@@ -254,6 +277,15 @@ def main():
     frame_ms = [evs[k][0].elapsed_time(evs[k][4]) for k in range(K)]
     log(f"timed {K} frames: {fps:.1f} FPS, {1e3 * wall / K:.3f} ms/frame wall")
 
+    if args.copy_probe:
+        # a plain copy kernel of known size: 256 MiB read and 256 MiB written
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # untimed pass over the same frames: counts and fragment statistics
     counts = []
     stats = torch.zeros(8, dtype=torch.int64, device="cuda")
@@ -306,7 +338,7 @@ def main():
     # taken by events that the library records around it on its stream
     blend_tops = (tot["blend_ops"] / f) / (blend_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", kernel="k_render", achieved=blend_tops, peak=VALU_PEAK_TOPS, unit="TFLOP/s",
-                    frac=blend_tops / VALU_PEAK_TOPS, traffic=None, kernel_ms=blend_ms,
+                    frac=blend_tops / VALU_PEAK_TOPS, traffic=measured_traffic(), kernel_ms=blend_ms,
                     ops_per_launch=tot["blend_ops"] / f)
 
     batched = None if args.no_batch else measure_batch(torch, dtree, tau_R, tau)
