@@ -74,9 +74,6 @@ extern "C" {
 #define FG_STATUS_BAD_PARENT 4u     /* a parent index >= the child's index, a
                                        parent that is a leaf, or an ancestor chain
                                        longer than max_depth */
-#define FG_STATUS_LOOKBACK_STALL 8u /* a compaction workgroup gave up waiting for
-                                       its predecessor (never expected; outputs
-                                       of the frame are then undefined) */
 
 /* ---- inputs ------------------------------------------------------------ */
 

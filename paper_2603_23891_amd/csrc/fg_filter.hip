@@ -21,43 +21,39 @@
 //   k_select   every node, one pass: RL(n) = small(n) for internal nodes and
 //              F(n) for leaves; sel(n) = RL(n) and not blocked(parent(n)).
 //              Leaves whose parent is blocked in every view never read their
-//              mean. Wave ballots give the selection words; the compacted ids
-//              are written in ascending order with a single-pass decoupled
-//              look-back scan per view (Merrill & Garland 2016; 64
-//              predecessors read per step), workgroups taking their tile from
-//              an atomic ticket so every predecessor a workgroup waits on has
-//              already started. A descriptor packs its state and value in one
-//              64-bit word, so relaxed agent-scope atomics suffice.
+//              mean. Wave ballots give the selection words and a count per
+//              2048-node tile and view.
+//   k_tile_scan  exclusive prefix sum of the tile counts (one workgroup per
+//              view) and n_sel.
+//   k_compact  per tile and view: the selected ids in ascending order at the
+//              tile's offset, from the selection words (256 bytes per tile).
+//
+// Stream compaction is thus reduce-then-scan in three launches. A single-pass
+// scan with decoupled look-back (Merrill & Garland 2016) was measured first:
+// with about a thousand tiles resident, each tile spent a quarter of its time
+// walking back through predecessors that had published only aggregates, since
+// agent-scope descriptor reads cost a memory round trip per step.
 #include "fg_device.h"
 
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRounds = 16;                   // nodes per thread in k_select
+constexpr int kRounds = 8;                    // nodes per thread in k_select
 constexpr int kTileNodes = kBlock * kRounds;  // nodes per k_select workgroup
 constexpr int kWaves = kBlock / fgd::kWave;
 constexpr int kMaxViews = 8;                  // views per pass over the tree
-static_assert((kRounds * kWaves) % 64 == 0, "group offsets are scanned 64 at a time");
 
-// look-back descriptor: state in bits 63..62 (0 none, 1 aggregate, 2 prefix), value in bits 31..0
-constexpr unsigned long long kAgg = 1ull << 62;
-constexpr unsigned long long kPre = 2ull << 62;
-constexpr uint32_t kSpinLimit = 1u << 26;
+constexpr int kScanThreads = 1024;          // k_tile_scan workgroup
 
 struct CamSet {
     fgd::Cam c[kMaxViews];
 };
 
-__global__ void k_reset(uint32_t* __restrict__ status, bool reset_status, uint32_t* __restrict__ n_sel, int nv,
-                        uint32_t* __restrict__ ticket, unsigned long long* __restrict__ desc, int64_t n_desc)
+__global__ void k_reset(uint32_t* __restrict__ status, bool reset_status, uint32_t* __restrict__ n_sel, int nv)
 {
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i0 == 0) {
-        if (reset_status) *status = 0u;
-        *ticket = 0u;
-    }
-    if (i0 < nv) n_sel[i0] = 0u;
-    for (int64_t i = i0; i < n_desc; i += (int64_t)gridDim.x * blockDim.x) desc[i] = 0ull;
+    const int i = threadIdx.x;
+    if (i == 0 && reset_status) *status = 0u;
+    if (i < nv) n_sel[i] = 0u;
 }
 
 __device__ __forceinline__ bool bit_of(const uint32_t* __restrict__ w, int64_t i)
@@ -157,21 +153,13 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
                                                    const uint32_t* __restrict__ blocked_bits, int64_t words,
                                                    int64_t N, int64_t span, CamSet cams, int nv,
                                                    uint32_t* __restrict__ sel_bits, int64_t sel_words,
-                                                   uint32_t* __restrict__ sel_idx, int64_t cap_sel,
-                                                   uint32_t* __restrict__ n_sel, uint32_t* __restrict__ ticket,
-                                                   unsigned long long* __restrict__ desc,
+                                                   uint32_t* __restrict__ tile_cnt, int64_t n_tiles,
                                                    uint32_t* __restrict__ status)
 {
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_off[NV][kRounds * kWaves];
-    __shared__ unsigned long long s_ball[NV][kRounds * kWaves];
-    __shared__ uint32_t s_excl[NV];
+    __shared__ uint32_t s_cnt[NV][kWaves];
     const int tid = threadIdx.x;
     const int wave = tid / fgd::kWave;
-    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
-    __syncthreads();
-    const int64_t tile = s_tile;
-    const int64_t n_tiles = (N + kTileNodes - 1) / kTileNodes;
+    const int64_t tile = blockIdx.x;
     const uint32_t all = (1u << nv) - 1u;
     bool bad = false;
     // Loads are issued phase by phase for all rounds at once (parent links and
@@ -213,6 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
             mz[r] = mean[2 * N + n];
         }
     }
+    uint32_t cnt[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) cnt[v] = 0u;
 #pragma unroll
     for (int r = 0; r < kRounds; r++) {
         const int64_t n = tile * kTileNodes + r * kBlock + tid;
@@ -231,94 +222,112 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
             }
             const uint64_t ball = __ballot(sel);
             store_wave_bits(sel_bits + v * sel_words, n - (int64_t)fgd::lane_id(), N, ball);
-            if (fgd::lane_id() == 0) {
-                s_ball[v][r * kWaves + wave] = ball;
-                s_off[v][r * kWaves + wave] = (uint32_t)__popcll(ball);
-            }
+            cnt[v] += (uint32_t)__popcll(ball);
         }
     }
     if (__ballot(bad) && fgd::lane_id() == 0) atomicOr(status, FG_STATUS_BAD_PARENT);
+    if (fgd::lane_id() == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            if (v < nv) s_cnt[v][wave] = cnt[v];
+    }
     __syncthreads();
-    if (tid < fgd::kWave) {
-        for (int v = 0; v < nv; v++) {
-            unsigned long long* dv = desc + (int64_t)v * n_tiles;
-            // exclusive offsets of the (round, wave) groups in node order, a
-            // wave scan over 64 groups at a time ...
-            uint32_t agg = 0;
-            const int lane = fgd::lane_id();
+    if (tid < nv) {
+        uint32_t t = 0;
 #pragma unroll
-            for (int g0 = 0; g0 < kRounds * kWaves; g0 += fgd::kWave) {
-                const uint32_t c = s_off[v][g0 + lane];
-                uint32_t x = c;
+        for (int w = 0; w < kWaves; w++) t += s_cnt[tid][w];
+        tile_cnt[(int64_t)tid * n_tiles + tile] = t;
+    }
+}
+
+// One workgroup per view: tile_cnt[v][0 .. n_tiles) becomes its exclusive
+// prefix sum in place; n_sel[v] = the total.
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t* __restrict__ tile_cnt, int64_t n_tiles,
+                                                            uint32_t* __restrict__ n_sel, int64_t cap_sel,
+                                                            uint32_t* __restrict__ status)
+{
+    __shared__ uint32_t s_wave[kScanThreads / fgd::kWave];
+    uint32_t* row = tile_cnt + (int64_t)blockIdx.x * n_tiles;
+    const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
+    const int64_t per = (n_tiles + kScanThreads - 1) / kScanThreads;
+    const int64_t lo = tid * per, hi = lo + per < n_tiles ? lo + per : n_tiles;
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; i++) s += row[i];
+    uint32_t x = s;
 #pragma unroll
-                for (int d = 1; d < fgd::kWave; d <<= 1) {
-                    const uint32_t y = __shfl_up(x, d, fgd::kWave);
-                    if (lane >= d) x += y;
-                }
-                s_off[v][g0 + lane] = agg + x - c;
-                agg += __shfl(x, fgd::kWave - 1, fgd::kWave);
-            }
-            if (tid == 0)
-                __hip_atomic_store(&dv[tile], (tile == 0 ? kPre : kAgg) | agg, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            // ... then the look-back, 64 predecessors per step: lane i reads the
-            // descriptor of tile j - i; the nearest "prefix" lane ends the walk
-            // once no lane up to it is still unpublished.
-            uint32_t excl = 0;
-            if (tile > 0) {
-                int64_t j = tile - 1;
-                uint32_t spins = 0;
-                for (;;) {
-                    const int64_t idx = j - lane;
-                    const unsigned long long d =
-                        idx >= 0 ? __hip_atomic_load(&dv[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kPre;
-                    const unsigned long long state = d & (3ull << 62);
-                    const uint64_t pend = __ballot(state == 0ull);
-                    const uint64_t pre = __ballot(state == kPre);
-                    const uint64_t upto = pre ? (pre & (~pre + 1ull)) * 2ull - 1ull : ~0ull;
-                    if (pend & upto) {
-                        __builtin_amdgcn_s_sleep(1);
-                        if (++spins > kSpinLimit) {  // never expected: predecessors always publish
-                            if (lane == 0) atomicOr(status, FG_STATUS_LOOKBACK_STALL);
-                            break;
-                        }
-                        continue;
-                    }
-                    uint32_t val = ((upto >> lane) & 1ull) ? (uint32_t)d : 0u;
+    for (int d = 1; d < fgd::kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, fgd::kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == fgd::kWave - 1) s_wave[wave] = x;
+    __syncthreads();
+    uint32_t run = x - s, total = 0;
+    for (int w = 0; w < kScanThreads / fgd::kWave; w++) {
+        if (w < wave) run += s_wave[w];
+        total += s_wave[w];
+    }
+    for (int64_t i = lo; i < hi; i++) {
+        const uint32_t c = row[i];
+        row[i] = run;
+        run += c;
+    }
+    if (tid == 0) {
+        n_sel[blockIdx.x] = total;
+        if ((int64_t)total > cap_sel) atomicOr(status, FG_STATUS_SEL_OVERFLOW);
+    }
+}
+
+// Workgroup (tile, view): the selected ids of the tile's nodes, in ascending
+// order, at the tile's offset. Each wave reads the 64-bit selection word of
+// its 64-node groups; group offsets within the tile are a wave scan.
+__global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__ sel_bits, int64_t sel_words,
+                                                    int64_t N, const uint32_t* __restrict__ tile_off,
+                                                    int64_t n_tiles, uint32_t* __restrict__ sel_idx,
+                                                    int64_t cap_sel)
+{
+    __shared__ uint32_t s_off[kRounds * kWaves];
+    const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
+    const int64_t tile = blockIdx.x;
+    const int v = blockIdx.y;
+    const uint32_t* bits = sel_bits + (int64_t)v * sel_words;
+    uint64_t ball[kRounds];
 #pragma unroll
-                    for (int o = fgd::kWave / 2; o > 0; o >>= 1) val += __shfl_xor(val, o, fgd::kWave);
-                    excl += val;
-                    if (pre) break;
-                    j -= fgd::kWave;
-                }
-                if (tid == 0)
-                    __hip_atomic_store(&dv[tile], kPre | (unsigned long long)(excl + agg), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+    for (int r = 0; r < kRounds; r++) {
+        const int64_t base = tile * kTileNodes + r * kBlock + wave * fgd::kWave;  // multiple of 64
+        uint64_t b = 0;
+        if (base < N) {
+            b = bits[base >> 5];
+            if (base + 32 < N) b |= (uint64_t)bits[(base >> 5) + 1] << 32;
+        }
+        ball[r] = b;
+        if (lane == 0) s_off[r * kWaves + wave] = (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t agg = 0;
+#pragma unroll
+        for (int g0 = 0; g0 < kRounds * kWaves; g0 += fgd::kWave) {
+            const bool in = g0 + lane < kRounds * kWaves;
+            const uint32_t c = in ? s_off[g0 + lane] : 0u;
+            uint32_t x = c;
+#pragma unroll
+            for (int d = 1; d < fgd::kWave; d <<= 1) {
+                const uint32_t y = __shfl_up(x, d, fgd::kWave);
+                if (lane >= d) x += y;
             }
-            if (tid == 0) {
-                s_excl[v] = excl;
-                if (tile == n_tiles - 1) {
-                    const uint32_t total = excl + agg;
-                    n_sel[v] = total;
-                    if ((int64_t)total > cap_sel) atomicOr(status, FG_STATUS_SEL_OVERFLOW);
-                }
-            }
+            if (in) s_off[g0 + lane] = agg + x - c;
+            agg += __shfl(x, fgd::kWave - 1, fgd::kWave);
         }
     }
     __syncthreads();
+    const uint32_t base_off = tile_off[(int64_t)v * n_tiles + tile];
     const uint64_t lt = fgd::lanemask_lt();
+    uint32_t* out = sel_idx + (int64_t)v * cap_sel;
 #pragma unroll
-    for (int v = 0; v < NV; v++) {
-        if (v >= nv) break;
-        const uint32_t base = s_excl[v];
-#pragma unroll
-        for (int r = 0; r < kRounds; r++) {
-            const uint64_t ball = s_ball[v][r * kWaves + wave];
-            if ((ball >> fgd::lane_id()) & 1ull) {
-                const uint32_t off = base + s_off[v][r * kWaves + wave] + (uint32_t)__popcll(ball & lt);
-                if ((int64_t)off < cap_sel)
-                    sel_idx[(int64_t)v * cap_sel + off] = (uint32_t)(tile * kTileNodes + r * kBlock + tid);
-            }
+    for (int r = 0; r < kRounds; r++) {
+        if ((ball[r] >> lane) & 1ull) {
+            const uint32_t off = base_off + s_off[r * kWaves + wave] + (uint32_t)__popcll(ball[r] & lt);
+            if ((int64_t)off < cap_sel) out[off] = (uint32_t)(tile * kTileNodes + r * kBlock + tid);
         }
     }
 }
@@ -326,8 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct FilterWs {
-    uint32_t *small_bits, *blocked_bits, *ticket;
-    unsigned long long* desc;
+    uint32_t *small_bits, *blocked_bits, *tile_cnt;
     int64_t words;
 };
 
@@ -335,11 +343,11 @@ size_t carve(void* base, int64_t N, int64_t span, int n_views, FilterWs* w)
 {
     const int nv = n_views < kMaxViews ? n_views : kMaxViews;
     w->words = ((span + 63) / 64) * 2 + 2;
-    const size_t n_desc = (size_t)((N + kTileNodes - 1) / kTileNodes) + 1;
-    const size_t sizes[4] = {(size_t)w->words * 4 * nv, (size_t)w->words * 4 * nv, 64, n_desc * 8 * nv};
-    void** dst[4] = {(void**)&w->small_bits, (void**)&w->blocked_bits, (void**)&w->ticket, (void**)&w->desc};
+    const size_t n_tiles = (size_t)((N + kTileNodes - 1) / kTileNodes) + 1;
+    const size_t sizes[3] = {(size_t)w->words * 4 * nv, (size_t)w->words * 4 * nv, n_tiles * 4 * nv};
+    void** dst[3] = {(void**)&w->small_bits, (void**)&w->blocked_bits, (void**)&w->tile_cnt};
     size_t off = 0;
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < 3; i++) {
         if (base) *dst[i] = (char*)base + off;
         off += align_up(sizes[i]);
     }
@@ -360,7 +368,12 @@ void launch_pass(const fg_tree* tree, const CamSet& cs, int nv, float tau_R, uin
     }
     hipLaunchKernelGGL(k_select<NV>, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, tree->mean, tree->parent,
                        tree->flags, w.small_bits, w.blocked_bits, w.words, N, span, cs, nv, sel_bits, sel_words,
-                       sel_idx, cap_sel, n_sel, w.ticket, w.desc, status);
+                       w.tile_cnt, n_tiles, status);
+    hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)nv), dim3(kScanThreads), 0, s, w.tile_cnt, n_tiles, n_sel,
+                       cap_sel, status);
+    if (cap_sel > 0)
+        hipLaunchKernelGGL(k_compact, dim3((unsigned)n_tiles, (unsigned)nv), dim3(kBlock), 0, s, sel_bits, sel_words,
+                           N, w.tile_cnt, n_tiles, sel_idx, cap_sel);
 }
 
 }  // namespace
@@ -395,10 +408,7 @@ extern "C" int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_v
         const int nv = n_views - v0 < kMaxViews ? n_views - v0 : kMaxViews;
         CamSet cs;
         for (int v = 0; v < kMaxViews; v++) cs.c[v] = fgd::make_cam(cams[v0 + (v < nv ? v : 0)]);
-        int64_t rg = (n_tiles * nv + 255) / 256;
-        rg = rg < 1 ? 1 : (rg > 1024 ? 1024 : rg);
-        hipLaunchKernelGGL(k_reset, dim3((unsigned)rg), dim3(256), 0, s, status, v0 == 0, n_sel + v0, nv, w.ticket,
-                           w.desc, n_tiles * nv);
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, status, v0 == 0, n_sel + v0, nv);
         if (N == 0) continue;
         uint32_t* sb = sel_bits + (int64_t)v0 * sel_words;
         uint32_t* si = sel_idx ? sel_idx + (int64_t)v0 * cap_sel : nullptr;

@@ -25,7 +25,6 @@ LIB_PATH = os.path.join(HERE, "libfg.so")
 FG_STATUS_SEL_OVERFLOW = 1
 FG_STATUS_PAIR_OVERFLOW = 2
 FG_STATUS_BAD_PARENT = 4
-FG_STATUS_LOOKBACK_STALL = 8
 
 
 class FgError(RuntimeError):
