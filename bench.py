@@ -186,7 +186,7 @@ def measure_batch(torch, dtree, tau_R, tau):
 
     single_ms = timed(one_by_one, 3)
     eager_ms = timed(lambda: br.run(tau_R, tau), 3)
-    tuned = batch.autotune(br, tau_R, tau, chunks=(256, 512, 1024), radix_bits=(6, 7, 8), repeats=2)
+    tuned = batch.autotune(br, tau_R, tau, chunks=(128, 256, 512), radix_bits=(6, 7, 8), repeats=2)
     br.capture(tau_R, tau)
     graph_ms = timed(br.replay, 5)
     ns, npairs, status = br.counts()

@@ -128,13 +128,15 @@ typedef struct fg_splats {
 
 /* Speed-only knobs; results never depend on them. NULL = defaults. */
 typedef struct fg_tune {
-    int32_t render_batch;  /* splats per blend work item (chunk): 256, 512 or 1024 (default 512) */
+    int32_t render_batch;  /* splats per blend work item (chunk): 128, 256 or 512 (default 256) */
     int32_t radix_bits;    /* digit width of the pair sort: 4..8 (default 8) */
     int32_t save_state;    /* 1: fg_render keeps, for every chunk of a long range, each pixel's
                               (T, C) after that chunk in its workspace (sized for it by
                               fg_render_workspace_size with the same tune), which
                               fg_render_backward reads; 0: not kept (default) */
-    int32_t reserved1;
+    int32_t mask_items;    /* at most this many chunks of long ranges get their pass masks
+                              stored by the parallel mask kernel; later chunks compute
+                              them in the blend itself (0: as many as 256 MiB hold) */
     void* blend_events[2]; /* NULL, NULL: none; else two caller-owned hipEvent_t that fg_render
                               records on its stream right before and right after its blend
                               kernel (k_render), for timing that kernel alone */

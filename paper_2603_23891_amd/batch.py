@@ -33,7 +33,7 @@ class ViewBuffers:
         self.n_pairs = torch.zeros(1, dtype=i32, device=device)
         self.sort_ws = torch.empty(fg.fg_sort_workspace_size(cap_sel, cap_pairs, cam), dtype=torch.uint8,
                                    device=device)
-        rw = max(fg.fg_render_workspace_size(cam, cap_pairs, fg.tune_struct(c)) for c in (256, 512, 1024))
+        rw = max(fg.fg_render_workspace_size(cam, cap_pairs, fg.tune_struct(c)) for c in (128, 256, 512))
         self.render_ws = torch.empty(rw, dtype=torch.uint8, device=device)
         self.image = torch.empty((3, height, width), dtype=torch.float32, device=device)
         self.final_T = torch.empty((height, width), dtype=torch.float32, device=device)
@@ -118,7 +118,7 @@ def _digest(br: BatchedRenderer) -> List[np.ndarray]:
                             vb.n_contrib.cpu().numpy().ravel().view(np.uint32)]) for vb in br.views]
 
 
-def autotune(br: BatchedRenderer, tau_R: float = 3.0, tau: float = 0.0, chunks=(256, 512, 1024),
+def autotune(br: BatchedRenderer, tau_R: float = 3.0, tau: float = 0.0, chunks=(128, 256, 512),
              radix_bits=(6, 7, 8), repeats: int = 3, cache_path: Optional[str] = None,
              cache_key: Optional[str] = None) -> Dict:
     """Times every (blend chunk, radix digit width) candidate on the batch and

@@ -199,7 +199,7 @@ __device__ __forceinline__ uint32_t box_area(uint32_t b)
 template <int CHUNK>
 __device__ __forceinline__ void area_prefix(const uint32_t* s_box, int cnt, uint32_t* s_pref, uint32_t* s_wave)
 {
-    constexpr int S = CHUNK / kThreads;
+    constexpr int S = CHUNK >= kThreads ? CHUNK / kThreads : 1;
     const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
     uint32_t a[S], sum = 0;
 #pragma unroll
@@ -411,13 +411,13 @@ __device__ __forceinline__ void blend_step(PixelState& p, bool valid, float alph
 }
 
 // Walks the marked splats of one staged chunk for this lane's pixel. mcol
-// points at the pixel's first mask word (words kThreads apart). A summary
+// points at the pixel's first mask word (words STRIDE apart). A summary
 // bit per 64-splat pair of words, read first, sends the lane straight to the
 // non-empty words. Up to four marked splats of one such word are taken at a
 // time and their alphas (independent of T) computed together, so their LDS
 // reads and arithmetic overlap; the blend steps then run strictly in list
 // order.
-template <int CHUNK, bool STATS>
+template <int CHUNK, bool STATS, int STRIDE>
 __device__ __forceinline__ void walk(const uint32_t* mcol, const float2* s_xy, const float4* s_co,
                                      const float4* s_rgb, float fpx, float fpy, uint32_t base, PixelState& p,
                                      Frag& f)
@@ -426,12 +426,12 @@ __device__ __forceinline__ void walk(const uint32_t* mcol, const float2* s_xy, c
     uint32_t summary = 0;
 #pragma unroll
     for (int k = 0; k < kPairs; k++)
-        summary |= ((mcol[(2 * k) * kThreads] | mcol[(2 * k + 1) * kThreads]) != 0u ? 1u : 0u) << k;
+        summary |= ((mcol[(2 * k) * STRIDE] | mcol[(2 * k + 1) * STRIDE]) != 0u ? 1u : 0u) << k;
     while (summary != 0u && !p.done) {
         const int k = __builtin_ctz(summary);
         summary &= summary - 1u;
-        unsigned long long m = (unsigned long long)mcol[(2 * k) * kThreads] |
-                               ((unsigned long long)mcol[(2 * k + 1) * kThreads] << 32);
+        unsigned long long m = (unsigned long long)mcol[(2 * k) * STRIDE] |
+                               ((unsigned long long)mcol[(2 * k + 1) * STRIDE] << 32);
         const int b = k << 6;
         while (m != 0ull && !p.done) {
             const int j0 = b + __builtin_ctzll(m);
@@ -458,11 +458,12 @@ __device__ __forceinline__ void walk(const uint32_t* mcol, const float2* s_xy, c
     }
 }
 
-// Register copy of one chunk: the splat records this thread stages and the
-// mask words of its pixel (zero where the masks are computed in place).
+// Register copy of one chunk for one wave of a heavy tile: the splat records
+// this lane stages (every 64th of the chunk) and the mask words of its pixel
+// (zero where the masks are computed in place).
 template <int CHUNK>
 struct ChunkRegs {
-    static constexpr int S = CHUNK / kThreads;
+    static constexpr int S = CHUNK / fgd::kWave;
     float2 xy[S];
     float4 co[S];
     float4 rgb[S];
@@ -484,7 +485,7 @@ __device__ __forceinline__ void fetch_vals(const uint32_t* __restrict__ vals, ui
     const uint32_t start = r0 + chunk * CHUNK;
 #pragma unroll
     for (int k = 0; k < ChunkRegs<CHUNK>::S; k++) {
-        const int j = k * kThreads + (int)threadIdx.x;
+        const int j = k * fgd::kWave + fgd::lane_id();
         g[k] = j < cnt ? vals[start + j] : 0u;
     }
 }
@@ -499,7 +500,7 @@ __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ xy, const
     const int cnt = chunk_count<CHUNK>(r0, r1, chunk);
 #pragma unroll
     for (int k = 0; k < ChunkRegs<CHUNK>::S; k++) {
-        const int j = k * kThreads + (int)threadIdx.x;
+        const int j = k * fgd::kWave + fgd::lane_id();
         if (j < cnt) {
             R.xy[k] = xy[g[k]];
             R.co[k] = conic_o[g[k]];
@@ -520,6 +521,44 @@ __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ xy, const
     }
 }
 
+// Orders this wave's LDS writes before its own later LDS reads (and reads
+// before later writes); no other wave takes part.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pass masks of a staged chunk for the 64 pixels of one wave (rows y0 ..
+// y0 + 3 of the tile), when the chunk's masks were not stored: each lane
+// takes every 64th splat and tests the pixels of its box in those rows.
+// w_mask [word][64] is zero on entry.
+template <bool STATS>
+__device__ __forceinline__ void wave_masks(const float2* w_xy, const float4* w_co, int cnt, int tx, int ty, int W,
+                                           int H, int y0, uint32_t* w_mask, Frag& f)
+{
+    for (int j = fgd::lane_id(); j < cnt; j += fgd::kWave) {
+        const float2 mm = w_xy[j];
+        const float4 co = w_co[j];
+        const uint32_t b = splat_box(mm, co, tx, ty, W, H);
+        const int x0 = (int)(b & 255u), x1 = (int)((b >> 8) & 255u);
+        const int by0 = (int)((b >> 16) & 255u), by1 = (int)(b >> 24);
+        if (x0 > x1) continue;
+        const int ya = by0 > y0 ? by0 : y0, yb = by1 < y0 + 3 ? by1 : y0 + 3;
+        const uint32_t bit = 1u << (j & 31);
+        uint32_t* mrow = w_mask + (j >> 5) * fgd::kWave;
+        for (int ly = ya; ly <= yb; ly++) {
+            const float fy = (float)(ty * fgd::kTile + ly) + 0.5f;
+            for (int lx = x0; lx <= x1; lx++) {
+                float alpha;
+                if (pixel_alpha<STATS>(mm, co, (float)(tx * fgd::kTile + lx) + 0.5f, fy, alpha, f))
+                    atomicOr(&mrow[(ly - y0) * fgd::kTile + lx], bit);
+            }
+        }
+    }
+}
+
 template <int CHUNK, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
                                                      const float4* __restrict__ rgb_depth,
@@ -531,14 +570,16 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
                                                      unsigned long long* __restrict__ frag_stats)
 {
     constexpr int kWords = CHUNK / 32;
-    __shared__ float2 s_xy[CHUNK];
-    __shared__ float4 s_co[CHUNK];
-    __shared__ float4 s_rgb[CHUNK];
+    constexpr int kWaves = kThreads / fgd::kWave;
+    // a light tile uses the first CHUNK records; a heavy tile gives each wave
+    // its own CHUNK records and its pixels' mask columns
+    __shared__ float2 s_xy[kWaves * CHUNK];
+    __shared__ float4 s_co[kWaves * CHUNK];
+    __shared__ float4 s_rgb[kWaves * CHUNK];
     __shared__ uint32_t s_mask[kWords * kThreads];
     __shared__ uint32_t s_box[CHUNK];
     __shared__ uint32_t s_pref[CHUNK + 1];
-    __shared__ uint32_t s_wave[kThreads / fgd::kWave];
-    __shared__ uint32_t s_done[kThreads / fgd::kWave];
+    __shared__ uint32_t s_wave[kWaves];
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
     const int lx = tid % fgd::kTile, ly = tid / fgd::kTile;
@@ -579,11 +620,18 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
                 splat_masks<STATS>(s_xy, s_co, s_box, cnt, tx, ty, s_mask, f);
             }
             __syncthreads();
-            walk<CHUNK, STATS>(s_mask + tid, s_xy, s_co, s_rgb, fpx, fpy, 0u, p, f);
+            walk<CHUNK, STATS, kThreads>(s_mask + tid, s_xy, s_co, s_rgb, fpx, fpy, 0u, p, f);
         } else {
-            // heavy tile: while one chunk is walked, the next chunk's splat
-            // records and stored masks are loaded into registers, and the
-            // indices of the chunk after it
+            // heavy tile: each wave walks the chunks for its own 64 pixels at
+            // its own pace, with its own staging area, so no wave waits on the
+            // others between chunks. While one chunk is walked, the next
+            // chunk's splat records and stored masks are loaded into
+            // registers, and the indices of the chunk after it.
+            const int wave = tid / fgd::kWave, lane = fgd::lane_id();
+            float2* w_xy = s_xy + wave * CHUNK;
+            float4* w_co = s_co + wave * CHUNK;
+            float4* w_rgb = s_rgb + wave * CHUNK;
+            uint32_t* w_mask = s_mask + wave * (kWords * fgd::kWave);
             ChunkRegs<CHUNK> R;
             uint32_t gnext[ChunkRegs<CHUNK>::S];
             {
@@ -592,40 +640,47 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
                 fetch_chunk<CHUNK>(xy, conic_o, rgb_depth, ws.masks, r0, r1, 0u, g0, mf, n_mask_items, R);
                 fetch_vals<CHUNK>(vals, r0, r1, 1u, gnext);
             }
-            for (uint32_t chunk = 0; chunk < nch; chunk++) {
-                // a workgroup stops once every pixel of the tile has terminated
-                const bool wave_done = __ballot(!p.done) == 0ull;  // the whole wave votes
-                if (fgd::lane_id() == 0) s_done[tid / fgd::kWave] = wave_done ? 1u : 0u;
-                __syncthreads();
-                if (s_done[0] & s_done[1] & s_done[2] & s_done[3]) break;
+            uint32_t chunk = 0;
+            for (; chunk < nch; chunk++) {
+                // the wave stops once all of its pixels have terminated
+                if (__ballot(!p.done) == 0ull) break;
                 const int cnt = chunk_count<CHUNK>(r0, r1, chunk);
                 const bool stored = mf + chunk < n_mask_items;
+                wave_sync();  // the previous chunk's reads are done
 #pragma unroll
                 for (int k = 0; k < ChunkRegs<CHUNK>::S; k++) {
-                    const int j = k * kThreads + tid;
+                    const int j = k * fgd::kWave + lane;
                     if (j < cnt) {
-                        s_xy[j] = R.xy[k];
-                        s_co[j] = R.co[k];
-                        s_rgb[j] = R.rgb[k];
-                        if (!stored) s_box[j] = splat_box(R.xy[k], R.co[k], tx, ty, W, H);
+                        w_xy[j] = R.xy[k];
+                        w_co[j] = R.co[k];
+                        w_rgb[j] = R.rgb[k];
                     }
                 }
-                // every lane writes only its own pixel's mask words (column tid);
                 // zero where the masks are computed here
 #pragma unroll
-                for (int w = 0; w < kWords; w++) s_mask[w * kThreads + tid] = R.m[w];
-                __syncthreads();
+                for (int w = 0; w < kWords; w++) w_mask[w * fgd::kWave + lane] = R.m[w];
+                wave_sync();
                 if (chunk + 1 < nch) {
                     fetch_chunk<CHUNK>(xy, conic_o, rgb_depth, ws.masks, r0, r1, chunk + 1, gnext, mf, n_mask_items,
                                        R);
                     if (chunk + 2 < nch) fetch_vals<CHUNK>(vals, r0, r1, chunk + 2, gnext);
                 }
                 if (!stored) {  // beyond the mask store: masks computed here
-                    splat_masks<STATS>(s_xy, s_co, s_box, cnt, tx, ty, s_mask, f);
-                    __syncthreads();
+                    wave_masks<STATS>(w_xy, w_co, cnt, tx, ty, W, H, wave * (fgd::kWave / fgd::kTile), w_mask, f);
+                    wave_sync();
                 }
-                walk<CHUNK, STATS>(s_mask + tid, s_xy, s_co, s_rgb, fpx, fpy, chunk * CHUNK, p, f);
+                walk<CHUNK, STATS, fgd::kWave>(w_mask + lane, w_xy, w_co, w_rgb, fpx, fpy, chunk * CHUNK, p, f);
                 if (ws.state && stored) {  // per-pixel state after this chunk, for the backward
+                    float* st = ws.state + (size_t)(mf + chunk) * (4 * kThreads);
+                    st[tid] = p.T;
+                    st[kThreads + tid] = p.C0;
+                    st[2 * kThreads + tid] = p.C1;
+                    st[3 * kThreads + tid] = p.C2;
+                }
+            }
+            // the state after every later chunk equals the final one
+            if (ws.state) {
+                for (; chunk < nch && mf + chunk < n_mask_items; chunk++) {
                     float* st = ws.state + (size_t)(mf + chunk) * (4 * kThreads);
                     st[tid] = p.T;
                     st[kThreads + tid] = p.C0;
@@ -654,7 +709,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int chunk_of(const fg_tune* tune)
 {
-    if (!tune || !tune->render_batch) return 512;
+    if (!tune || !tune->render_batch) return 256;
     return tune->render_batch;
 }
 
@@ -662,12 +717,13 @@ int chunk_of(const fg_tune* tune)
 // tile's own workgroup (same results, less parallelism).
 constexpr int64_t kMaskStoreBytes = (int64_t)256 << 20;
 
-size_t carve(void* base, int64_t n_tiles, int64_t cap_pairs, int chunk, bool save_state, RenderWs* w,
-             int64_t* max_mask_items)
+size_t carve(void* base, int64_t n_tiles, int64_t cap_pairs, int chunk, bool save_state, int mask_items,
+             RenderWs* w, int64_t* max_mask_items)
 {
     const int64_t mask_bytes = (int64_t)(chunk / 32) * kThreads * 4;
     const int64_t need = 2 * ((cap_pairs + chunk - 1) / chunk) + 1;
-    const int64_t cap = kMaskStoreBytes / mask_bytes;
+    int64_t cap = kMaskStoreBytes / mask_bytes;
+    if (mask_items > 0 && mask_items < cap) cap = mask_items;
     *max_mask_items = need < cap ? need : cap;
     const size_t state_bytes = save_state ? (size_t)*max_mask_items * 4 * kThreads * 4 : 0;
     const size_t sizes[7] = {(size_t)n_tiles * 4, (size_t)n_tiles * 4, (size_t)n_tiles * 4,
@@ -685,6 +741,8 @@ size_t carve(void* base, int64_t n_tiles, int64_t cap_pairs, int chunk, bool sav
 }
 
 bool save_of(const fg_tune* tune) { return tune && tune->save_state; }
+
+int mask_items_of(const fg_tune* tune) { return tune ? tune->mask_items : 0; }
 
 template <int CHUNK>
 void launch(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
@@ -725,7 +783,7 @@ extern "C" size_t fg_render_workspace_size(const fg_camera* cam, int64_t cap_pai
     const int64_t n_tiles = (int64_t)((cam->width + 15) / 16) * ((cam->height + 15) / 16);
     RenderWs w;
     int64_t mi;
-    return carve(nullptr, n_tiles, cap_pairs, chunk_of(tune), save_of(tune), &w, &mi);
+    return carve(nullptr, n_tiles, cap_pairs, chunk_of(tune), save_of(tune), mask_items_of(tune), &w, &mi);
 }
 
 extern "C" int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
@@ -738,23 +796,23 @@ extern "C" int fg_render(const fg_splats* splats, const uint32_t* vals, const ui
         return FG_ERR_INVALID_ARG;
     if (cam->width <= 0 || cam->height <= 0) return FG_ERR_INVALID_ARG;
     const int chunk = chunk_of(tune);
-    if (chunk != 256 && chunk != 512 && chunk != 1024) return FG_ERR_INVALID_ARG;
+    if (chunk != 128 && chunk != 256 && chunk != 512) return FG_ERR_INVALID_ARG;
     const int64_t n_tiles = (int64_t)((cam->width + 15) / 16) * ((cam->height + 15) / 16);
     if (n_tiles >= ((int64_t)1 << 31)) return FG_ERR_UNSUPPORTED;
     RenderWs w;
     int64_t max_mask_items;
     const bool save = save_of(tune);
-    if (!ws || ws_bytes < carve(nullptr, n_tiles, cap_pairs, chunk, save, &w, &max_mask_items))
+    if (!ws || ws_bytes < carve(nullptr, n_tiles, cap_pairs, chunk, save, mask_items_of(tune), &w, &max_mask_items))
         return FG_ERR_WORKSPACE;
-    carve(ws, n_tiles, cap_pairs, chunk, save, &w, &max_mask_items);
+    carve(ws, n_tiles, cap_pairs, chunk, save, mask_items_of(tune), &w, &max_mask_items);
     hipStream_t s = (hipStream_t)stream;
     switch (chunk) {
-        case 256: launch<256>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
-                                max_mask_items, tune, s); break;
-        case 1024: launch<1024>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
-                                max_mask_items, tune, s); break;
-        default: launch<512>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
-                                max_mask_items, tune, s); break;
+        case 128: launch<128>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
+                              max_mask_items, tune, s); break;
+        case 512: launch<512>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
+                              max_mask_items, tune, s); break;
+        default: launch<256>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
+                             max_mask_items, tune, s); break;
     }
     return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
 }
@@ -766,12 +824,12 @@ bool render_ws_view(const void* ws, size_t ws_bytes, const fg_camera* cam, int64
 {
     if (!ws || !cam || !v || !save_of(tune) || cam->width <= 0 || cam->height <= 0 || cap_pairs < 0) return false;
     const int chunk = chunk_of(tune);
-    if (chunk != 256 && chunk != 512 && chunk != 1024) return false;
+    if (chunk != 128 && chunk != 256 && chunk != 512) return false;
     const int64_t n_tiles = (int64_t)((cam->width + 15) / 16) * ((cam->height + 15) / 16);
     RenderWs w;
     int64_t mi;
-    if (ws_bytes < carve(nullptr, n_tiles, cap_pairs, chunk, true, &w, &mi)) return false;
-    carve(const_cast<void*>(ws), n_tiles, cap_pairs, chunk, true, &w, &mi);
+    if (ws_bytes < carve(nullptr, n_tiles, cap_pairs, chunk, true, mask_items_of(tune), &w, &mi)) return false;
+    carve(const_cast<void*>(ws), n_tiles, cap_pairs, chunk, true, mask_items_of(tune), &w, &mi);
     v->nch = w.nch;
     v->mfirst = w.mfirst;
     v->mitem = w.mitem;

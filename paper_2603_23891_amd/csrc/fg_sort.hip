@@ -20,9 +20,10 @@
 //   k_rowscan   one workgroup per digit: exclusive scan over the tiles,
 //               digit totals
 //   k_scatter   per tile: stable local ranks (wave ballot match on the digit
-//               bits, per-wave counts combined in LDS in item order), items
-//               staged through LDS in locally sorted order, then written out
-//               so that consecutive lanes write consecutive addresses.
+//               bits for all of a wave's rounds, then one pass per digit over
+//               the per-(round, wave) counts in item order), items staged
+//               through LDS in locally sorted order, then written out so that
+//               consecutive lanes write consecutive addresses.
 //
 // Block offsets of the packing and emission steps are exclusive sums over
 // the per-block counts of all earlier blocks, which every block adds up
@@ -140,10 +141,12 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ digit_total)
 {
     constexpr int R = 1 << BITS;
+    static_assert(R <= kThreads, "one thread per digit");
     __shared__ uint32_t s_base[R];
-    __shared__ uint32_t s_run[R];
     __shared__ uint32_t s_start[R];
-    __shared__ uint32_t s_wcnt[kWaves][R];
+    // per (round, wave, digit): the group's count, then its exclusive offset
+    // among the tile's items of that digit (at most kTileItems: fits 16 bits)
+    __shared__ uint16_t s_cnt[kIPT][kWaves][R];
     __shared__ uint32_t s_keys[kTileItems];
     __shared__ uint32_t s_vals[kTileItems];
     __shared__ uint32_t s_wave[kWaves];
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
         if (tid < R) s_base[tid] = e;
     }
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        uint32_t k[kIPT], v[kIPT], rank[kIPT];
+        uint32_t k[kIPT], v[kIPT], below[kIPT];
 #pragma unroll
         for (int r = 0; r < kIPT; r++) {
             const int64_t idx = tile * kTileItems + r * kThreads + tid;
@@ -166,36 +169,38 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
             k[r] = valid ? kin[idx] : 0xFFFFFFFFu;
             v[r] = valid ? vin[idx] : 0u;
         }
-        if (tid < R) s_run[tid] = 0;
+        {
+            uint32_t* c32 = reinterpret_cast<uint32_t*>(&s_cnt[0][0][0]);
+            for (int i = tid; i < kIPT * kWaves * R / 2; i += kThreads) c32[i] = 0u;
+        }
+        __syncthreads();
+        // every wave ranks its items of every round among equal digits
+        // (ballot match), with no barrier between rounds
 #pragma unroll
         for (int r = 0; r < kIPT; r++) {
-            for (int d = tid; d < R * kWaves; d += kThreads) (&s_wcnt[0][0])[d] = 0;
-            __syncthreads();
             const int64_t idx = tile * kTileItems + r * kThreads + tid;
             const bool valid = idx < n;
             const uint32_t d = (k[r] >> shift) & (R - 1);
             const uint64_t m = match_digit<BITS>(d, valid);
-            const uint32_t below = (uint32_t)__popcll(m & fgd::lanemask_lt());
-            if (valid && below == 0) s_wcnt[wave][d] = (uint32_t)__popcll(m);
-            __syncthreads();
-            if (tid < R) {
-                uint32_t run = s_run[tid];
+            below[r] = (uint32_t)__popcll(m & fgd::lanemask_lt());
+            if (valid && below[r] == 0) s_cnt[r][wave][d] = (uint16_t)__popcll(m);
+        }
+        __syncthreads();
+        // per digit, groups in item order (round-major, then wave)
+        uint32_t run = 0;
+        if (tid < R) {
+#pragma unroll
+            for (int r = 0; r < kIPT; r++)
 #pragma unroll
                 for (int w = 0; w < kWaves; w++) {
-                    const uint32_t c = s_wcnt[w][tid];
-                    s_wcnt[w][tid] = run;
+                    const uint32_t c = s_cnt[r][w][tid];
+                    s_cnt[r][w][tid] = (uint16_t)run;
                     run += c;
                 }
-                s_run[tid] = run;
-            }
-            __syncthreads();
-            rank[r] = s_wcnt[wave][d] + below;
-            __syncthreads();
         }
         {
             uint32_t tot;
-            const uint32_t c = tid < R ? s_run[tid] : 0u;
-            const uint32_t e = block_excl_scan(c, s_wave, tot);
+            const uint32_t e = block_excl_scan(run, s_wave, tot);
             if (tid < R) s_start[tid] = e;
         }
         __syncthreads();
@@ -204,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
             const int64_t idx = tile * kTileItems + r * kThreads + tid;
             if (idx < n) {
                 const uint32_t d = (k[r] >> shift) & (R - 1);
-                const uint32_t pos = s_start[d] + rank[r];
+                const uint32_t pos = s_start[d] + s_cnt[r][wave][d] + below[r];
                 s_keys[pos] = k[r];
                 s_vals[pos] = v[r];
             }
@@ -307,11 +312,13 @@ __global__ __launch_bounds__(kThreads) void k_vis_pack(const float4* __restrict_
     }
 }
 
-// Per 2048 splats in depth order: the sum of their tile counts.
+// Per 2048 splats in depth order: the sum of their tile counts (the areas of
+// their rectangles). The rectangles are gathered here once and stored in depth
+// order, so that the emission reads them contiguously.
 __global__ __launch_bounds__(kThreads) void k_count_reduce(const uint32_t* __restrict__ order,
-                                                           const uint32_t* __restrict__ tiles,
+                                                           const ushort4* __restrict__ rect,
                                                            const uint32_t* __restrict__ n_p, int64_t cap,
-                                                           uint32_t* __restrict__ bsum)
+                                                           uint32_t* __restrict__ bsum, ushort4* __restrict__ rect_d)
 {
     __shared__ uint32_t s_wave[kWaves];
     const int64_t n = count_of(n_p, cap);
@@ -321,7 +328,11 @@ __global__ __launch_bounds__(kThreads) void k_count_reduce(const uint32_t* __res
 #pragma unroll
         for (int r = 0; r < kEmitIPT; r++) {
             const int64_t j = blk * kEmitItems + r * kThreads + threadIdx.x;
-            if (j < n) s += tiles[order[j]];
+            if (j < n) {
+                const ushort4 q = rect[order[j]];
+                rect_d[j] = q;
+                s += (uint32_t)(q.z - q.x) * (uint32_t)(q.w - q.y);
+            }
         }
         uint32_t total;
         block_excl_scan(s, s_wave, total);
@@ -335,8 +346,8 @@ __global__ __launch_bounds__(kThreads) void k_count_reduce(const uint32_t* __res
 // output positions k, k + 256, ...: a binary search over the offsets finds
 // the splat, and the position within its rectangle (rows, then columns)
 // gives the tile. Block 0 also stores n_pairs and flags an overflow.
-__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles,
-                                                   const ushort4* __restrict__ rect, const uint32_t* __restrict__ n_p,
+__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order,
+                                                   const ushort4* __restrict__ rect_d, const uint32_t* __restrict__ n_p,
                                                    int64_t cap, const uint32_t* __restrict__ bsum, int64_t cap_pairs,
                                                    int Wt, uint32_t tile_base, uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals, uint32_t* __restrict__ n_pairs,
@@ -359,9 +370,10 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
         for (int r = 0; r < kEmitIPT; r++) {
             const int64_t j = j0 + r;
             const uint32_t g = j < n ? order[j] : 0u;
-            c[r] = j < n ? tiles[g] : 0u;
+            const ushort4 q = j < n ? rect_d[j] : make_ushort4(0, 0, 0, 0);
+            c[r] = (uint32_t)(q.z - q.x) * (uint32_t)(q.w - q.y);
             s_g[tid * kEmitIPT + r] = g;
-            s_rect[tid * kEmitIPT + r] = j < n ? rect[g] : make_ushort4(0, 0, 0, 0);
+            s_rect[tid * kEmitIPT + r] = q;
             sum += c[r];
         }
         uint32_t total;
@@ -436,24 +448,32 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int64_t tiles_for(int64_t n) { return (n + kTileItems - 1) / kTileItems; }
 
+// Depth keys and splat ids ping-pong between buffers 0 and 1; the depth sort
+// has an even number of passes and ends in buffer 0, after which buffer 1
+// (8 bytes per splat) holds the rectangles in depth order.
 struct SortWs {
     uint32_t *dkey0, *dval0, *dkey1, *dval1, *bsum, *kalt, *valt, *hist, *digit_total, *vcnt, *n_vis;
+    ushort4* rect_d;
 };
 
 size_t carve(void* base, int64_t cap_sel, int64_t cap_pairs, SortWs* w)
 {
     const int64_t ht = tiles_for(cap_sel > cap_pairs ? cap_sel : cap_pairs);
     const size_t nblk = (size_t)((cap_sel + kTileItems - 1) / kTileItems + 1);
-    const size_t sizes[11] = {
-        (size_t)cap_sel * 4, (size_t)cap_sel * 4, (size_t)cap_sel * 4, (size_t)cap_sel * 4, nblk * 4,
+    const size_t sizes[10] = {
+        (size_t)cap_sel * 4, (size_t)cap_sel * 4, (size_t)cap_sel * 8, nblk * 4,
         (size_t)cap_pairs * 4, (size_t)cap_pairs * 4,
         (size_t)256 * (size_t)(ht + 1) * 4, (size_t)256 * 4, nblk * 4, 4};
-    uint32_t** dst[11] = {&w->dkey0, &w->dval0, &w->dkey1, &w->dval1, &w->bsum, &w->kalt, &w->valt, &w->hist,
+    uint32_t** dst[10] = {&w->dkey0, &w->dval0, &w->dkey1, &w->bsum, &w->kalt, &w->valt, &w->hist,
                           &w->digit_total, &w->vcnt, &w->n_vis};
     size_t off = 0;
-    for (int i = 0; i < 11; i++) {
+    for (int i = 0; i < 10; i++) {
         if (base) *dst[i] = (uint32_t*)((char*)base + off);
         off += align_up(sizes[i] + 4);
+    }
+    if (base) {
+        w->dval1 = w->dkey1 + cap_sel;
+        w->rect_d = reinterpret_cast<ushort4*>(w->dkey1);
     }
     return off;
 }
@@ -537,17 +557,16 @@ extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t c
                       even ? w.dval1 : w.dval0, w.n_vis, cap_sel, 8 * p, w, s);
     }
     // 2. tile counts in depth order and key emission
-    hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)gb), dim3(kThreads), 0, s, w.dval0, splats->tiles, w.n_vis,
-                       cap_sel, w.bsum);
+    hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)gb), dim3(kThreads), 0, s, w.dval0,
+                       (const ushort4*)splats->rect, w.n_vis, cap_sel, w.bsum, w.rect_d);
     int tile_bits = 1;
     while (tile_bits < 32 && (max_tile >> tile_bits) != 0) ++tile_bits;
     const int passes = (tile_bits + bits - 1) / bits;
     // emit into the buffer that the last pass will not write
     uint32_t* ek = cap_pairs == 0 ? nullptr : (passes % 2) ? w.kalt : tile_keys;
     uint32_t* ev = cap_pairs == 0 ? nullptr : (passes % 2) ? w.valt : vals;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)gb), dim3(kThreads), 0, s, w.dval0, splats->tiles,
-                       (const ushort4*)splats->rect, w.n_vis, cap_sel, w.bsum, cap_pairs, Wt, cam->tile_base, ek, ev,
-                       n_pairs, status);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)gb), dim3(kThreads), 0, s, w.dval0, w.rect_d, w.n_vis, cap_sel,
+                       w.bsum, cap_pairs, Wt, cam->tile_base, ek, ev, n_pairs, status);
     if (cap_pairs > 0) {
         // 3. stable sort of the pairs by tile id
         uint32_t *ka = ek, *va = ev, *kb = (ek == tile_keys) ? w.kalt : tile_keys, *vb = (ev == vals) ? w.valt : vals;

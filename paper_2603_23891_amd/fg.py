@@ -61,7 +61,7 @@ class FgGrads(C.Structure):
 
 class FgTune(C.Structure):
     _fields_ = [("render_batch", C.c_int32), ("radix_bits", C.c_int32), ("save_state", C.c_int32),
-                ("reserved1", C.c_int32), ("blend_events", C.c_void_p * 2)]
+                ("mask_items", C.c_int32), ("blend_events", C.c_void_p * 2)]
 
 
 EXPORTS = ["fg_filter_workspace_size", "fg_filter", "fg_preprocess", "fg_sort_workspace_size", "fg_sort",
@@ -137,10 +137,12 @@ def camera_struct(cam) -> FgCamera:
     return c
 
 
-def tune_struct(render_batch: int = 0, radix_bits: int = 0, save_state: bool = False, blend_events=None) -> FgTune:
+def tune_struct(render_batch: int = 0, radix_bits: int = 0, save_state: bool = False, blend_events=None,
+                mask_items: int = 0) -> FgTune:
     """blend_events: None, or two recorded torch.cuda.Event (timing enabled)
     that fg_render records around its blend kernel."""
-    t = FgTune(render_batch=render_batch, radix_bits=radix_bits, save_state=1 if save_state else 0, reserved1=0)
+    t = FgTune(render_batch=render_batch, radix_bits=radix_bits, save_state=1 if save_state else 0,
+               mask_items=mask_items)
     if blend_events is not None:
         t.blend_events[0] = blend_events[0].cuda_event
         t.blend_events[1] = blend_events[1].cuda_event
@@ -276,7 +278,7 @@ class FrameBuffers:
         self.sort_ws = torch.empty(fg_sort_workspace_size(self.cap_sel, self.cap_pairs, _C), dtype=torch.uint8,
                                    device=device)
         rw = max(fg_render_workspace_size(_C, self.cap_pairs, tune_struct(c, save_state=save_state))
-                 for c in (256, 512, 1024))
+                 for c in (128, 256, 512))
         self.render_ws = torch.empty(rw, dtype=torch.uint8, device=device)
         self.image = torch.empty((3, height, width), dtype=torch.float32, device=device)
         self.final_T = torch.empty((height, width), dtype=torch.float32, device=device)

@@ -73,7 +73,7 @@ def test_workspace_sizes_are_monotone_and_reject_bad_sizes():
     s2 = fg.fg_sort_workspace_size(100000, 500000, cam)
     assert 0 < s1 < s2
     assert fg.fg_sort_workspace_size(-1, 5, cam) == 0
-    r = [fg.fg_render_workspace_size(cam, 1 << 20, fg.tune_struct(k)) for k in (256, 512, 1024)]
+    r = [fg.fg_render_workspace_size(cam, 1 << 20, fg.tune_struct(k)) for k in (128, 256, 512)]
     assert all(x > 0 for x in r)
     assert fg.fg_render_workspace_size(cam, -1) == 0
     assert fg.lib().fg_render_backward_workspace_size(1000) >= 1000 * 9 * 4

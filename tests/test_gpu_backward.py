@@ -22,7 +22,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2603_23891_amd import diff, synth
+from paper_2603_23891_amd import diff, fg, synth
 from tests.test_oracle_backward import make_params, perturbed
 
 pytestmark = pytest.mark.gpu
@@ -33,9 +33,11 @@ def to_dev(prm):
     return [torch.from_numpy(a.copy()).cuda() for a in prm.keep]
 
 
-def gpu_fwd_bwd(prm, cam, w, tau=0.0, bg=(0.0, 0.0, 0.0)):
+def gpu_fwd_bwd(prm, cam, w, tau=0.0, bg=(0.0, 0.0, 0.0), tune=None):
     args = to_dev(prm)
     r = diff.GaussianRenderer(prm.m, prm.sh_degree, cam.width, cam.height, cap_pairs=1 << 20)
+    if tune is not None:
+        r.tune = tune
     img = r.forward(*args, cam, tau, bg).clone()
     g = r.backward(*args, cam, torch.from_numpy(w.astype(np.float32)).cuda(), bg)
     torch.cuda.synchronize()
@@ -137,17 +139,20 @@ def heavy_params(seed, m, opacity_logit_mu):
     return oracle.ParamsRef(mean.T, log_scale.T, quat.T, logit, sh, 3), cam, rng
 
 
-@pytest.mark.parametrize("mu", [-3.0, 0.5])
-def test_backward_long_ranges_from_saved_chunk_state(mu):
+@pytest.mark.parametrize("mu,chunk,mask_items", [(-3.0, 256, 0), (0.5, 256, 0), (-3.0, 128, 3), (0.5, 512, 2)])
+def test_backward_long_ranges_from_saved_chunk_state(mu, chunk, mask_items):
     """Translucent (pixels never saturate: every chunk blends) and opaque
     (pixels stop inside a later chunk) variants; gradients against the
-    float64 oracle at the same bar, forward bit-exact."""
+    float64 oracle at the same bar, forward bit-exact. With mask_items > 0
+    only the first chunks have stored masks and saved state: the tiles past
+    them are walked whole by the backward."""
     prm, cam, rng = heavy_params(21, 9000, mu)
     fwd = oracle.forward32(prm, cam)
     lens = np.diff(fwd["ranges"], axis=1).ravel()
-    assert lens.max() > 1024  # several 512-splat chunks per tile
+    assert lens.max() > 1024  # several chunks per tile
     w = rng.normal(0, 1, (3, cam.height, cam.width))
-    img, g_gpu, _ = gpu_fwd_bwd(prm, cam, w)
+    tune = fg.tune_struct(chunk, save_state=True, mask_items=mask_items)
+    img, g_gpu, _ = gpu_fwd_bwd(prm, cam, w, tune=tune)
     assert np.array_equal(img, fwd["image"])
     _, g64 = oracle.replay64(prm, cam, fwd, dL_dimage=w, want_image=False)
     check_grads(g_gpu, g64)

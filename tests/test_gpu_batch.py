@@ -143,7 +143,7 @@ def test_autotune_identical_outputs_and_cache(dtree, tmp_path):
     cams = views(3, seed=11)
     br = batch.BatchedRenderer(dtree, cams, cap_sel=TREE.n_nodes, cap_pairs=1 << 21)
     path = str(tmp_path / "tune.json")
-    res = batch.autotune(br, 3.0, 0.0, chunks=(256, 512, 1024), radix_bits=(4, 6, 8), repeats=1,
+    res = batch.autotune(br, 3.0, 0.0, chunks=(128, 256, 512), radix_bits=(4, 6, 8), repeats=1,
                          cache_path=path, cache_key="block40k")
     assert not res["from_cache"] and len(res["candidates"]) == 9
     with open(path) as f:
