@@ -6,18 +6,23 @@
 // stop (T < 1e-4) and the colour sum run sequentially. Tiles near a horizon
 // can hold ~10^4 splats whose pixels seldom saturate, so one workgroup that
 // tests every (pixel, splat) of such a tile would leave the frame waiting on
-// it. The blend therefore runs in two launches:
+// it. The blend therefore runs in two main launches:
 //
 //   k_masks   every chunk of CHUNK splats of a "heavy" tile (more than CHUNK
 //             splats) is one work item: per-pixel bit masks of the splats
 //             whose alpha passes the skip tests there go to global memory.
 //             All chunks run in parallel.
-//   k_render  one workgroup per tile (heavy tiles first, tiles claimed from an
-//             atomic ticket): one pixel per lane walks the tile's splats in
-//             list order, chunk by chunk, visiting only the marked ones and
-//             recomputing alpha with the same expressions, so every value and
-//             decision is bit-identical to one sequential pass. Light tiles
-//             compute their single chunk's masks in place.
+//   k_render  one workgroup per tile that holds splats (heavy tiles first,
+//             tiles claimed from an atomic ticket): one pixel per lane walks
+//             the tile's splats in list order, chunk by chunk, visiting only
+//             the marked ones and recomputing alpha with the same
+//             expressions, so every value and decision is bit-identical to
+//             one sequential pass. Light tiles compute their single chunk's
+//             masks in place. In a heavy tile each wave walks the chunks for
+//             its own 64 pixels at its own pace.
+//
+// Before them, k_tile_prep counts each tile's chunks and writes the pixels of
+// tiles with no splats (background, T = 1), and k_schedule orders the others.
 //
 // Masks are computed over the (splat, pixel) pairs inside a conservative box
 // per splat (the pixels where its skip test can pass), split evenly over the
@@ -42,11 +47,11 @@ constexpr float kSkipPower = -5.6f;
 constexpr int kPairSplats = 128;
 
 struct RenderWs {
-    uint32_t* nch;        // [n_tiles] chunks per tile
+    uint32_t* nch;        // [n_tiles] chunks per tile (0: no splats)
     uint32_t* mfirst;     // [n_tiles] first mask item of a heavy tile
     uint32_t* order;      // [n_tiles] tiles in processing order, heavy first
     uint32_t* mitem;      // [max_mask_items] mask item -> tile
-    uint32_t* counters;   // [0] ticket, [1] heavy tiles, [2] mask items (clamped)
+    uint32_t* counters;   // [0] ticket, [1] heavy tiles, [2] mask items (clamped), [3] tiles with splats
     uint32_t* masks;      // [max_mask_items][CHUNK/32][256]
     float* state;         // with save_state: [max_mask_items][4][256] T, C0, C1, C2 after each chunk; else null
 };
@@ -55,90 +60,137 @@ struct Frag {
     unsigned n_eval, n_exp, n_pass, n_blend;
 };
 
+// One workgroup per tile: the tile's chunk count (0 for a tile with no
+// splats), and the final values of an empty tile's pixels (background, T = 1,
+// no contributor), so that the blend never visits it.
 template <int CHUNK>
-__global__ __launch_bounds__(kThreads) void k_chunk_count(const uint32_t* __restrict__ ranges, int64_t n_tiles,
-                                                          uint32_t* __restrict__ nch)
+__global__ __launch_bounds__(kThreads) void k_tile_prep(const uint32_t* __restrict__ ranges, int64_t n_tiles, int W,
+                                                        int H, int Wt, float bg0, float bg1, float bg2,
+                                                        uint32_t* __restrict__ nch, float* __restrict__ image,
+                                                        float* __restrict__ final_T,
+                                                        uint32_t* __restrict__ n_contrib)
 {
-    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (t < n_tiles) {
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const uint32_t L = ranges[2 * t + 1] - ranges[2 * t];
-        nch[t] = L == 0 ? 1u : (L + CHUNK - 1) / CHUNK;
+        if (threadIdx.x == 0) nch[t] = (L + CHUNK - 1) / CHUNK;
+        if (L == 0) {
+            const int px = (int)(t % Wt) * fgd::kTile + (int)threadIdx.x % fgd::kTile;
+            const int py = (int)(t / Wt) * fgd::kTile + (int)threadIdx.x / fgd::kTile;
+            if (px < W && py < H) {
+                const size_t o = (size_t)py * W + px;
+                const size_t plane = (size_t)W * H;
+                image[o] = bg0;
+                image[plane + o] = bg1;
+                image[2 * plane + o] = bg2;
+                final_T[o] = 1.0f;
+                n_contrib[o] = 0u;
+            }
+        }
     }
 }
 
-// One workgroup: orders the tiles (heavy ones first, each group in tile
-// order), numbers the mask items of heavy tiles and resets the ticket.
-// 8 consecutive tiles per thread per round; two running counts (heavy tiles,
-// mask items) are scanned together in one 64-bit word; a light tile's place
-// is its index minus the heavy tiles before it.
+// One workgroup: orders the tiles that hold splats (heavy ones first, each
+// group in tile order), numbers the mask items of heavy tiles and resets the
+// ticket. 8 consecutive tiles per thread per round; the running counts of
+// heavy and light tiles (one 64-bit word) and of mask items are scanned
+// together.
 __global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __restrict__ nch, int64_t n_tiles,
                                                            int64_t max_mask_items, uint32_t* __restrict__ mfirst,
                                                            uint32_t* __restrict__ order, uint32_t* __restrict__ mitem,
                                                            uint32_t* __restrict__ counters)
 {
     __shared__ unsigned long long s_wave[kScanThreads / fgd::kWave];
+    __shared__ uint32_t s_wave_m[kScanThreads / fgd::kWave];
     __shared__ unsigned long long s_carry;
+    __shared__ uint32_t s_carry_m;
     __shared__ uint32_t s_heavy_total;
     const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
     // pass 0 counts the heavy tiles (light tiles are placed after them), pass 1 places
     for (int pass = 0; pass < 2; pass++) {
-        if (tid == 0) s_carry = 0ull;
+        if (tid == 0) {
+            s_carry = 0ull;
+            s_carry_m = 0u;
+        }
         __syncthreads();
         const uint32_t heavy_total = pass ? s_heavy_total : 0u;
         for (int64_t base = 0; base < n_tiles; base += 8 * kScanThreads) {
             uint32_t c[8];
-            unsigned long long sum = 0;  // low 32: heavy tiles, high 32: mask items
+            unsigned long long sum = 0;  // low 32: heavy tiles, high 32: light tiles
+            uint32_t msum = 0;           // mask items
 #pragma unroll
             for (int k = 0; k < 8; k++) {
                 const int64_t t = base + (int64_t)tid * 8 + k;
-                c[k] = t < n_tiles ? nch[t] : 1u;
-                if (c[k] > 1) sum += 1ull | ((unsigned long long)c[k] << 32);
+                c[k] = t < n_tiles ? nch[t] : 0u;
+                if (c[k] > 1) {
+                    sum += 1ull;
+                    msum += c[k];
+                } else if (c[k] == 1) {
+                    sum += 1ull << 32;
+                }
             }
             unsigned long long x = sum;
+            uint32_t xm = msum;
 #pragma unroll
             for (int d = 1; d < fgd::kWave; d <<= 1) {
                 const unsigned long long y = __shfl_up(x, d, fgd::kWave);
-                if (lane >= d) x += y;
+                const uint32_t ym = __shfl_up(xm, d, fgd::kWave);
+                if (lane >= d) {
+                    x += y;
+                    xm += ym;
+                }
             }
-            if (lane == fgd::kWave - 1) s_wave[wave] = x;
+            if (lane == fgd::kWave - 1) {
+                s_wave[wave] = x;
+                s_wave_m[wave] = xm;
+            }
             __syncthreads();
             unsigned long long before = s_carry, total = 0;
+            uint32_t before_m = s_carry_m, total_m = 0;
             for (int w = 0; w < kScanThreads / fgd::kWave; w++) {
-                if (w < wave) before += s_wave[w];
+                if (w < wave) {
+                    before += s_wave[w];
+                    before_m += s_wave_m[w];
+                }
                 total += s_wave[w];
+                total_m += s_wave_m[w];
             }
             if (pass) {
                 unsigned long long run = before + x - sum;
+                uint32_t mf = before_m + xm - msum;  // mask items before t
 #pragma unroll
                 for (int k = 0; k < 8; k++) {
                     const int64_t t = base + (int64_t)tid * 8 + k;
-                    if (t < n_tiles) {
-                        const uint32_t hv = (uint32_t)run;          // heavy tiles before t
-                        const uint32_t mf = (uint32_t)(run >> 32);  // mask items before t
+                    if (t < n_tiles && c[k] > 0) {
                         if (c[k] > 1) {
-                            order[hv] = (uint32_t)t;
+                            order[(uint32_t)run] = (uint32_t)t;  // heavy tiles before t
                             mfirst[t] = mf;
                             for (uint32_t i = 0; i < c[k]; i++)
                                 if ((int64_t)(mf + i) < max_mask_items) mitem[mf + i] = (uint32_t)t;
-                            run += 1ull | ((unsigned long long)c[k] << 32);
+                            run += 1ull;
+                            mf += c[k];
                         } else {
-                            order[heavy_total + (uint32_t)(t - hv)] = (uint32_t)t;
+                            order[heavy_total + (uint32_t)(run >> 32)] = (uint32_t)t;  // light tiles before t
+                            run += 1ull << 32;
                         }
                     }
                 }
             }
             __syncthreads();
-            if (tid == 0) s_carry += total;
+            if (tid == 0) {
+                s_carry += total;
+                s_carry_m += total_m;
+            }
             __syncthreads();
         }
         if (tid == 0) {
             if (!pass) {
                 s_heavy_total = (uint32_t)s_carry;
             } else {
-                const uint32_t items = (uint32_t)(s_carry >> 32);
+                const uint32_t items = s_carry_m;
                 counters[0] = 0u;
                 counters[1] = (uint32_t)s_carry;
                 counters[2] = (int64_t)items < max_mask_items ? items : (uint32_t)max_mask_items;
+                counters[3] = (uint32_t)s_carry + (uint32_t)(s_carry >> 32);
             }
         }
         __syncthreads();
@@ -584,12 +636,13 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
     const int tid = threadIdx.x;
     const int lx = tid % fgd::kTile, ly = tid / fgd::kTile;
     const uint32_t n_mask_items = ws.counters[2];
+    const uint32_t n_work = ws.counters[3];
     Frag f = {0, 0, 0, 0};
     if (tid == 0) s_item = atomicAdd(&ws.counters[0], 1u);
     __syncthreads();
     for (;;) {
         const uint32_t item = s_item;
-        if ((int64_t)item >= n_tiles) break;
+        if (item >= n_work) break;
         const uint32_t tile = ws.order[item];
         const uint32_t r0 = ranges[2 * tile], r1 = ranges[2 * tile + 1];
         const uint32_t nch = ws.nch[tile];
@@ -750,8 +803,9 @@ void launch(const fg_splats* splats, const uint32_t* vals, const uint32_t* range
             const RenderWs& w, int64_t n_tiles, int64_t max_mask_items, const fg_tune* tune, hipStream_t s)
 {
     const int Wt = (cam->width + 15) / 16;
-    hipLaunchKernelGGL(k_chunk_count<CHUNK>, dim3((unsigned)((n_tiles + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                       s, ranges, n_tiles, w.nch);
+    const unsigned gp = (unsigned)(n_tiles < 65536 ? n_tiles : 65536);
+    hipLaunchKernelGGL(k_tile_prep<CHUNK>, dim3(gp), dim3(kThreads), 0, s, ranges, n_tiles, cam->width, cam->height,
+                       Wt, bg[0], bg[1], bg[2], w.nch, image, final_T, n_contrib);
     hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kScanThreads), 0, s, w.nch, n_tiles, max_mask_items, w.mfirst,
                        w.order, w.mitem, w.counters);
     const float2* xy = (const float2*)splats->xy;
