@@ -25,8 +25,9 @@
 //              2048-node tile and view.
 //   k_tile_scan  exclusive prefix sum of the tile counts (one workgroup per
 //              view) and n_sel.
-//   k_compact  per tile and view: the selected ids in ascending order at the
-//              tile's offset, from the selection words (256 bytes per tile).
+//   k_compact  one wave per tile and view: the selected ids in ascending
+//              order at the tile's offset, from the selection words (256
+//              bytes per tile).
 //
 // Stream compaction is thus reduce-then-scan in three launches. A single-pass
 // scan with decoupled look-back (Merrill & Garland 2016) was measured first:
@@ -241,7 +242,8 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
 }
 
 // One workgroup per view: tile_cnt[v][0 .. n_tiles) becomes its exclusive
-// prefix sum in place; n_sel[v] = the total.
+// prefix sum in place; n_sel[v] = the total. Each thread takes a run of
+// consecutive tiles, read 8 at a time with independent loads.
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t* __restrict__ tile_cnt, int64_t n_tiles,
                                                             uint32_t* __restrict__ n_sel, int64_t cap_sel,
                                                             uint32_t* __restrict__ status)
@@ -252,7 +254,13 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t* __restrict
     const int64_t per = (n_tiles + kScanThreads - 1) / kScanThreads;
     const int64_t lo = tid * per, hi = lo + per < n_tiles ? lo + per : n_tiles;
     uint32_t s = 0;
-    for (int64_t i = lo; i < hi; i++) s += row[i];
+    for (int64_t i0 = lo; i0 < hi; i0 += 8) {
+        uint32_t c[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) c[u] = i0 + u < hi ? row[i0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 8; u++) s += c[u];
+    }
     uint32_t x = s;
 #pragma unroll
     for (int d = 1; d < fgd::kWave; d <<= 1) {
@@ -266,10 +274,15 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t* __restrict
         if (w < wave) run += s_wave[w];
         total += s_wave[w];
     }
-    for (int64_t i = lo; i < hi; i++) {
-        const uint32_t c = row[i];
-        row[i] = run;
-        run += c;
+    for (int64_t i0 = lo; i0 < hi; i0 += 8) {
+        uint32_t c[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) c[u] = i0 + u < hi ? row[i0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            if (i0 + u < hi) row[i0 + u] = run;
+            run += c[u];
+        }
     }
     if (tid == 0) {
         n_sel[blockIdx.x] = total;
@@ -277,57 +290,50 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t* __restrict
     }
 }
 
-// Workgroup (tile, view): the selected ids of the tile's nodes, in ascending
-// order, at the tile's offset. Each wave reads the 64-bit selection word of
-// its 64-node groups; group offsets within the tile are a wave scan.
+// One wave per (tile, view): the selected ids of the tile's nodes, in
+// ascending order, at the tile's offset. Lane g reads the 64-bit selection
+// word of the tile's 64-node group g; a wave scan of their popcounts gives
+// each group's offset; then group by group the set lanes write their ids.
+constexpr int kGroups = kTileNodes / fgd::kWave;  // 64-node groups per tile
+static_assert(kGroups <= fgd::kWave, "one lane per group");
+
 __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__ sel_bits, int64_t sel_words,
                                                     int64_t N, const uint32_t* __restrict__ tile_off,
                                                     int64_t n_tiles, uint32_t* __restrict__ sel_idx,
                                                     int64_t cap_sel)
 {
-    __shared__ uint32_t s_off[kRounds * kWaves];
-    const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
-    const int64_t tile = blockIdx.x;
+    const int lane = fgd::lane_id();
+    const int64_t tile = (int64_t)blockIdx.x * kWaves + threadIdx.x / fgd::kWave;
     const int v = blockIdx.y;
+    if (tile >= n_tiles) return;
     const uint32_t* bits = sel_bits + (int64_t)v * sel_words;
-    uint64_t ball[kRounds];
-#pragma unroll
-    for (int r = 0; r < kRounds; r++) {
-        const int64_t base = tile * kTileNodes + r * kBlock + wave * fgd::kWave;  // multiple of 64
-        uint64_t b = 0;
+    uint64_t b = 0;
+    if (lane < kGroups) {
+        const int64_t base = tile * kTileNodes + (int64_t)lane * fgd::kWave;  // multiple of 64
         if (base < N) {
             b = bits[base >> 5];
             if (base + 32 < N) b |= (uint64_t)bits[(base >> 5) + 1] << 32;
         }
-        ball[r] = b;
-        if (lane == 0) s_off[r * kWaves + wave] = (uint32_t)__popcll(b);
     }
-    __syncthreads();
-    if (wave == 0) {
-        uint32_t agg = 0;
+    const uint32_t c = (uint32_t)__popcll(b);
+    uint32_t x = c;
 #pragma unroll
-        for (int g0 = 0; g0 < kRounds * kWaves; g0 += fgd::kWave) {
-            const bool in = g0 + lane < kRounds * kWaves;
-            const uint32_t c = in ? s_off[g0 + lane] : 0u;
-            uint32_t x = c;
-#pragma unroll
-            for (int d = 1; d < fgd::kWave; d <<= 1) {
-                const uint32_t y = __shfl_up(x, d, fgd::kWave);
-                if (lane >= d) x += y;
-            }
-            if (in) s_off[g0 + lane] = agg + x - c;
-            agg += __shfl(x, fgd::kWave - 1, fgd::kWave);
-        }
+    for (int d = 1; d < fgd::kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, fgd::kWave);
+        if (lane >= d) x += y;
     }
-    __syncthreads();
-    const uint32_t base_off = tile_off[(int64_t)v * n_tiles + tile];
+    const uint32_t excl = tile_off[(int64_t)v * n_tiles + tile] + x - c;
     const uint64_t lt = fgd::lanemask_lt();
     uint32_t* out = sel_idx + (int64_t)v * cap_sel;
-#pragma unroll
-    for (int r = 0; r < kRounds; r++) {
-        if ((ball[r] >> lane) & 1ull) {
-            const uint32_t off = base_off + s_off[r * kWaves + wave] + (uint32_t)__popcll(ball[r] & lt);
-            if ((int64_t)off < cap_sel) out[off] = (uint32_t)(tile * kTileNodes + r * kBlock + tid);
+    const uint32_t lo = (uint32_t)b, hi = (uint32_t)(b >> 32);
+#pragma unroll 4
+    for (int g = 0; g < kGroups; g++) {
+        const uint64_t gb = (uint64_t)(uint32_t)__shfl((int)lo, g, fgd::kWave) |
+                            ((uint64_t)(uint32_t)__shfl((int)hi, g, fgd::kWave) << 32);
+        const uint32_t off = (uint32_t)__shfl((int)excl, g, fgd::kWave);
+        if ((gb >> lane) & 1ull) {
+            const uint32_t o = off + (uint32_t)__popcll(gb & lt);
+            if ((int64_t)o < cap_sel) out[o] = (uint32_t)(tile * kTileNodes + (int64_t)g * fgd::kWave + lane);
         }
     }
 }
@@ -372,8 +378,8 @@ void launch_pass(const fg_tree* tree, const CamSet& cs, int nv, float tau_R, uin
     hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)nv), dim3(kScanThreads), 0, s, w.tile_cnt, n_tiles, n_sel,
                        cap_sel, status);
     if (cap_sel > 0)
-        hipLaunchKernelGGL(k_compact, dim3((unsigned)n_tiles, (unsigned)nv), dim3(kBlock), 0, s, sel_bits, sel_words,
-                           N, w.tile_cnt, n_tiles, sel_idx, cap_sel);
+        hipLaunchKernelGGL(k_compact, dim3((unsigned)((n_tiles + kWaves - 1) / kWaves), (unsigned)nv), dim3(kBlock), 0,
+                           s, sel_bits, sel_words, N, w.tile_cnt, n_tiles, sel_idx, cap_sel);
 }
 
 }  // namespace

@@ -89,11 +89,13 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const uint32_t* __restri
     }
 }
 
-// One workgroup: orders the tiles that hold splats (heavy ones first, each
-// group in tile order), numbers the mask items of heavy tiles and resets the
-// ticket. 8 consecutive tiles per thread per round; the running counts of
-// heavy and light tiles (one 64-bit word) and of mask items are scanned
-// together.
+// One workgroup, one pass: lists the tiles that hold splats, heavy ones from
+// the front of order[] in tile order and light ones from its back in reverse
+// tile order, numbers the mask items of heavy tiles and resets the ticket.
+// Work item i of the blend is order[i] for i < heavy tiles, else
+// order[n_tiles - 1 - (i - heavy tiles)]. 8 consecutive tiles per thread per
+// round; the running counts of heavy and light tiles (one 64-bit word) and of
+// mask items are scanned together.
 __global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __restrict__ nch, int64_t n_tiles,
                                                            int64_t max_mask_items, uint32_t* __restrict__ mfirst,
                                                            uint32_t* __restrict__ order, uint32_t* __restrict__ mitem,
@@ -103,97 +105,85 @@ __global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __res
     __shared__ uint32_t s_wave_m[kScanThreads / fgd::kWave];
     __shared__ unsigned long long s_carry;
     __shared__ uint32_t s_carry_m;
-    __shared__ uint32_t s_heavy_total;
     const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
-    // pass 0 counts the heavy tiles (light tiles are placed after them), pass 1 places
-    for (int pass = 0; pass < 2; pass++) {
-        if (tid == 0) {
-            s_carry = 0ull;
-            s_carry_m = 0u;
+    if (tid == 0) {
+        s_carry = 0ull;
+        s_carry_m = 0u;
+    }
+    __syncthreads();
+    for (int64_t base = 0; base < n_tiles; base += 8 * kScanThreads) {
+        uint32_t c[8];
+        unsigned long long sum = 0;  // low 32: heavy tiles, high 32: light tiles
+        uint32_t msum = 0;           // mask items
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int64_t t = base + (int64_t)tid * 8 + k;
+            c[k] = t < n_tiles ? nch[t] : 0u;
+            if (c[k] > 1) {
+                sum += 1ull;
+                msum += c[k];
+            } else if (c[k] == 1) {
+                sum += 1ull << 32;
+            }
+        }
+        unsigned long long x = sum;
+        uint32_t xm = msum;
+#pragma unroll
+        for (int d = 1; d < fgd::kWave; d <<= 1) {
+            const unsigned long long y = __shfl_up(x, d, fgd::kWave);
+            const uint32_t ym = __shfl_up(xm, d, fgd::kWave);
+            if (lane >= d) {
+                x += y;
+                xm += ym;
+            }
+        }
+        if (lane == fgd::kWave - 1) {
+            s_wave[wave] = x;
+            s_wave_m[wave] = xm;
         }
         __syncthreads();
-        const uint32_t heavy_total = pass ? s_heavy_total : 0u;
-        for (int64_t base = 0; base < n_tiles; base += 8 * kScanThreads) {
-            uint32_t c[8];
-            unsigned long long sum = 0;  // low 32: heavy tiles, high 32: light tiles
-            uint32_t msum = 0;           // mask items
+        unsigned long long before = s_carry, total = 0;
+        uint32_t before_m = s_carry_m, total_m = 0;
+        for (int w = 0; w < kScanThreads / fgd::kWave; w++) {
+            if (w < wave) {
+                before += s_wave[w];
+                before_m += s_wave_m[w];
+            }
+            total += s_wave[w];
+            total_m += s_wave_m[w];
+        }
+        unsigned long long run = before + x - sum;
+        uint32_t mf = before_m + xm - msum;  // mask items before t
 #pragma unroll
-            for (int k = 0; k < 8; k++) {
-                const int64_t t = base + (int64_t)tid * 8 + k;
-                c[k] = t < n_tiles ? nch[t] : 0u;
+        for (int k = 0; k < 8; k++) {
+            const int64_t t = base + (int64_t)tid * 8 + k;
+            if (t < n_tiles && c[k] > 0) {
                 if (c[k] > 1) {
-                    sum += 1ull;
-                    msum += c[k];
-                } else if (c[k] == 1) {
-                    sum += 1ull << 32;
+                    order[(uint32_t)run] = (uint32_t)t;  // heavy tiles before t
+                    mfirst[t] = mf;
+                    for (uint32_t i = 0; i < c[k]; i++)
+                        if ((int64_t)(mf + i) < max_mask_items) mitem[mf + i] = (uint32_t)t;
+                    run += 1ull;
+                    mf += c[k];
+                } else {
+                    order[n_tiles - 1 - (int64_t)(run >> 32)] = (uint32_t)t;  // light tiles before t
+                    run += 1ull << 32;
                 }
-            }
-            unsigned long long x = sum;
-            uint32_t xm = msum;
-#pragma unroll
-            for (int d = 1; d < fgd::kWave; d <<= 1) {
-                const unsigned long long y = __shfl_up(x, d, fgd::kWave);
-                const uint32_t ym = __shfl_up(xm, d, fgd::kWave);
-                if (lane >= d) {
-                    x += y;
-                    xm += ym;
-                }
-            }
-            if (lane == fgd::kWave - 1) {
-                s_wave[wave] = x;
-                s_wave_m[wave] = xm;
-            }
-            __syncthreads();
-            unsigned long long before = s_carry, total = 0;
-            uint32_t before_m = s_carry_m, total_m = 0;
-            for (int w = 0; w < kScanThreads / fgd::kWave; w++) {
-                if (w < wave) {
-                    before += s_wave[w];
-                    before_m += s_wave_m[w];
-                }
-                total += s_wave[w];
-                total_m += s_wave_m[w];
-            }
-            if (pass) {
-                unsigned long long run = before + x - sum;
-                uint32_t mf = before_m + xm - msum;  // mask items before t
-#pragma unroll
-                for (int k = 0; k < 8; k++) {
-                    const int64_t t = base + (int64_t)tid * 8 + k;
-                    if (t < n_tiles && c[k] > 0) {
-                        if (c[k] > 1) {
-                            order[(uint32_t)run] = (uint32_t)t;  // heavy tiles before t
-                            mfirst[t] = mf;
-                            for (uint32_t i = 0; i < c[k]; i++)
-                                if ((int64_t)(mf + i) < max_mask_items) mitem[mf + i] = (uint32_t)t;
-                            run += 1ull;
-                            mf += c[k];
-                        } else {
-                            order[heavy_total + (uint32_t)(run >> 32)] = (uint32_t)t;  // light tiles before t
-                            run += 1ull << 32;
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            if (tid == 0) {
-                s_carry += total;
-                s_carry_m += total_m;
-            }
-            __syncthreads();
-        }
-        if (tid == 0) {
-            if (!pass) {
-                s_heavy_total = (uint32_t)s_carry;
-            } else {
-                const uint32_t items = s_carry_m;
-                counters[0] = 0u;
-                counters[1] = (uint32_t)s_carry;
-                counters[2] = (int64_t)items < max_mask_items ? items : (uint32_t)max_mask_items;
-                counters[3] = (uint32_t)s_carry + (uint32_t)(s_carry >> 32);
             }
         }
         __syncthreads();
+        if (tid == 0) {
+            s_carry += total;
+            s_carry_m += total_m;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const uint32_t items = s_carry_m;
+        counters[0] = 0u;
+        counters[1] = (uint32_t)s_carry;
+        counters[2] = (int64_t)items < max_mask_items ? items : (uint32_t)max_mask_items;
+        counters[3] = (uint32_t)s_carry + (uint32_t)(s_carry >> 32);
     }
 }
 
@@ -640,10 +630,11 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
     Frag f = {0, 0, 0, 0};
     if (tid == 0) s_item = atomicAdd(&ws.counters[0], 1u);
     __syncthreads();
+    const uint32_t n_heavy = ws.counters[1];
     for (;;) {
         const uint32_t item = s_item;
         if (item >= n_work) break;
-        const uint32_t tile = ws.order[item];
+        const uint32_t tile = ws.order[item < n_heavy ? (int64_t)item : n_tiles - 1 - (int64_t)(item - n_heavy)];
         const uint32_t r0 = ranges[2 * tile], r1 = ranges[2 * tile + 1];
         const uint32_t nch = ws.nch[tile];
         // Tiles are ordered heavy first, so a light tile is followed only by

@@ -122,13 +122,24 @@ __global__ __launch_bounds__(kThreads) void k_rowscan(const uint32_t* __restrict
     const int64_t lo = threadIdx.x * per;
     const int64_t hi = lo + per < n_tiles ? lo + per : n_tiles;
     uint32_t s = 0;
-    for (int64_t i = lo; i < hi; i++) s += row[i];
+    for (int64_t i0 = lo; i0 < hi; i0 += 4) {  // 4 independent loads per step
+        uint32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) c[u] = i0 + u < hi ? row[i0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; u++) s += c[u];
+    }
     uint32_t total;
     uint32_t run = block_excl_scan(s, s_wave, total);
-    for (int64_t i = lo; i < hi; i++) {
-        const uint32_t v = row[i];
-        row[i] = run;
-        run += v;
+    for (int64_t i0 = lo; i0 < hi; i0 += 4) {
+        uint32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) c[u] = i0 + u < hi ? row[i0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (i0 + u < hi) row[i0 + u] = run;
+            run += c[u];
+        }
     }
     if (threadIdx.x == 0) digit_total[blockIdx.x] = total;
 }
@@ -236,7 +247,13 @@ __device__ __forceinline__ unsigned long long block_prefix(const uint32_t* __res
                                                            unsigned long long* s_red)
 {
     unsigned long long x = 0;
-    for (int64_t i = threadIdx.x; i < k; i += kThreads) x += v[i];
+    for (int64_t i0 = threadIdx.x; i0 < k; i0 += 4 * kThreads) {  // 4 independent loads per step
+        uint32_t a[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) a[u] = i0 + u * kThreads < k ? v[i0 + u * kThreads] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; u++) x += a[u];
+    }
 #pragma unroll
     for (int d = fgd::kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, fgd::kWave);
     if (fgd::lane_id() == 0) s_red[threadIdx.x / fgd::kWave] = x;
