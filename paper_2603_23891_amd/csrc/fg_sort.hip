@@ -16,7 +16,7 @@
 // records to 2 passes over 8-byte records at 1080p.
 //
 // Radix pass (LSD, one digit of BITS bits, stable), three kernels:
-//   k_hist      per 2048-item tile: digit histogram -> hist[digit][tile]
+//   k_hist      per 1024-item tile: digit histogram -> hist[digit][tile]
 //   k_rowscan   one workgroup per digit: exclusive scan over the tiles,
 //               digit totals
 //   k_scatter   per tile: stable local ranks (wave ballot match on the digit
@@ -34,8 +34,8 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kIPT = 8;
-constexpr int kTileItems = kThreads * kIPT;  // 2048
+constexpr int kIPT = 4;
+constexpr int kTileItems = kThreads * kIPT;  // 1024
 constexpr int kWaves = kThreads / fgd::kWave;
 constexpr int kEmitIPT = 8;
 constexpr int kEmitItems = kThreads * kEmitIPT;  // 2048
@@ -265,7 +265,7 @@ __device__ __forceinline__ unsigned long long block_prefix(const uint32_t* __res
     return t;
 }
 
-// Per 2048 splats (index order): how many cover at least one tile. Also
+// Per 1024 splats (index order): how many cover at least one tile. Also
 // clears the tile ranges of this view.
 __global__ __launch_bounds__(kThreads) void k_vis_count(const uint32_t* __restrict__ tiles,
                                                         const uint32_t* __restrict__ n_p, int64_t cap,
@@ -291,7 +291,9 @@ __global__ __launch_bounds__(kThreads) void k_vis_count(const uint32_t* __restri
 }
 
 // Packs the splats that cover a tile, in index order: dkey = depth bits,
-// dval = splat index; *n_vis = their number.
+// dval = splat index; *n_vis = their number. A block's packed run is
+// assembled in LDS, then written with consecutive lanes on consecutive
+// addresses.
 __global__ __launch_bounds__(kThreads) void k_vis_pack(const float4* __restrict__ rgb_depth,
                                                        const uint32_t* __restrict__ tiles,
                                                        const uint32_t* __restrict__ n_p, int64_t cap,
@@ -300,6 +302,8 @@ __global__ __launch_bounds__(kThreads) void k_vis_pack(const float4* __restrict_
 {
     __shared__ uint32_t s_wave[kWaves];
     __shared__ unsigned long long s_red[kWaves];
+    __shared__ uint32_t s_k[kTileItems];
+    __shared__ uint32_t s_v[kTileItems];
     const int64_t n = count_of(n_p, cap);
     const int64_t nblk = (n + kTileItems - 1) / kTileItems;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
@@ -313,15 +317,21 @@ __global__ __launch_bounds__(kThreads) void k_vis_pack(const float4* __restrict_
             c += vis[r] ? 1u : 0u;
         }
         uint32_t total;
-        uint64_t off = base + block_excl_scan(c, s_wave, total);
+        uint32_t off = block_excl_scan(c, s_wave, total);
 #pragma unroll
         for (int r = 0; r < kIPT; r++) {
             if (vis[r]) {
-                dkey[off] = __float_as_uint(rgb_depth[j0 + r].w);
-                dval[off] = (uint32_t)(j0 + r);
+                s_k[off] = __float_as_uint(rgb_depth[j0 + r].w);
+                s_v[off] = (uint32_t)(j0 + r);
                 ++off;
             }
         }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < total; i += kThreads) {
+            dkey[base + i] = s_k[i];
+            dval[base + i] = s_v[i];
+        }
+        __syncthreads();
     }
     if (blockIdx.x == 0) {
         const unsigned long long t = block_prefix(vcnt, nblk, s_red);
@@ -500,7 +510,7 @@ void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32
                 int64_t cap, int shift, const SortWs& w, hipStream_t s)
 {
     int64_t grid = tiles_for(cap);
-    if (grid > 2048) grid = 2048;
+    if (grid > 4096) grid = 4096;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_hist<BITS>, dim3((unsigned)grid), dim3(kThreads), 0, s, kin, n_p, cap, shift, w.hist);
     hipLaunchKernelGGL(k_rowscan, dim3(1u << BITS), dim3(kThreads), 0, s, n_p, cap, w.hist, w.digit_total);
