@@ -21,8 +21,9 @@
 //             masks in place. In a heavy tile each wave walks the chunks for
 //             its own 64 pixels at its own pace.
 //
-// Before them, k_tile_prep counts each tile's chunks and writes the pixels of
-// tiles with no splats (background, T = 1), and k_schedule orders the others.
+// Before them, k_schedule counts each tile's chunks and orders the tiles that
+// hold splats, and k_tile_prep writes the pixels of the others (background,
+// T = 1) and maps mask items to their tiles.
 //
 // Masks are computed over the (splat, pixel) pairs inside a conservative box
 // per splat (the pixels where its skip test can pass), split evenly over the
@@ -60,20 +61,20 @@ struct Frag {
     unsigned n_eval, n_exp, n_pass, n_blend;
 };
 
-// One workgroup per tile: the tile's chunk count (0 for a tile with no
-// splats), and the final values of an empty tile's pixels (background, T = 1,
-// no contributor), so that the blend never visits it.
+// One workgroup per tile, after k_schedule: the final values of an empty
+// tile's pixels (background, T = 1, no contributor), so that the blend never
+// visits it, and the mask item -> tile map of a heavy tile's chunks.
 template <int CHUNK>
-__global__ __launch_bounds__(kThreads) void k_tile_prep(const uint32_t* __restrict__ ranges, int64_t n_tiles, int W,
-                                                        int H, int Wt, float bg0, float bg1, float bg2,
-                                                        uint32_t* __restrict__ nch, float* __restrict__ image,
+__global__ __launch_bounds__(kThreads) void k_tile_prep(int64_t n_tiles, int W, int H, int Wt, float bg0,
+                                                        float bg1, float bg2, const uint32_t* __restrict__ nch,
+                                                        const uint32_t* __restrict__ mfirst, int64_t max_mask_items,
+                                                        uint32_t* __restrict__ mitem, float* __restrict__ image,
                                                         float* __restrict__ final_T,
                                                         uint32_t* __restrict__ n_contrib)
 {
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        const uint32_t L = ranges[2 * t + 1] - ranges[2 * t];
-        if (threadIdx.x == 0) nch[t] = (L + CHUNK - 1) / CHUNK;
-        if (L == 0) {
+        const uint32_t c = nch[t];
+        if (c == 0) {
             const int px = (int)(t % Wt) * fgd::kTile + (int)threadIdx.x % fgd::kTile;
             const int py = (int)(t / Wt) * fgd::kTile + (int)threadIdx.x / fgd::kTile;
             if (px < W && py < H) {
@@ -85,20 +86,27 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const uint32_t* __restri
                 final_T[o] = 1.0f;
                 n_contrib[o] = 0u;
             }
+        } else if (c > 1) {
+            const uint32_t mf = mfirst[t];
+            for (uint32_t i = threadIdx.x; i < c; i += kThreads)
+                if ((int64_t)(mf + i) < max_mask_items) mitem[mf + i] = (uint32_t)t;
         }
     }
 }
 
-// One workgroup, one pass: lists the tiles that hold splats, heavy ones from
-// the front of order[] in tile order and light ones from its back in reverse
-// tile order, numbers the mask items of heavy tiles and resets the ticket.
+// One workgroup, one pass: each tile's chunk count (0 for a tile with no
+// splats); lists the tiles that hold splats, heavy ones from the front of
+// order[] in tile order and light ones from its back in reverse tile order;
+// numbers the mask items of heavy tiles (first item per tile) and resets the
+// ticket.
 // Work item i of the blend is order[i] for i < heavy tiles, else
 // order[n_tiles - 1 - (i - heavy tiles)]. 8 consecutive tiles per thread per
 // round; the running counts of heavy and light tiles (one 64-bit word) and of
 // mask items are scanned together.
-__global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __restrict__ nch, int64_t n_tiles,
-                                                           int64_t max_mask_items, uint32_t* __restrict__ mfirst,
-                                                           uint32_t* __restrict__ order, uint32_t* __restrict__ mitem,
+template <int CHUNK>
+__global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __restrict__ ranges, int64_t n_tiles,
+                                                           int64_t max_mask_items, uint32_t* __restrict__ nch,
+                                                           uint32_t* __restrict__ mfirst, uint32_t* __restrict__ order,
                                                            uint32_t* __restrict__ counters)
 {
     __shared__ unsigned long long s_wave[kScanThreads / fgd::kWave];
@@ -118,7 +126,8 @@ __global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __res
 #pragma unroll
         for (int k = 0; k < 8; k++) {
             const int64_t t = base + (int64_t)tid * 8 + k;
-            c[k] = t < n_tiles ? nch[t] : 0u;
+            c[k] = t < n_tiles ? (ranges[2 * t + 1] - ranges[2 * t] + CHUNK - 1) / CHUNK : 0u;
+            if (t < n_tiles) nch[t] = c[k];
             if (c[k] > 1) {
                 sum += 1ull;
                 msum += c[k];
@@ -161,8 +170,6 @@ __global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __res
                 if (c[k] > 1) {
                     order[(uint32_t)run] = (uint32_t)t;  // heavy tiles before t
                     mfirst[t] = mf;
-                    for (uint32_t i = 0; i < c[k]; i++)
-                        if ((int64_t)(mf + i) < max_mask_items) mitem[mf + i] = (uint32_t)t;
                     run += 1ull;
                     mf += c[k];
                 } else {
@@ -794,11 +801,12 @@ void launch(const fg_splats* splats, const uint32_t* vals, const uint32_t* range
             const RenderWs& w, int64_t n_tiles, int64_t max_mask_items, const fg_tune* tune, hipStream_t s)
 {
     const int Wt = (cam->width + 15) / 16;
+    hipLaunchKernelGGL(k_schedule<CHUNK>, dim3(1), dim3(kScanThreads), 0, s, ranges, n_tiles, max_mask_items, w.nch,
+                       w.mfirst, w.order, w.counters);
     const unsigned gp = (unsigned)(n_tiles < 65536 ? n_tiles : 65536);
-    hipLaunchKernelGGL(k_tile_prep<CHUNK>, dim3(gp), dim3(kThreads), 0, s, ranges, n_tiles, cam->width, cam->height,
-                       Wt, bg[0], bg[1], bg[2], w.nch, image, final_T, n_contrib);
-    hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kScanThreads), 0, s, w.nch, n_tiles, max_mask_items, w.mfirst,
-                       w.order, w.mitem, w.counters);
+    hipLaunchKernelGGL(k_tile_prep<CHUNK>, dim3(gp), dim3(kThreads), 0, s, n_tiles, cam->width, cam->height,
+                       Wt, bg[0], bg[1], bg[2], w.nch, w.mfirst, max_mask_items, w.mitem, image, final_T,
+                       n_contrib);
     const float2* xy = (const float2*)splats->xy;
     const float4* co = (const float4*)splats->conic_o;
     const float4* rgb = (const float4*)splats->rgb_depth;
