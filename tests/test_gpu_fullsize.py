@@ -1,9 +1,11 @@
 """GPU parity at the benchmark's full size, in the launch configuration the
 bench times: the 20,000,003-node city tree at 1920x1080 with the calibrated
-GTC threshold and the bench's capacities (frames of the fly-through), and two
+GTC threshold and the bench's capacities (frames of the fly-through), two
 views of the 32-view batch (720p and 2160p, global tile ids) through the
-batched renderer. Same bar as the small cases: selection, splats, keys,
-ranges and contributor counts bit-exact, colours within 1e-4.
+batched renderer, and the single 1080p view of the 1M-leaf city (1.14M
+nodes) with and without the shrink, at every chunk size. Same bar as the
+small cases: selection, splats, keys, ranges and contributor counts
+bit-exact, colours within 1e-4.
 """
 import json
 import os
@@ -65,3 +67,25 @@ def test_batch_views_full_size(city):
         assert np.array_equal(u32(vb.ranges).reshape(-1, 2), o["ranges"])
         assert np.abs(vb.image.cpu().numpy() - o["image"]).max() <= 1e-4
         assert np.array_equal(u32(vb.n_contrib), o["n_contrib"])
+
+
+@pytest.fixture(scope="module")
+def city1m():
+    tree = synth.city_tree(synth.CITY1M)
+    with open(os.path.join(ROOT, "tests", "golden", "city_tau.json")) as f:
+        tau = float(json.load(f)["city1m"]["tau"])
+    return tree, fg.DeviceTree(tree), tau
+
+
+@pytest.mark.parametrize("shrink", [False, True])
+def test_city1m_single_view(city1m, shrink):
+    tree, dtree, tau = city1m
+    tau = tau if shrink else 0.0
+    cam = synth.city1m_camera()
+    o = oracle.render_frame(tree, cam, synth.TAU_R, tau)
+    assert o["sel_idx"].size > 100_000 and o["keys"].size > 100_000
+    for chunk in (128, 256, 512):
+        fb = fg.FrameBuffers(dtree, cam.width, cam.height, cap_sel=2_000_000, cap_pairs=16_000_000)
+        fg.render_frame(dtree, cam, fb, synth.TAU_R, tau, tune=fg.tune_struct(chunk))
+        torch.cuda.synchronize()
+        assert_frame_parity(read_frame(fb, tree.n_nodes), o)
