@@ -129,7 +129,9 @@ typedef struct fg_splats {
 /* Speed-only knobs; results never depend on them. NULL = defaults. */
 typedef struct fg_tune {
     int32_t render_batch;  /* splats per blend work item (chunk): 128, 256 or 512 (default 256) */
-    int32_t radix_bits;    /* digit width of the pair sort: 4..8 (default 8) */
+    int32_t radix_bits;    /* digit width of the pair sort: 4..8 (default: the narrowest width
+                              that needs no more passes than 8-bit digits, e.g. 7 for
+                              13-bit tile ids) */
     int32_t save_state;    /* 1: fg_render keeps, for every chunk of a long range, each pixel's
                               (T, C) after that chunk in its workspace (sized for it by
                               fg_render_workspace_size with the same tune), which

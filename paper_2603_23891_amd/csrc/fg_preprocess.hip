@@ -161,7 +161,7 @@ extern "C" int fg_preprocess(const fg_tree* tree, const fg_camera* cam, float ta
     hipStream_t s = (hipStream_t)stream;
     const fgd::Cam c = fgd::make_cam(*cam);
     int64_t blocks = (cap_sel + kBlock - 1) / kBlock;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 32768) blocks = 32768;
     const dim3 g((unsigned)blocks), b(kBlock);
     switch (tree->sh_degree) {
         case 0: hipLaunchKernelGGL(k_preprocess<0>, g, b, 0, s, *tree, c, tau, sel_idx, n_sel, cap_sel, *out); break;

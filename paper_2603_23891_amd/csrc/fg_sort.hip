@@ -550,7 +550,7 @@ extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t c
     if (cap_pairs > 0 && (!tile_keys || !vals)) return FG_ERR_INVALID_ARG;
     if (cap_sel > 0 && (!splats->rgb_depth || !splats->rect || !splats->tiles)) return FG_ERR_INVALID_ARG;
     if (cam->width <= 0 || cam->height <= 0) return FG_ERR_INVALID_ARG;
-    int bits = 8;
+    int bits = 0;  // 0: the narrowest digit that needs no more passes than 8-bit digits
     if (tune && tune->radix_bits) {
         if (tune->radix_bits < 4 || tune->radix_bits > 8) return FG_ERR_INVALID_ARG;
         bits = tune->radix_bits;
@@ -588,6 +588,11 @@ extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t c
                        (const ushort4*)splats->rect, w.n_vis, cap_sel, w.bsum, w.rect_d);
     int tile_bits = 1;
     while (tile_bits < 32 && (max_tile >> tile_bits) != 0) ++tile_bits;
+    if (bits == 0) {
+        const int p8 = (tile_bits + 7) / 8;
+        bits = (tile_bits + p8 - 1) / p8;  // e.g. 13 bits: two passes of 7
+        if (bits < 4) bits = 4;
+    }
     const int passes = (tile_bits + bits - 1) / bits;
     // emit into the buffer that the last pass will not write
     uint32_t* ek = cap_pairs == 0 ? nullptr : (passes % 2) ? w.kalt : tile_keys;
