@@ -248,7 +248,7 @@ def main():
                     help="also run a plain 256 MiB device copy three times (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        log("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'Sharding').")
+        log("bench.py measures one GPU: the library drives one GPU and has no multi-GPU path.")
         sys.exit(2)
 
     import torch

@@ -75,9 +75,11 @@ template <int NV>
 __global__ __launch_bounds__(kBlock) void k_small(const float* __restrict__ mean, const float* __restrict__ scale,
                                                   const float* __restrict__ quat, const uint8_t* __restrict__ flags,
                                                   int64_t N, int64_t span, CamSet cams, int nv, float tau_R,
-                                                  uint32_t* __restrict__ small_bits, int64_t words)
+                                                  uint32_t* __restrict__ small_bits, int64_t words,
+                                                  uint32_t* __restrict__ status, bool reset_status)
 {
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n == 0 && reset_status) *status = 0u;  // before any later kernel of the call sets a bit
     uint32_t small = 0;  // bit v: small in view v
     if (n < span && !(flags[n] & 1u)) {
         const float mx = mean[n], my = mean[N + n], mz = mean[2 * N + n];
@@ -362,13 +364,13 @@ size_t carve(void* base, int64_t N, int64_t span, int n_views, FilterWs* w)
 
 template <int NV>
 void launch_pass(const fg_tree* tree, const CamSet& cs, int nv, float tau_R, uint32_t* sel_bits, int64_t sel_words,
-                 uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status, const FilterWs& w, int64_t N,
-                 int64_t span, int64_t n_tiles, hipStream_t s)
+                 uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status, bool reset_status,
+                 const FilterWs& w, int64_t N, int64_t span, int64_t n_tiles, hipStream_t s)
 {
     if (span > 0) {
         const dim3 g((unsigned)((span + kBlock - 1) / kBlock));
         hipLaunchKernelGGL(k_small<NV>, g, dim3(kBlock), 0, s, tree->mean, tree->scale, tree->quat, tree->flags, N,
-                           span, cs, nv, tau_R, w.small_bits, w.words);
+                           span, cs, nv, tau_R, w.small_bits, w.words, status, reset_status);
         hipLaunchKernelGGL(k_blocked<NV>, g, dim3(kBlock), 0, s, tree->parent, tree->flags, w.small_bits, w.words,
                            span, tree->max_depth, nv, w.blocked_bits, status);
     }
@@ -414,14 +416,21 @@ extern "C" int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_v
         const int nv = n_views - v0 < kMaxViews ? n_views - v0 : kMaxViews;
         CamSet cs;
         for (int v = 0; v < kMaxViews; v++) cs.c[v] = fgd::make_cam(cams[v0 + (v < nv ? v : 0)]);
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, status, v0 == 0, n_sel + v0, nv);
+        // the status word is cleared by the first pass: by k_small when the
+        // tree has internal nodes, else by k_reset (which also zeroes n_sel
+        // for an empty tree)
+        const bool first = v0 == 0;
+        if (N == 0 || span == 0)
+            hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, status, first, n_sel + v0, nv);
         if (N == 0) continue;
         uint32_t* sb = sel_bits + (int64_t)v0 * sel_words;
         uint32_t* si = sel_idx ? sel_idx + (int64_t)v0 * cap_sel : nullptr;
-        if (nv == 1) launch_pass<1>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, n_sel + v0, status, w, N, span, n_tiles, s);
-        else if (nv == 2) launch_pass<2>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, n_sel + v0, status, w, N, span, n_tiles, s);
-        else if (nv <= 4) launch_pass<4>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, n_sel + v0, status, w, N, span, n_tiles, s);
-        else launch_pass<8>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, n_sel + v0, status, w, N, span, n_tiles, s);
+        uint32_t* ns = n_sel + v0;
+        const bool rs = first && span > 0;
+        if (nv == 1) launch_pass<1>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
+        else if (nv == 2) launch_pass<2>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
+        else if (nv <= 4) launch_pass<4>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
+        else launch_pass<8>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
     }
     return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
 }
