@@ -37,9 +37,9 @@ constexpr int kThreads = 256;
 constexpr int kIPT = 4;
 constexpr int kTileItems = kThreads * kIPT;  // 1024
 constexpr int kWaves = kThreads / fgd::kWave;
-constexpr int kEmitIPT = 8;
-constexpr int kEmitItems = kThreads * kEmitIPT;  // 2048
-constexpr int kEmitRun = 8;                       // consecutive pairs per thread
+constexpr int kEmitIPT = 4;
+constexpr int kEmitItems = kThreads * kEmitIPT;  // 1024
+constexpr int kEmitRun = 4;                       // consecutive pairs per thread
 
 __device__ __forceinline__ int64_t count_of(const uint32_t* p, int64_t cap)
 {
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_vis_pack(const float4* __restrict_
     }
 }
 
-// Per 2048 splats in depth order: the sum of their tile counts (the areas of
+// Per 1024 splats in depth order: the sum of their tile counts (the areas of
 // their rectangles). The rectangles are gathered here once and stored in depth
 // order, so that the emission reads them contiguously.
 __global__ __launch_bounds__(kThreads) void k_count_reduce(const uint32_t* __restrict__ order,
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(kThreads) void k_count_reduce(const uint32_t* __res
     }
 }
 
-// Per 2048 splats in depth order: every splat's output offset (the block's
+// Per 1024 splats in depth order: every splat's output offset (the block's
 // offset, summed from the earlier blocks' totals, plus an exclusive scan
 // within the block), then the block's pairs are written with thread k taking
 // output positions k, k + 256, ...: a binary search over the offsets finds
@@ -486,7 +486,8 @@ struct SortWs {
 size_t carve(void* base, int64_t cap_sel, int64_t cap_pairs, SortWs* w)
 {
     const int64_t ht = tiles_for(cap_sel > cap_pairs ? cap_sel : cap_pairs);
-    const size_t nblk = (size_t)((cap_sel + kTileItems - 1) / kTileItems + 1);
+    const int64_t blk_items = kTileItems < kEmitItems ? kTileItems : kEmitItems;  // vcnt and bsum entries
+    const size_t nblk = (size_t)((cap_sel + blk_items - 1) / blk_items + 1);
     const size_t sizes[10] = {
         (size_t)cap_sel * 4, (size_t)cap_sel * 4, (size_t)cap_sel * 8, nblk * 4,
         (size_t)cap_pairs * 4, (size_t)cap_pairs * 4,
