@@ -9,7 +9,7 @@
 
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 128;
 
 // Real spherical harmonics (orthonormal, closed-form Cartesian polynomials of
 // the unit direction), coefficient order (l, m = -l..l).
