@@ -234,12 +234,14 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
                     }
                 }
                 if (__ballot(hit)) {
-                    float* dst = gacc + (size_t)s_g[jj] * kNG;
+                    // the 9 wave sums, then one atomic instruction: lane k adds sum k
+                    float mine = 0.0f;
 #pragma unroll
                     for (int k = 0; k < kNG; k++) {
                         const float v = wave_sum(gr[k]);
-                        if (lane == k && v != 0.0f) atomicAdd(&dst[k], v);
+                        mine = lane == k ? v : mine;
                     }
+                    if (lane < kNG && mine != 0.0f) atomicAdd(gacc + (size_t)s_g[jj] * kNG + lane, mine);
                 }
             }
         }
