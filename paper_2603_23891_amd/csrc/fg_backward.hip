@@ -55,25 +55,26 @@ __global__ void k_zero(float* __restrict__ p, int64_t n)
         p[i] = 0.0f;
 }
 
-// Sum over the 64 lanes, returned in every lane: DPP quad and row permutes
-// give each row of 16 lanes its sum, four lane reads add the rows.
+// DPP move within rows of 16 lanes.
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
 
-__device__ __forceinline__ float wave_sum(float v)
+// Sum over the 64 lanes, returned in every lane: DPP quad permutes and row
+// mirrors give every lane of a row of 16 its row's sum; row broadcasts (lane
+// 15 of rows 0 and 2 into rows 1 and 3, then lane 31 into rows 2 and 3) leave
+// the total in lane 63, and one lane read returns it.
+__device__ __forceinline__ float wave_total(float v)
 {
     v = v + dpp_mov<0xB1>(v);   // quad_perm [1, 0, 3, 2]
     v = v + dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]
     v = v + dpp_mov<0x141>(v);  // row_half_mirror
     v = v + dpp_mov<0x140>(v);  // row_mirror
-    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-    return (r0 + r1) + (r2 + r3);
+    v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // Chunk items of long ranges (from the forward's saved state) and whole
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
                     float mine = 0.0f;
 #pragma unroll
                     for (int k = 0; k < kNG; k++) {
-                        const float v = wave_sum(gr[k]);
+                        const float v = wave_total(gr[k]);
                         mine = lane == k ? v : mine;
                     }
                     if (lane < kNG && mine != 0.0f) atomicAdd(gacc + (size_t)s_g[jj] * kNG + lane, mine);
