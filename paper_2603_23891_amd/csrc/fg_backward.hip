@@ -204,20 +204,22 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
                     const float dy = m.y - fpy;
                     const float power = -0.5f * ((co.x * dx) * dx + (co.z * dy) * dy) - (co.y * dx) * dy;
                     if (!(power > 0.0f || power < kSkipPower)) {
-                        const float e = fgd::exp_neg(power);
+                        const float e = fgd::exp_neg_in_range(power);  // -5.6 <= power <= 0
                         const float araw = co.w * e;
                         const float alpha = araw < 0.99f ? araw : 0.99f;
                         if (alpha >= 1.0f / 255.0f) {
                             hit = true;
                             const float4 c = s_rgb[jj];
-                            const float one_m = 1.0f - alpha;
-                            const float Tk = T / one_m;
+                            // one division, then products: the gradients carry a
+                            // tolerance, not the forward's bit-exactness
+                            const float inv = 1.0f / (1.0f - alpha);
+                            const float Tk = T * inv;
                             const float w = alpha * Tk;
                             gr[6] = G0 * w;
                             gr[7] = G1 * w;
                             gr[8] = G2 * w;
-                            const float dLda = (G0 * (c.x * Tk - S0 / one_m) + G1 * (c.y * Tk - S1 / one_m)) +
-                                               G2 * (c.z * Tk - S2 / one_m);
+                            const float dLda = (G0 * (c.x * Tk - S0 * inv) + G1 * (c.y * Tk - S1 * inv)) +
+                                               G2 * (c.z * Tk - S2 * inv);
                             S0 = S0 + c.x * w;
                             S1 = S1 + c.y * w;
                             S2 = S2 + c.z * w;
