@@ -332,6 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__
     for (int g = 0; g < kGroups; g++) {
         const uint64_t gb = (uint64_t)(uint32_t)__shfl((int)lo, g, fgd::kWave) |
                             ((uint64_t)(uint32_t)__shfl((int)hi, g, fgd::kWave) << 32);
+        if (gb == 0ull) continue;  // nothing selected in this group (the same for the whole wave)
         const uint32_t off = (uint32_t)__shfl((int)excl, g, fgd::kWave);
         if ((gb >> lane) & 1ull) {
             const uint32_t o = off + (uint32_t)__popcll(gb & lt);
