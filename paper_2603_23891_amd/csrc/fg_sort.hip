@@ -16,7 +16,7 @@
 // records to 2 passes over 8-byte records at 1080p.
 //
 // Radix pass (LSD, one digit of BITS bits, stable), three kernels:
-//   k_hist      per 1024-item tile: digit histogram -> hist[digit][tile]
+//   k_hist      per 1024-item tile: digit histogram (LDS atomics) -> hist[digit][tile]
 //   k_rowscan   one workgroup per digit: exclusive scan over the tiles,
 //               digit totals
 //   k_scatter   per tile: stable local ranks (wave ballot match on the digit
@@ -101,8 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint32_t* __restrict__ 
             const int64_t idx = tile * kTileItems + r * kThreads + threadIdx.x;
             const bool valid = idx < n;
             const uint32_t d = valid ? (keys[idx] >> shift) & (R - 1) : 0u;
-            const uint64_t m = match_digit<BITS>(d, valid);
-            if (valid && (m & fgd::lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(m));
+            if (valid) atomicAdd(&h[d], 1u);
         }
         __syncthreads();
         for (int d = threadIdx.x; d < R; d += kThreads) hist[(int64_t)d * n_tiles + tile] = h[d];
