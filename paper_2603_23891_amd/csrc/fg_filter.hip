@@ -167,13 +167,15 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
     bool bad = false;
     // Loads are issued phase by phase for all rounds at once (parent links and
     // flags, then the parents' blocked bits, then leaf positions), so a
-    // workgroup waits three memory latencies rather than three per round.
+    // workgroup waits three memory latencies rather than three per round. The
+    // streamed parent links and positions are loaded non-temporally, which
+    // keeps the small and blocked bits of the internal nodes in the caches.
     int32_t par[kRounds];
     uint32_t fl[kRounds];
 #pragma unroll
     for (int r = 0; r < kRounds; r++) {
         const int64_t n = tile * kTileNodes + r * kBlock + tid;
-        par[r] = n < N ? parent[n] : -1;
+        par[r] = n < N ? __builtin_nontemporal_load(parent + n) : -1;
         fl[r] = (n < N && n < span) ? (uint32_t)flags[n] : 1u;
     }
     uint32_t cull[kRounds];  // bit v: removed by the Ancestor filter in view v
@@ -199,9 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
         const int64_t n = tile * kTileNodes + r * kBlock + tid;
         mx[r] = my[r] = mz[r] = 0.0f;
         if (n < N && cull[r] != all && (fl[r] & 1u)) {
-            mx[r] = mean[n];
-            my[r] = mean[N + n];
-            mz[r] = mean[2 * N + n];
+            mx[r] = __builtin_nontemporal_load(mean + n);
+            my[r] = __builtin_nontemporal_load(mean + N + n);
+            mz[r] = __builtin_nontemporal_load(mean + 2 * N + n);
         }
     }
     uint32_t cnt[NV];
