@@ -250,20 +250,30 @@ def kpc(splats, vals, ranges, cam) -> np.ndarray:
     return out[: vals.size]
 
 
-def gtc_view(kpc_pairs, ranges) -> float:
-    """View GTC (Eq. (7)): mean over the tiles that hold pairs of the tile GTC
-    (Eq. (6)), the mean KPC over all pairs of the tile."""
+def tile_gtc(kpc_pairs, ranges) -> np.ndarray:
+    """Tile GTC (Eq. (6)): for every tile, the mean KPC over all of its pairs,
+    pairs with zero contribution included; NaN for a tile without pairs (0/0,
+    which the paper leaves undefined)."""
     ranges = np.asarray(ranges).reshape(-1, 2).astype(np.int64)
-    g = []
-    for lo, hi in ranges:
+    out = np.full(ranges.shape[0], np.nan)
+    for t, (lo, hi) in enumerate(ranges):
         if hi > lo:
-            g.append(kpc_pairs[lo:hi].sum() / (hi - lo))
-    return float(np.mean(g)) if g else 0.0
+            out[t] = kpc_pairs[lo:hi].sum() / (hi - lo)
+    return out
+
+
+def gtc_view(kpc_pairs, ranges):
+    """View GTC (Eq. (7)): mean of the tile GTCs over the tiles that hold
+    pairs. None for a view without pairs (undefined; such a view is left out
+    of the scene mean)."""
+    g = tile_gtc(kpc_pairs, ranges)
+    g = g[~np.isnan(g)]
+    return float(g.mean()) if g.size else None
 
 
 def scene_tau(tree, cams, lambda_G: float = 0.2, tau_R: float = 3.0) -> dict:
-    """Eq. (8): G_bar = mean of the view GTCs (3-sigma extents, the filtered
-    cut), tau = lambda_G / G_bar."""
+    """Eq. (8): G_bar = mean of the view GTCs over the views that hold pairs
+    (3-sigma extents, the filtered cut), tau = lambda_G / G_bar."""
     t = _tree_ref(tree)
     gv = []
     for cam in cams:
@@ -271,7 +281,10 @@ def scene_tau(tree, cams, lambda_G: float = 0.2, tau_R: float = 3.0) -> dict:
         sp = preprocess(t, cam, 0.0, sel)
         keys, vals, ranges = sort(sp, cam)
         gv.append(gtc_view(kpc(sp, vals, ranges, cam), ranges))
-    G = float(np.mean(gv))
+    defined = [g for g in gv if g is not None]
+    if not defined:
+        raise ValueError("no view holds a Gaussian-tile pair: G_bar is undefined")
+    G = float(np.mean(defined))
     return dict(G_views=gv, G_bar=G, lambda_G=lambda_G, tau=lambda_G / G)
 
 

@@ -57,7 +57,7 @@ typedef struct fgo_camera {
 /* transcendental functions                                               */
 /* ---------------------------------------------------------------------- */
 
-/* exp(x) for x <= 0 (0 below -87, where the true value approaches the
+/* exp(x) for x <= 88 (0 below -87, where the true value approaches the
  * smallest normal float). Cody & Waite (1980) argument reduction
  * x = n*ln2 + r with ln2 split into a 16-bit head and a tail, then the
  * degree-7 Taylor polynomial of e^r in Horner form with fused multiply-add,

@@ -97,3 +97,26 @@ def test_tune_struct_layout():
     assert C.sizeof(t) == 16 + 2 * C.sizeof(C.c_void_p)
     assert (t.render_batch, t.radix_bits, t.save_state) == (512, 7, 1)
     assert t.blend_events[0] is None and t.blend_events[1] is None
+
+
+def test_filter_rejects_inconsistent_trees_on_the_host(lib):
+    """FG_ERR_INVALID_TREE is decided from the struct's sizes before any device
+    work: the plane pointers (never dereferenced here) only need to be set."""
+    cam = (fg.FgCamera * 1)(fg.camera_struct(cam_1080p()))
+    fake = 1 << 20  # a non-null address no device work ever reads: the call returns first
+
+    def call(n_nodes, span, max_depth):
+        t = fg.FgTree(n_nodes=n_nodes, n_internal_span=span, sh_degree=0, max_depth=max_depth, mean=fake,
+                      scale=fake, quat=fake, opacity=fake, sh=fake, parent=fake, flags=fake)
+        return lib.fg_filter(C.byref(t), C.cast(cam, C.c_void_p), 1, C.c_float(3.0), C.c_void_p(fake),
+                             C.c_void_p(fake), 16, C.c_void_p(fake), C.c_void_p(fake), C.c_void_p(fake), 1 << 30,
+                             None)
+
+    FG_ERR_INVALID_TREE = -2
+    assert call(100, 101, 3) == FG_ERR_INVALID_TREE      # internal span beyond the node count
+    assert call(100, -1, 3) == FG_ERR_INVALID_TREE       # negative span
+    assert call(100, 10, 16) == FG_ERR_INVALID_TREE      # ancestor chains longer than 15
+    assert call(100, 10, -1) == FG_ERR_INVALID_TREE
+    assert call(-5, 0, 0) == FG_ERR_INVALID_TREE
+    assert call(1 << 31, 0, 0) == FG_ERR_INVALID_TREE    # node ids must fit 31 bits
+    assert lib.fg_status_string(FG_ERR_INVALID_TREE) == b"invalid tree"

@@ -4,7 +4,8 @@ exp feeds the per-fragment opacity alpha = o * exp(power) of Eq. (2)'s blend;
 log feeds the shrink radius r = sqrt(2 lambda_max ln(alpha0 / tau)) of
 Sec. 3.3. Both are project-defined (Cody & Waite reduction + Taylor; atanh
 series) so CPU and GPU evaluate them identically; here they are held to
-< 1 ulp of the exact value (measured 0.89 and 0.82).
+< 1 ulp of the exact value (measured 0.89 and 0.82), exp on [-87, 88] and
+log on (1, 3.4e38].
 """
 import numpy as np
 import pytest
@@ -32,6 +33,22 @@ def test_exp_ulp_dense():
     err = ulp_err(y, np.exp(x.astype(np.float64)))
     assert err.max() < 1.0, (err.max(), x[np.argmax(err)])
     assert oracle.exp(np.float32([0.0]))[0] == 1.0
+
+
+def test_exp_ulp_positive_arguments():
+    """The activation (scale = exp(log_scale), opacity = 1 / (1 + exp(-logit)))
+    also calls exp with positive arguments, up to 87."""
+    rng = np.random.default_rng(13)
+    x = np.concatenate([
+        rng.uniform(0, 88.0, 300000),
+        rng.uniform(0, 4.0, 200000),
+        np.exp(rng.uniform(-40, 0, 50000)),
+        np.float32([1e-30, 1e-7, 0.5, 1.0, 2.0, 0.34657359, 10.0, 44.3614196, 87.0, 88.0]),
+    ]).astype(np.float32)
+    y = oracle.exp(x)
+    err = ulp_err(y, np.exp(x.astype(np.float64)))
+    assert err.max() < 1.0, (err.max(), x[np.argmax(err)])
+    assert np.all(np.isfinite(y))
 
 
 def test_exp_underflow_and_monotone_at_blend_threshold():

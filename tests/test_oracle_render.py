@@ -172,3 +172,16 @@ def test_skip_threshold_and_termination():
     img, T, nc = oracle.render(sp, vals, ranges, cam)
     # alpha = 0.5 at the centre: T halves each step, 0.5^13 = 1.2e-4 >= 1e-4, 0.5^14 < 1e-4
     assert nc[8, 8] == 13 and T[8, 8] == np.float32(0.5 ** 13)
+
+
+def test_render_pixels_equals_the_tiled_render():
+    """The sampled-pixel form (used where a whole image is too slow) blends
+    exactly the pixels of the full render."""
+    _, cam, out = _frame(1 / 255, 25.0, 3.0)
+    rng = np.random.default_rng(3)
+    px = rng.integers(0, cam.width, 500)
+    py = rng.integers(0, cam.height, 500)
+    rgb, T, nc = oracle.render_pixels(out["splats"], out["vals"], out["ranges"], cam, px, py, bg=(0.1, 0.2, 0.3))
+    img, Tf, ncf = oracle.render(out["splats"], out["vals"], out["ranges"], cam, bg=(0.1, 0.2, 0.3))
+    assert np.array_equal(rgb, img[:, py, px].T)
+    assert np.array_equal(T, Tf[py, px]) and np.array_equal(nc, ncf[py, px])
