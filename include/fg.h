@@ -67,6 +67,8 @@ extern "C" {
 #define FG_ERR_UNSUPPORTED (-3)   /* e.g. SH degree > 3, image too large */
 #define FG_ERR_WORKSPACE (-4)     /* ws_bytes below the *_workspace_size value */
 #define FG_ERR_HIP (-5)           /* a HIP launch or runtime call failed */
+#define FG_ERR_SCRATCH (-6)       /* fg_filter_noalloc: the problem needs more than
+                                     FG_NOALLOC_SCRATCH_BYTES of workspace */
 
 /* ---- device status bits ------------------------------------------------ */
 #define FG_STATUS_SEL_OVERFLOW 1u   /* more selected nodes than cap_sel */
@@ -169,6 +171,26 @@ size_t fg_filter_workspace_size(int64_t n_nodes, int64_t n_internal_span, int32_
 int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float tau_R, uint32_t* sel_bits,
               uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status, void* ws, size_t ws_bytes,
               void* stream);
+
+/* fg_filter without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Same arguments, outputs, status bits and errors as
+ * fg_filter; the scratch space is a fixed device array of
+ * FG_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends. The call allocates nothing (its first call on a device only
+ * looks up that device's array address). It returns FG_ERR_SCRATCH, before
+ * enqueueing anything, when fg_filter_workspace_size(n_nodes,
+ * n_internal_span, n_views) exceeds FG_NOALLOC_SCRATCH_BYTES (16 MiB; views
+ * are filtered 8 per pass in the same scratch, so a 20M-node tree with 2.5M
+ * internal nodes needs 5.1 MiB for any number of views).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (different streams, or host threads, without ordering between them)
+ * race on it and give undefined selections. Calls ordered on one stream are
+ * safe; no contents carry over from one call to the next. */
+#define FG_NOALLOC_SCRATCH_BYTES (16u << 20)
+int fg_filter_noalloc(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float tau_R,
+                      uint32_t* sel_bits, uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status,
+                      void* stream);
 
 /* ---- stage 2: projection and shrunk extents (Sec. 3.1, Sec. 3.3) -------- */
 

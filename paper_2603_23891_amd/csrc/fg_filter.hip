@@ -36,6 +36,8 @@
 // agent-scope descriptor reads cost a memory round trip per step.
 #include "fg_device.h"
 
+#include <mutex>
+
 namespace {
 
 constexpr int kBlock = 256;
@@ -387,18 +389,9 @@ void launch_pass(const fg_tree* tree, const CamSet& cs, int nv, float tau_R, uin
                            s, sel_bits, sel_words, N, w.tile_cnt, n_tiles, sel_idx, cap_sel);
 }
 
-}  // namespace
-
-extern "C" size_t fg_filter_workspace_size(int64_t n_nodes, int64_t n_internal_span, int32_t n_views)
-{
-    if (n_nodes < 0 || n_internal_span < 0 || n_views < 1) return 0;
-    FilterWs w;
-    return carve(nullptr, n_nodes, n_internal_span, n_views, &w);
-}
-
-extern "C" int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float tau_R,
-                         uint32_t* sel_bits, uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status,
-                         void* ws, size_t ws_bytes, void* stream)
+// Argument checks shared by fg_filter and fg_filter_noalloc (host only).
+int check_filter_args(const fg_tree* tree, const fg_camera* cams, int32_t n_views, uint32_t* sel_bits,
+                      uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status)
 {
     if (!tree || !cams || n_views < 1 || !sel_bits || !n_sel || !status || cap_sel < 0 || (cap_sel > 0 && !sel_idx))
         return FG_ERR_INVALID_ARG;
@@ -409,8 +402,15 @@ extern "C" int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_v
         return FG_ERR_INVALID_ARG;
     for (int v = 0; v < n_views; v++)
         if (cams[v].width <= 0 || cams[v].height <= 0) return FG_ERR_INVALID_ARG;
+    return FG_OK;
+}
+
+// The launches of one filter call on a workspace already checked for size.
+int run_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float tau_R, uint32_t* sel_bits,
+               uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status, void* ws, void* stream)
+{
+    const int64_t N = tree->n_nodes, span = tree->n_internal_span;
     FilterWs w;
-    if (!ws || ws_bytes < carve(nullptr, N, span, n_views, &w)) return FG_ERR_WORKSPACE;
     carve(ws, N, span, n_views, &w);
     hipStream_t s = (hipStream_t)stream;
     const int64_t n_tiles = (N + kTileNodes - 1) / kTileNodes;
@@ -436,4 +436,64 @@ extern "C" int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_v
         else launch_pass<8>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
     }
     return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" size_t fg_filter_workspace_size(int64_t n_nodes, int64_t n_internal_span, int32_t n_views)
+{
+    if (n_nodes < 0 || n_internal_span < 0 || n_views < 1) return 0;
+    FilterWs w;
+    return carve(nullptr, n_nodes, n_internal_span, n_views, &w);
+}
+
+extern "C" int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float tau_R,
+                         uint32_t* sel_bits, uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status,
+                         void* ws, size_t ws_bytes, void* stream)
+{
+    const int rc = check_filter_args(tree, cams, n_views, sel_bits, sel_idx, cap_sel, n_sel, status);
+    if (rc != FG_OK) return rc;
+    FilterWs w;
+    if (!ws || ws_bytes < carve(nullptr, tree->n_nodes, tree->n_internal_span, n_views, &w)) return FG_ERR_WORKSPACE;
+    return run_filter(tree, cams, n_views, tau_R, sel_bits, sel_idx, cap_sel, n_sel, status, ws, stream);
+}
+
+// ---- fg_filter_noalloc: the same filter on a fixed device array -----------
+//
+// For callers that cannot allocate (code under graph capture, serving loops):
+// the workspace lives in `scratch`, a file-scope device array of
+// FG_NOALLOC_SCRATCH_BYTES. Each device holds its own copy at its own
+// address; host code never passes the array's name to a kernel (on the host it
+// is only a stand-in symbol), but the device address that hipGetSymbolAddress
+// returns, looked up once per device on that device's first call.
+namespace {
+
+static __device__ __align__(256) unsigned char scratch[FG_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+}  // namespace
+
+extern "C" int fg_filter_noalloc(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float tau_R,
+                                 uint32_t* sel_bits, uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel,
+                                 uint32_t* status, void* stream)
+{
+    const int rc = check_filter_args(tree, cams, n_views, sel_bits, sel_idx, cap_sel, n_sel, status);
+    if (rc != FG_OK) return rc;
+    FilterWs w;
+    if (carve(nullptr, tree->n_nodes, tree->n_internal_span, n_views, &w) > (size_t)FG_NOALLOC_SCRATCH_BYTES)
+        return FG_ERR_SCRATCH;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FG_ERR_HIP;
+    std::call_once(g_scratch_once[dev], [dev] {
+        void* p = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = p;
+    });
+    if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev]) return FG_ERR_HIP;
+    return run_filter(tree, cams, n_views, tau_R, sel_bits, sel_idx, cap_sel, n_sel, status, g_scratch_ptr[dev],
+                      stream);
 }

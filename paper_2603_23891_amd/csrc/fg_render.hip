@@ -904,6 +904,7 @@ extern "C" const char* fg_status_string(int code)
         case FG_ERR_UNSUPPORTED: return "unsupported configuration";
         case FG_ERR_WORKSPACE: return "workspace too small";
         case FG_ERR_HIP: return "HIP launch or runtime error";
+        case FG_ERR_SCRATCH: return "problem larger than the fixed scratch array of fg_filter_noalloc";
         default: return "unknown status";
     }
 }

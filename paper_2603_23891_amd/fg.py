@@ -64,7 +64,7 @@ class FgTune(C.Structure):
                 ("mask_items", C.c_int32), ("blend_events", C.c_void_p * 2)]
 
 
-EXPORTS = ["fg_filter_workspace_size", "fg_filter", "fg_preprocess", "fg_sort_workspace_size", "fg_sort",
+EXPORTS = ["fg_filter_workspace_size", "fg_filter", "fg_filter_noalloc", "fg_preprocess", "fg_sort_workspace_size", "fg_sort",
            "fg_render_workspace_size", "fg_render", "fg_activate", "fg_render_backward_workspace_size",
            "fg_render_backward", "fg_status_string"]
 
@@ -83,6 +83,8 @@ def lib():
         L.fg_filter_workspace_size.argtypes = [i64, i64, C.c_int32]
         L.fg_filter.restype = i32
         L.fg_filter.argtypes = [vp, vp, C.c_int32, f32, vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
+        L.fg_filter_noalloc.restype = i32
+        L.fg_filter_noalloc.argtypes = [vp, vp, C.c_int32, f32, vp, vp, i64, vp, vp, vp]
         L.fg_preprocess.restype = i32
         L.fg_preprocess.argtypes = [vp, vp, f32, vp, vp, i64, vp, vp, vp]
         L.fg_sort_workspace_size.restype = C.c_size_t
@@ -216,6 +218,17 @@ def fg_filter(tree: DeviceTree, cams, tau_R: float, sel_bits, sel_idx, cap_sel: 
     _check(lib().fg_filter(_ref(ts), C.cast(arr, C.c_void_p), len(cams), C.c_float(tau_R), _p(sel_bits),
                            _p(sel_idx), cap_sel, _p(n_sel), _p(status), _p(ws), ws.numel() * ws.element_size(),
                            _stream(stream)), "fg_filter")
+
+
+def fg_filter_noalloc(tree: DeviceTree, cams, tau_R: float, sel_bits, sel_idx, cap_sel: int, n_sel, status,
+                      stream=None):
+    """fg_filter on the library's fixed per-device scratch array (no workspace argument)."""
+    cams = list(cams) if isinstance(cams, (list, tuple)) else [cams]
+    ts = tree.struct()
+    arr = (FgCamera * len(cams))(*[camera_struct(c) for c in cams])
+    _check(lib().fg_filter_noalloc(_ref(ts), C.cast(arr, C.c_void_p), len(cams), C.c_float(tau_R), _p(sel_bits),
+                                   _p(sel_idx), cap_sel, _p(n_sel), _p(status), _stream(stream)),
+           "fg_filter_noalloc")
 
 
 def fg_preprocess(tree: DeviceTree, cam, tau: float, sel_idx, n_sel, cap_sel: int, out: Splats, status,

@@ -120,3 +120,26 @@ def test_filter_rejects_inconsistent_trees_on_the_host(lib):
     assert call(-5, 0, 0) == FG_ERR_INVALID_TREE
     assert call(1 << 31, 0, 0) == FG_ERR_INVALID_TREE    # node ids must fit 31 bits
     assert lib.fg_status_string(FG_ERR_INVALID_TREE) == b"invalid tree"
+
+
+def test_filter_noalloc_rejects_problems_beyond_its_scratch_on_the_host(lib):
+    """fg_filter_noalloc refuses, before any device work, a tree whose filter
+    workspace exceeds its fixed scratch array, and checks arguments like
+    fg_filter."""
+    cam = (fg.FgCamera * 1)(fg.camera_struct(cam_1080p()))
+    fake = 1 << 20
+
+    def call(n_nodes, span):
+        t = fg.FgTree(n_nodes=n_nodes, n_internal_span=span, sh_degree=0, max_depth=8, mean=fake, scale=fake,
+                      quat=fake, opacity=fake, sh=fake, parent=fake, flags=fake)
+        return lib.fg_filter_noalloc(C.byref(t), C.cast(cam, C.c_void_p), 1, C.c_float(3.0), C.c_void_p(fake),
+                                     C.c_void_p(fake), 16, C.c_void_p(fake), C.c_void_p(fake), None)
+
+    FG_ERR_SCRATCH, FG_ERR_INVALID_TREE = -6, -2
+    limit = 16 << 20
+    big = (1 << 31) - 1  # every node internal: about 0.53 GB of small/blocked bits
+    assert fg.fg_filter_workspace_size(big, big, 1) > limit
+    assert call(big, big) == FG_ERR_SCRATCH
+    assert call(100, 101) == FG_ERR_INVALID_TREE
+    assert lib.fg_filter_noalloc(None, None, 1, C.c_float(3.0), None, None, 0, None, None, None) == FG_ERR_INVALID_ARG
+    assert b"fixed scratch" in lib.fg_status_string(FG_ERR_SCRATCH)
