@@ -76,6 +76,8 @@ extern "C" {
 #define FG_STATUS_BAD_PARENT 4u     /* a parent index >= the child's index, a
                                        parent that is a leaf, or an ancestor chain
                                        longer than max_depth */
+#define FG_STATUS_GTC_UNDEFINED 8u  /* fg_gtc_tau: no view holds a Gaussian-tile
+                                       pair, so G_bar (Eq. (8)) is undefined */
 
 /* ---- inputs ------------------------------------------------------------ */
 
@@ -192,6 +194,46 @@ int fg_filter_noalloc(const fg_tree* tree, const fg_camera* cams, int32_t n_view
                       uint32_t* sel_bits, uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status,
                       void* stream);
 
+/* ---- the serial level-wise filter (the scheme Sec. 3.2 replaces) -------- */
+
+/* Children of every node as a CSR built from the parent links, for top-down
+ * walks: the children of node n are child_ids[child_offs[n] ..
+ * child_offs[n+1]), and a virtual node N holds the roots (child_offs has
+ * N + 2 entries, child_ids N; device). Sibling order is unspecified. A node
+ * whose parent index is not below its own is left out and
+ * FG_STATUS_BAD_PARENT is ORed into *status. Built once per tree.
+ * Errors: FG_ERR_INVALID_ARG, FG_ERR_INVALID_TREE, FG_ERR_WORKSPACE. */
+size_t fg_children_workspace_size(int64_t n_nodes);
+int fg_children(const int32_t* parent, int64_t n_nodes, int32_t* child_offs, int32_t* child_ids, uint32_t* status,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* Timing of one fg_filter_levelwise call (host struct). */
+typedef struct fg_levelwise_stats {
+    int32_t levels;   /* frontier levels evaluated */
+    int32_t pad;
+    int64_t visited;  /* nodes evaluated over all levels */
+    double calc_ms;   /* sum of the level kernels' durations (HIP events): T_calcu */
+    double wall_ms;   /* host wall time of the whole call; wall - calc is T_synch */
+} fg_levelwise_stats;
+
+/* The same selection as fg_filter for one camera, computed the serial way
+ * (Sec. 3.2, Eq. (3)): the cut grows from the roots one level at a time;
+ * each frontier node that passes R&L (in frustum, leaf or
+ * R_2D = 3 sqrt(lambda_max) <= tau_R) is selected and ends its branch, every
+ * other internal node passes its children to the next level. One kernel
+ * launch per level, after which the host reads the next frontier's size: the
+ * call SYNCHRONISES the stream once per level (it is the baseline the
+ * traversal-free filter is measured against, and cannot be graph-captured).
+ * Outputs (device): sel_bits [ceil(N/32)] as in fg_filter (order-free: a
+ * bitmask), *n_sel. child_offs / child_ids from fg_children. stats (host,
+ * may be NULL) receives the level count and the T_calcu / wall split.
+ * Errors: FG_ERR_INVALID_ARG, FG_ERR_INVALID_TREE, FG_ERR_WORKSPACE,
+ * FG_ERR_HIP; FG_STATUS_BAD_PARENT when the walk goes deeper than max_depth. */
+size_t fg_filter_levelwise_workspace_size(int64_t n_nodes);
+int fg_filter_levelwise(const fg_tree* tree, const int32_t* child_offs, const int32_t* child_ids,
+                        const fg_camera* cam, float tau_R, uint32_t* sel_bits, uint32_t* n_sel, uint32_t* status,
+                        void* ws, size_t ws_bytes, fg_levelwise_stats* stats, void* stream);
+
 /* ---- stage 2: projection and shrunk extents (Sec. 3.1, Sec. 3.3) -------- */
 
 /* For i < min(*n_sel, cap_sel), node g = sel_idx[i]: camera-space centre,
@@ -263,6 +305,46 @@ int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ran
               const float bg[3], float* image, float* final_T, uint32_t* n_contrib, int64_t cap_pairs,
               unsigned long long* frag_stats, uint32_t* status, void* ws, size_t ws_bytes, const fg_tune* tune,
               void* stream);
+
+/* ---- GTC pre-pass and the scene threshold (Sec. 3.3, Fig. 2(b)) -------- */
+
+/* For one view rendered by fg_filter, fg_preprocess (tau <= 0: the 3-sigma
+ * extents of the pre-rendering pass) and fg_sort, with the same camera:
+ *   kpc [cap_pairs] (device, entries [0, n_pairs) written): the key-value pair
+ *       contribution of each sorted pair k, Eq. (5): the sum over the pixels
+ *       of its tile of alpha * T for the pixels that blend that splat (the
+ *       tests and termination of Eq. (2), as fg_render; fragments skipped or
+ *       never reached add nothing). Each pixel's terms are float32 products
+ *       identical to the sequential blend's; their sum is float32 in an
+ *       unspecified order.
+ *   tile_gtc [n_tiles] (device): the tile's GTC, Eq. (6), the mean KPC over
+ *       all pairs of the tile, zero contributions included; NaN for a tile
+ *       without pairs (0/0).
+ *   view_gtc [2] (device float64): [0] the view's GTC, Eq. (7), the mean of
+ *       tile_gtc over the tiles that hold pairs (0 if none); [1] the number of
+ *       those tiles.
+ *   kpc_hist (device, optional): with n_edges ascending host values
+ *       hist_edges (1..16), counts are ADDED to kpc_hist[0 .. n_edges]: bin b
+ *       holds the pairs with hist_edges[b-1] <= KPC < hist_edges[b] (bin 0
+ *       below hist_edges[0], bin n_edges at or above the last edge); the
+ *       caller zeroes it. NULL with n_edges = 0: no histogram.
+ * n_pairs (device) and cap_pairs are the sort's pair count and capacity:
+ * when the sort overflowed (n_pairs > cap_pairs) every tile is left undefined
+ * and view_gtc = (NaN, -1), which fg_gtc_tau reports as an overflow.
+ * Errors: FG_ERR_INVALID_ARG (null pointers, bad edges). */
+int fg_gtc(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
+           const uint32_t* n_pairs, int64_t cap_pairs, float* kpc, float* tile_gtc, double* view_gtc, const float* hist_edges,
+           int32_t n_edges, uint32_t* kpc_hist, void* stream);
+
+/* Eq. (8) over n_views views: view_gtc [n_views][2] (device float64, each
+ * written by fg_gtc); g_bar (device float64) = the mean view GTC over the
+ * views that hold pairs; tau (device float32) = lambda_G / g_bar, rounded
+ * once from float64 (lambda_G = 0.2 in Sec. 4.1). With no such view, g_bar
+ * = 0, tau = NaN and FG_STATUS_GTC_UNDEFINED is ORed into *status (device,
+ * may be NULL); if a view's sort overflowed, g_bar = tau = NaN and
+ * FG_STATUS_PAIR_OVERFLOW is ORed in. Errors: FG_ERR_INVALID_ARG. */
+int fg_gtc_tau(const double* view_gtc, int32_t n_views, float lambda_G, double* g_bar, float* tau,
+               uint32_t* status, void* stream);
 
 /* ---- differentiable form (Sec. 3.1: differentiable splatting) ---------- */
 

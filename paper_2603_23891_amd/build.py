@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfg.so")
-SOURCES = ["fg_filter.hip", "fg_preprocess.hip", "fg_sort.hip", "fg_render.hip", "fg_backward.hip"]
+SOURCES = ["fg_filter.hip", "fg_preprocess.hip", "fg_sort.hip", "fg_render.hip", "fg_backward.hip", "fg_gtc.hip", "fg_levelwise.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -55,28 +55,6 @@ __global__ void k_zero(float* __restrict__ p, int64_t n)
         p[i] = 0.0f;
 }
 
-// DPP move within rows of 16 lanes.
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-
-// Sum over the 64 lanes, returned in every lane: DPP quad permutes and row
-// mirrors give every lane of a row of 16 its row's sum; row broadcasts (lane
-// 15 of rows 0 and 2 into rows 1 and 3, then lane 31 into rows 2 and 3) leave
-// the total in lane 63, and one lane read returns it.
-__device__ __forceinline__ float wave_total(float v)
-{
-    v = v + dpp_mov<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-    v = v + dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-    v = v + dpp_mov<0x141>(v);  // row_half_mirror
-    v = v + dpp_mov<0x140>(v);  // row_mirror
-    v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false));  // row_bcast:15
-    v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false));  // row_bcast:31
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-
 // Chunk items of long ranges (from the forward's saved state) and whole
 // tiles; see the header comment.
 struct BwdView {
@@ -86,6 +64,7 @@ struct BwdView {
     const uint32_t* n_items;  // device count of chunk items; null: no saved state
     const float* state;
     int chunk;
+    int64_t max_items;        // chunk items the workspace holds (bounds *n_items)
 };
 
 __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restrict__ xy,
@@ -111,7 +90,8 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
     const int lane = fgd::lane_id();
     const int wy0 = (tid / fgd::kWave) * (fgd::kWave / fgd::kTile);  // first pixel row of this wave
     const size_t plane = (size_t)W * H;
-    const int64_t n_chunk_items = view.n_items ? (int64_t)*view.n_items : 0;
+    int64_t n_chunk_items = view.n_items ? (int64_t)*view.n_items : 0;
+    if (n_chunk_items > view.max_items) n_chunk_items = view.max_items;
     for (int64_t item = blockIdx.x; item < n_chunk_items + n_tiles; item += gridDim.x) {
         // work item: a chunk of a long range, or a whole tile
         uint32_t tile;
@@ -119,6 +99,7 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
         int64_t citem = -1;
         if (item < n_chunk_items) {
             tile = view.mitem[item];
+            if ((int64_t)tile >= n_tiles) continue;  // not a map this frame's forward wrote
             const uint32_t nch = view.nch[tile];
             if ((int64_t)view.mfirst[tile] + nch > n_chunk_items) continue;  // tile item walks it whole
             lo = (int64_t)(item - view.mfirst[tile]) * view.chunk;
@@ -241,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
                     float mine = 0.0f;
 #pragma unroll
                     for (int k = 0; k < kNG; k++) {
-                        const float v = wave_total(gr[k]);
+                        const float v = fgd::wave_total(gr[k]);
                         mine = lane == k ? v : mine;
                     }
                     if (lane < kNG && mine != 0.0f) atomicAdd(gacc + (size_t)s_g[jj] * kNG + lane, mine);
@@ -500,10 +481,10 @@ extern "C" int fg_render_backward(const fg_params* p, const fg_camera* cam, cons
     if (cap_sel == 0 || m == 0) return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
     const int Wt = (cam->width + 15) / 16, Ht = (cam->height + 15) / 16;
     const int64_t n_tiles = (int64_t)Wt * Ht;
-    BwdView view = {nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+    BwdView view = {nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
     fgr::RenderWsView rv;
     if (image && fgr::render_ws_view(render_ws, render_ws_bytes, cam, cap_pairs, tune, &rv))
-        view = {rv.nch, rv.mfirst, rv.mitem, rv.counters, rv.state, rv.chunk};
+        view = {rv.nch, rv.mfirst, rv.mitem, rv.counters, rv.state, rv.chunk, rv.max_items};
     int64_t gb = n_tiles + (view.n_items ? rv.max_items : 0);
     if (gb > 8192) gb = 8192;
     hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)gb), dim3(kThreads), 0, s, (const float2*)splats->xy,

@@ -175,6 +175,29 @@ __device__ __forceinline__ float lambda_max(float a, float b, float c)
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
+// DPP move within rows of 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// Sum over the 64 lanes, returned in every lane: DPP quad permutes and row
+// mirrors give every lane of a row of 16 its row's sum; row broadcasts (lane
+// 15 of rows 0 and 2 into rows 1 and 3, then lane 31 into rows 2 and 3) leave
+// the total in lane 63, and one lane read returns it.
+__device__ __forceinline__ float wave_total(float v)
+{
+    v = v + dpp_mov<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v = v + dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v = v + dpp_mov<0x141>(v);  // row_half_mirror
+    v = v + dpp_mov<0x140>(v);  // row_mirror
+    v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
 // Conservative box, in tile-relative pixel coordinates (inclusive), of the

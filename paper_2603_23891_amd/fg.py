@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(HERE, "libfg.so")
 FG_STATUS_SEL_OVERFLOW = 1
 FG_STATUS_PAIR_OVERFLOW = 2
 FG_STATUS_BAD_PARENT = 4
+FG_STATUS_GTC_UNDEFINED = 8
 
 
 class FgError(RuntimeError):
@@ -59,13 +60,19 @@ class FgGrads(C.Structure):
                 ("sh", C.c_void_p)]
 
 
+class FgLevelwiseStats(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("pad", C.c_int32), ("visited", C.c_int64), ("calc_ms", C.c_double),
+                ("wall_ms", C.c_double)]
+
+
 class FgTune(C.Structure):
     _fields_ = [("render_batch", C.c_int32), ("radix_bits", C.c_int32), ("save_state", C.c_int32),
                 ("mask_items", C.c_int32), ("blend_events", C.c_void_p * 2)]
 
 
-EXPORTS = ["fg_filter_workspace_size", "fg_filter", "fg_filter_noalloc", "fg_preprocess", "fg_sort_workspace_size", "fg_sort",
-           "fg_render_workspace_size", "fg_render", "fg_activate", "fg_render_backward_workspace_size",
+EXPORTS = ["fg_filter_workspace_size", "fg_filter", "fg_filter_noalloc", "fg_children_workspace_size",
+           "fg_children", "fg_filter_levelwise_workspace_size", "fg_filter_levelwise", "fg_preprocess", "fg_sort_workspace_size", "fg_sort",
+           "fg_render_workspace_size", "fg_render", "fg_gtc", "fg_gtc_tau", "fg_activate", "fg_render_backward_workspace_size",
            "fg_render_backward", "fg_status_string"]
 
 _lib = None
@@ -85,6 +92,14 @@ def lib():
         L.fg_filter.argtypes = [vp, vp, C.c_int32, f32, vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
         L.fg_filter_noalloc.restype = i32
         L.fg_filter_noalloc.argtypes = [vp, vp, C.c_int32, f32, vp, vp, i64, vp, vp, vp]
+        L.fg_children_workspace_size.restype = C.c_size_t
+        L.fg_children_workspace_size.argtypes = [i64]
+        L.fg_children.restype = i32
+        L.fg_children.argtypes = [vp, i64, vp, vp, vp, vp, C.c_size_t, vp]
+        L.fg_filter_levelwise_workspace_size.restype = C.c_size_t
+        L.fg_filter_levelwise_workspace_size.argtypes = [i64]
+        L.fg_filter_levelwise.restype = i32
+        L.fg_filter_levelwise.argtypes = [vp, vp, vp, vp, f32, vp, vp, vp, vp, C.c_size_t, vp, vp]
         L.fg_preprocess.restype = i32
         L.fg_preprocess.argtypes = [vp, vp, f32, vp, vp, i64, vp, vp, vp]
         L.fg_sort_workspace_size.restype = C.c_size_t
@@ -95,6 +110,10 @@ def lib():
         L.fg_render_workspace_size.restype = C.c_size_t
         L.fg_render_workspace_size.argtypes = [vp, i64, vp]
         L.fg_render.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, C.c_size_t, vp, vp]
+        L.fg_gtc.restype = i32
+        L.fg_gtc.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, C.c_int32, vp, vp]
+        L.fg_gtc_tau.restype = i32
+        L.fg_gtc_tau.argtypes = [vp, C.c_int32, f32, vp, vp, vp, vp]
         L.fg_activate.restype = i32
         L.fg_activate.argtypes = [vp, vp, vp, vp]
         L.fg_render_backward_workspace_size.restype = C.c_size_t
@@ -231,6 +250,35 @@ def fg_filter_noalloc(tree: DeviceTree, cams, tau_R: float, sel_bits, sel_idx, c
            "fg_filter_noalloc")
 
 
+def fg_children(parent, n_nodes: int, child_offs, child_ids, status, ws, stream=None):
+    _check(lib().fg_children(_p(parent), n_nodes, _p(child_offs), _p(child_ids), _p(status), _p(ws),
+                             ws.numel() * ws.element_size(), _stream(stream)), "fg_children")
+
+
+def fg_filter_levelwise(tree: DeviceTree, child_offs, child_ids, cam, tau_R: float, sel_bits, n_sel, status, ws,
+                        stream=None) -> FgLevelwiseStats:
+    ts, cs = tree.struct(), camera_struct(cam)
+    st = FgLevelwiseStats()
+    _check(lib().fg_filter_levelwise(_ref(ts), _p(child_offs), _p(child_ids), _ref(cs), C.c_float(tau_R),
+                                     _p(sel_bits), _p(n_sel), _p(status), _p(ws), ws.numel() * ws.element_size(),
+                                     _ref(st), _stream(stream)), "fg_filter_levelwise")
+    return st
+
+
+class TreeChildren:
+    """Children of every node (CSR, built on the device by fg_children), for the
+    serial level-wise filter; plus that filter's workspace."""
+
+    def __init__(self, tree: DeviceTree, device="cuda"):
+        N = tree.n_nodes
+        self.offs = torch.empty(N + 2, dtype=torch.int32, device=device)
+        self.ids = torch.empty(max(N, 1), dtype=torch.int32, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        ws = torch.empty(lib().fg_children_workspace_size(N), dtype=torch.uint8, device=device)
+        fg_children(tree.parent, N, self.offs, self.ids, self.status, ws)
+        self.ws = torch.empty(lib().fg_filter_levelwise_workspace_size(N), dtype=torch.uint8, device=device)
+
+
 def fg_preprocess(tree: DeviceTree, cam, tau: float, sel_idx, n_sel, cap_sel: int, out: Splats, status,
                   stream=None):
     ts, cs, ss = tree.struct(), camera_struct(cam), out.struct()
@@ -259,6 +307,21 @@ def fg_render(splats: Splats, vals, ranges, cam, bg: Sequence[float], image, fin
                            _p(final_T), _p(n_contrib), cap_pairs, _p(frag_stats), _p(status), _p(ws),
                            ws.numel() * ws.element_size(), _ref(tune) if tune is not None else None,
                            _stream(stream)), "fg_render")
+
+
+def fg_gtc(splats: Splats, vals, ranges, cam, n_pairs, cap_pairs: int, kpc, tile_gtc, view_gtc, hist_edges=None,
+           kpc_hist=None, stream=None):
+    """hist_edges: None or a sequence of ascending floats (host); kpc_hist the device counts."""
+    ss, cs = splats.struct(), camera_struct(cam)
+    n_e = 0 if hist_edges is None else len(hist_edges)
+    ev = (C.c_float * max(n_e, 1))(*([float(e) for e in hist_edges] if n_e else [0.0]))
+    _check(lib().fg_gtc(_ref(ss), _p(vals), _p(ranges), _ref(cs), _p(n_pairs), cap_pairs, _p(kpc), _p(tile_gtc), _p(view_gtc),
+                        C.cast(ev, C.c_void_p) if n_e else None, n_e, _p(kpc_hist), _stream(stream)), "fg_gtc")
+
+
+def fg_gtc_tau(view_gtc, n_views: int, lambda_G: float, g_bar, tau, status=None, stream=None):
+    _check(lib().fg_gtc_tau(_p(view_gtc), n_views, C.c_float(lambda_G), _p(g_bar), _p(tau), _p(status),
+                            _stream(stream)), "fg_gtc_tau")
 
 
 # ---------------------------------------------------------------------------
@@ -335,6 +398,47 @@ def render_frame(tree: DeviceTree, cam, fb: FrameBuffers, tau_R: float = 3.0, ta
     preprocess_stage(tree, cam, fb, tau, stream)
     sort_stage(cam, fb, tune, stream)
     render_stage(cam, fb, bg, tune, stream)
+
+
+class GtcBuffers:
+    """Outputs of the GTC pre-pass for n_views views of one size: per-pair KPC
+    and per-tile GTC of the last view, the view GTCs, G_bar, tau, and one
+    status word per view (plus one for fg_gtc_tau)."""
+
+    def __init__(self, fb: FrameBuffers, n_views: int = 1, device="cuda"):
+        self.kpc = torch.empty(max(fb.cap_pairs, 1), dtype=torch.float32, device=device)
+        self.tile_gtc = torch.empty(fb.ranges.shape[0], dtype=torch.float32, device=device)
+        self.view_gtc = torch.zeros((n_views, 2), dtype=torch.float64, device=device)
+        self.g_bar = torch.zeros(1, dtype=torch.float64, device=device)
+        self.tau = torch.zeros(1, dtype=torch.float32, device=device)
+        self.status = torch.zeros(n_views + 1, dtype=torch.int32, device=device)
+
+
+def gtc_view_stage(cam, fb: FrameBuffers, gb: GtcBuffers, v: int = 0, hist_edges=None, kpc_hist=None,
+                   stream=None):
+    fg_gtc(fb.splats, fb.vals, fb.ranges, cam, fb.n_pairs, fb.cap_pairs, gb.kpc, gb.tile_gtc, gb.view_gtc[v],
+           hist_edges, kpc_hist, stream)
+
+
+def scene_tau(tree: DeviceTree, cams, fb: FrameBuffers, lambda_G: float = 0.2, tau_R: float = 3.0,
+              gb: Optional[GtcBuffers] = None, stream=None) -> GtcBuffers:
+    """The GTC pre-pass over training views (Fig. 2(b)): each view filtered,
+    projected with 3-sigma extents and sorted, its GTC accumulated; then
+    tau = lambda_G / G_bar on the device (gb.tau, gb.g_bar). Asynchronous:
+    each view's stages report into their own status word gb.status[v], and
+    fg_gtc_tau into gb.status[n_views]; all must read 0."""
+    cams = list(cams)
+    gb = gb or GtcBuffers(fb, len(cams))
+    for v, cam in enumerate(cams):
+        st = gb.status[v:v + 1]
+        fg_filter(tree, cam, tau_R, fb.sel_bits, fb.sel_idx, fb.cap_sel, fb.n_sel, st, fb.filter_ws, stream)
+        fg_preprocess(tree, cam, 0.0, fb.sel_idx, fb.n_sel, fb.cap_sel, fb.splats, st, stream)
+        fg_sort(fb.splats, fb.n_sel, fb.cap_sel, cam, fb.tile_keys, fb.vals, fb.cap_pairs, fb.n_pairs, fb.ranges, st,
+                fb.sort_ws, None, stream)
+        gtc_view_stage(cam, fb, gb, v, stream=stream)
+    n = len(cams)
+    fg_gtc_tau(gb.view_gtc, n, lambda_G, gb.g_bar, gb.tau, gb.status[n:n + 1], stream)
+    return gb
 
 
 def read_counts(fb: FrameBuffers):

@@ -89,3 +89,22 @@ def test_city1m_single_view(city1m, shrink):
         fg.render_frame(dtree, cam, fb, synth.TAU_R, tau, tune=fg.tune_struct(chunk))
         torch.cuda.synchronize()
         assert_frame_parity(read_frame(fb, tree.n_nodes), o)
+
+
+def test_city20m_scene_tau_on_gpu(city):
+    """The GTC pre-pass on the GPU over the 8 training views of the 20M-node
+    city reproduces the stored per-view GTCs, G_bar and tau (written by the
+    oracle's pre-pass); tolerance as in test_gpu_gtc."""
+    tree, dtree, tau = city
+    views = synth.city20m_training_views(8)
+    fb = fg.FrameBuffers(dtree, views[0].width, views[0].height, cap_sel=8_000_000, cap_pairs=48_000_000)
+    gb = fg.scene_tau(dtree, views, fb, synth.LAMBDA_G, synth.TAU_R)
+    torch.cuda.synchronize()
+    assert not gb.status.any(), gb.status
+    with open(os.path.join(ROOT, "tests", "golden", "city_tau.json")) as f:
+        ref = json.load(f)["city20m"]
+    vg = gb.view_gtc.cpu().numpy()
+    assert np.all(vg[:, 1] > 0)
+    assert np.allclose(vg[:, 0], ref["G_views"], rtol=2e-6, atol=0)
+    assert abs(gb.g_bar.item() - ref["G_bar"]) <= 2e-6 * ref["G_bar"]
+    assert abs(gb.tau.item() - tau) <= 5e-6 * tau
