@@ -7,6 +7,13 @@ Layouts follow the C-ABI: mean [3, M], log_scale [3, M], quat [4, M] (w, x, y,
 z), logit [M], sh [M, (D+1)^2, 3]. The activation (fg_activate), the four
 frame stages and the backward all run in the HIP kernels; this module only
 passes pointers and keeps the forward buffers for the backward.
+
+A renderer holds the state of its latest forward only: the backward of a
+frame must run before the next forward on the same renderer (and with the
+tune that forward used). Each forward is stamped with a generation number
+and its tune; a backward whose frame has been overwritten raises instead of
+returning the gradients of another frame. Render several views before one
+loss.backward() with one renderer per view.
 """
 from __future__ import annotations
 
@@ -45,6 +52,12 @@ class GaussianRenderer:
         self.fb = fg.FrameBuffers(self.tree, width, height, cap_sel=m, cap_pairs=cap_pairs, device=device,
                                   save_state=True)
         self.bwd_ws = torch.empty(fg.fg_render_backward_workspace_size(m), dtype=torch.uint8, device=device)
+        self.generation = 0     # number of forwards run so far
+        self._fwd_stamp = None  # (generation, tune fields) of the frame held in self.fb
+
+    def _tune_key(self):
+        t = self.tune
+        return (t.render_batch, t.radix_bits, t.save_state, t.mask_items)
 
     def forward(self, mean, log_scale, quat, logit, sh, cam, tau: float = 0.0, bg=(0.0, 0.0, 0.0)):
         t = self.tree
@@ -52,9 +65,23 @@ class GaussianRenderer:
         prm = fg.params_struct(mean, log_scale, quat, logit, sh, self.sh_degree)
         fg.fg_activate(prm, t.scale, t.opacity)
         fg.render_frame(t, cam, self.fb, tau_R=3.0e38, tau=tau, bg=bg, tune=self.tune)
+        self.generation += 1
+        self._fwd_stamp = (self.generation, self._tune_key())
         return self.fb.image
 
-    def backward(self, mean, log_scale, quat, logit, sh, cam, grad_image, bg=(0.0, 0.0, 0.0)):
+    def backward(self, mean, log_scale, quat, logit, sh, cam, grad_image, bg=(0.0, 0.0, 0.0),
+                 generation: int = None):
+        """generation: the number forward() stamped on the frame (None: the
+        latest frame). Raises if that frame's buffers were overwritten by a
+        later forward or the tune changed since."""
+        if self._fwd_stamp is None:
+            raise RuntimeError("GaussianRenderer.backward before any forward")
+        gen, key = self._fwd_stamp
+        if generation is not None and generation != gen:
+            raise RuntimeError(f"the frame of forward #{generation} was overwritten by forward #{gen} on this "
+                               "renderer: run each backward before the next forward, or use one renderer per view")
+        if key != self._tune_key():
+            raise RuntimeError("the renderer's tune changed between forward and backward")
         prm = fg.params_struct(mean, log_scale, quat, logit, sh, self.sh_degree)
         g = [torch.empty_like(x) for x in (mean, log_scale, quat, logit, sh)]
         grads = fg.FgGrads(*[x.data_ptr() for x in g])
@@ -73,11 +100,16 @@ class FilterGSRender(torch.autograd.Function):
     def forward(ctx, mean, log_scale, quat, logit, sh, renderer: GaussianRenderer, cam, tau, bg):
         args = [x.detach().contiguous() for x in (mean, log_scale, quat, logit, sh)]
         img = renderer.forward(*args, cam, tau, bg).clone()
+        n_sel, n_pairs, status = fg.read_counts(renderer.fb)  # synchronises
+        if status != 0:
+            raise fg.FgError(f"forward status {status:#x} (selected {n_sel} of capacity {renderer.fb.cap_sel}, "
+                             f"pairs {n_pairs} of capacity {renderer.fb.cap_pairs})")
         ctx.renderer, ctx.cam, ctx.bg = renderer, cam, bg
+        ctx.generation = renderer.generation
         ctx.save_for_backward(*args)
         return img
 
     @staticmethod
     def backward(ctx, grad_image):
-        g = ctx.renderer.backward(*ctx.saved_tensors, ctx.cam, grad_image, ctx.bg)
+        g = ctx.renderer.backward(*ctx.saved_tensors, ctx.cam, grad_image, ctx.bg, generation=ctx.generation)
         return (*g, None, None, None, None)
