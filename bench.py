@@ -123,6 +123,125 @@ def measure_pipelined(torch, dtree, cams, fb0, tau_R, tau, K):
     return dict(frames_in_flight=2, streams=2, frames=K, fps=K / wall, ms_per_frame=1e3 * wall / K)
 
 
+def measure_gtc_prepass(torch, dtree, fb, tau_golden, G_golden):
+    """The GTC pre-pass (Fig. 2(b)) on the GPU over the scene's 8 training
+    views: filter, 3-sigma preprocess, sort and fg_gtc per view, then
+    tau = lambda_G / G_bar (Eq. (8)) on the device; checked against the stored
+    tau of the oracle's pre-pass."""
+    from paper_2603_23891_amd import fg, synth
+    views = synth.city20m_training_views(8)
+    gb = fg.GtcBuffers(fb, len(views))
+    stream = torch.cuda.current_stream()
+    fg.scene_tau(dtree, views, fb, synth.LAMBDA_G, synth.TAU_R, gb)  # warm-up
+    torch.cuda.synchronize()
+    reps = 5
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record(stream)
+    for _ in range(reps):
+        fg.scene_tau(dtree, views, fb, synth.LAMBDA_G, synth.TAU_R, gb)
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    ms = e[0].elapsed_time(e[1]) / reps
+    assert not gb.status.any(), gb.status
+    # the KPC kernel alone, on the last view's sorted pairs
+    ek = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ek[0].record(stream)
+    for _ in range(reps):
+        fg.gtc_view_stage(views[-1], fb, gb, len(views) - 1)
+    ek[1].record(stream)
+    torch.cuda.synchronize()
+    n_pairs_last = fg.read_counts(fb)[1]
+    tau = float(gb.tau.item())
+    out = dict(views=len(views), ms=ms, ms_per_view=ms / len(views), tau=tau, G_bar=float(gb.g_bar.item()),
+               tau_stored=tau_golden, G_bar_stored=G_golden, tau_rel_err=abs(tau - tau_golden) / tau_golden,
+               kpc_kernel_ms_last_view=ek[0].elapsed_time(ek[1]) / reps, pairs_last_view=n_pairs_last,
+               workload="8 training views of the 20M-node city, 1920x1080, 3-sigma extents")
+    log(f"GTC pre-pass: {ms:.2f} ms for 8 views, tau {tau:.7f} (stored {tau_golden:.7f})")
+    assert out["tau_rel_err"] <= 5e-6, out
+    return out
+
+
+def measure_serial_filter(torch, dtree, cams, fb, tau_R, n_frames=8):
+    """The serial level-by-level filter (Eq. (3), the scheme of Table 2's
+    serial rows) against the traversal-free fg_filter on the same frames:
+    T_calcu (its level kernels), T_synch (host round trips between levels)
+    and the parallel filter's event time; selections compared."""
+    from paper_2603_23891_amd import fg
+    ch = fg.TreeChildren(dtree)
+    N = dtree.n_nodes
+    bits = torch.empty(max((N + 31) // 32, 1), dtype=torch.int32, device="cuda")
+    n_lw = torch.zeros(1, dtype=torch.int32, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for k in range(n_frames + 1):
+        cam = cams[k % len(cams)]
+        s = fg.fg_filter_levelwise(dtree, ch.offs, ch.ids, cam, tau_R, bits, n_lw, st, ch.ws)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        fg.filter_stage(dtree, cam, fb, tau_R)
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(bits, fb.sel_bits)) and int(n_lw.item()) == fg.read_counts(fb)[0]
+        assert same and int(st.item()) == 0 and int(ch.status.item()) == 0, f"frame {k}"
+        if k == 0:
+            continue  # warm-up
+        rows.append((s.levels, s.visited, s.calc_ms, s.wall_ms, e[0].elapsed_time(e[1])))
+    a = np.asarray(rows, np.float64)
+    out = dict(frames=n_frames, levels=int(a[0, 0]), visited_mean=float(a[:, 1].mean()),
+               calc_ms=float(np.median(a[:, 2])), synch_ms=float(np.median(a[:, 3] - a[:, 2])),
+               serial_wall_ms=float(np.median(a[:, 3])), parallel_filter_ms=float(np.median(a[:, 4])),
+               same_selection=True)
+    out["serial_over_parallel"] = out["serial_wall_ms"] / out["parallel_filter_ms"]
+    log(f"serial filter: {out['serial_wall_ms']:.3f} ms ({out['calc_ms']:.3f} calc + {out['synch_ms']:.3f} synch, "
+        f"{out['levels']} levels) vs parallel {out['parallel_filter_ms']:.3f} ms")
+    return out
+
+
+def measure_lambda_sweep(torch, dtree, cams, fb, tau_R, G_bar, n_frames=16):
+    """Shrink strength sweep (synthetic analogue of the Fig. 5 / Fig. 7 tables and
+    Fig. 6(b)): the 3-sigma rule, the fixed 1/255 threshold and tau = lambda_G /
+    G_bar for several lambda_G, each over the first frames of the fly-through:
+    FPS, pairs per frame and the pairs with KPC < 0.01 (N_low) and < 0.05, the
+    KPC measured on each frame's own (shrunk) pairs."""
+    from paper_2603_23891_amd import fg
+    edges = [0.01, 0.05]
+    gb = fg.GtcBuffers(fb, 1)
+    hist = torch.zeros(len(edges) + 1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    settings = [("3sigma", 0.0), ("1/255", 1.0 / 255.0)] + \
+        [(f"lambda_G={lg}", lg / G_bar) for lg in (0.02, 0.05, 0.1, 0.2, 0.3, 0.43)]
+    out = []
+    for name, tau in settings:
+        for k in range(2):
+            fg.render_frame(dtree, cams[k], fb, tau_R, tau)
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        for k in range(n_frames):
+            fg.render_frame(dtree, cams[k], fb, tau_R, tau)
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        ms = e[0].elapsed_time(e[1]) / n_frames
+        hist.zero_()
+        n_pairs = 0
+        for k in range(n_frames):
+            fg.render_frame(dtree, cams[k], fb, tau_R, tau)
+            fg.gtc_view_stage(cams[k], fb, gb, 0, edges, hist)
+            torch.cuda.synchronize()
+            c = fg.read_counts(fb)
+            assert c[2] == 0, (name, k, c)
+            n_pairs += c[1]
+        h = hist.cpu().numpy().astype(np.int64)
+        out.append(dict(setting=name, tau=tau, fps=1e3 / ms, ms_per_frame=ms, n_pairs_mean=n_pairs / n_frames,
+                        n_low_mean=float(h[0]) / n_frames, n_below_005_mean=float(h[0] + h[1]) / n_frames,
+                        frac_low=float(h[0]) / max(n_pairs, 1)))
+        log(f"  {name:>16}: tau {tau:.5f} {1e3 / ms:7.1f} FPS, N_P {n_pairs / n_frames / 1e6:.3f}M, "
+            f"N_low {h[0] / n_frames / 1e6:.3f}M")
+    return dict(frames=n_frames, rows=out, kpc_edges=edges,
+                workload="first 16 frames of the 20M-node city fly-through, 1920x1080")
+
+
 def measure_fwd_bwd(torch):
     """Differentiable forward + backward of 2M raw Gaussians (SH degree 3) at
     1920x1080 against a seeded uniform target with an L1 loss: ms per view for
@@ -147,7 +266,8 @@ def measure_fwd_bwd(torch):
         step(cam)
     torch.cuda.synchronize()
     from paper_2603_23891_amd import fg
-    n_sel = fg.read_counts(r.fb)[0]
+    n_sel, n_pairs, status = fg.read_counts(r.fb)
+    assert status == 0, f"fwd+bwd status {status}"
 
     def timed(cams):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(cams) + 1)]
@@ -169,8 +289,21 @@ def measure_fwd_bwd(torch):
     r.backward(*dev, views[3], dl)
     e[2].record(stream)
     torch.cuda.synchronize()
+    n_sel, n_pairs, status = fg.read_counts(r.fb)
+    assert status == 0, f"fwd+bwd status {status}"
+    # blended fragments of that view (the backward revisits exactly these)
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    fg.render_stage(views[3], r.fb, tune=r.tune, frag_stats=stats)
+    torch.cuda.synchronize()
+    blended = int(stats[3].item())
+    bwd_ms = e[1].elapsed_time(e[2])
+    # the projection backward's bytes: 236 B of parameters read and 236 B of
+    # gradients written per Gaussian, 36 B of splat gradients read
     out = dict(one_view_ms=float(np.median(one)), batch8_ms_per_view=float(np.mean(batch)),
-               forward_ms=e[0].elapsed_time(e[1]), backward_ms=e[1].elapsed_time(e[2]), n_gaussians=2_000_000,
+               forward_ms=e[0].elapsed_time(e[1]), backward_ms=bwd_ms, n_gaussians=2_000_000,
+               n_pairs_central_view=n_pairs, blended_fragments_central_view=blended,
+               backward_blended_fragments_per_s=blended / (bwd_ms * 1e-3),
+               backward_projection_bytes=2_000_000 * (236 + 236 + 36),
                n_rendered_central_view=n_sel,
                workload="2M raw Gaussians (city1m leaf law in view), SH3, 1920x1080, L1 loss vs seeded U[0,1] target")
     log(f"fwd+bwd: {out['one_view_ms']:.3f} ms/view (1 view), {out['batch8_ms_per_view']:.3f} ms/view (batch of 8)")
@@ -236,6 +369,47 @@ def measure_batch(torch, dtree, tau_R, tau):
     return out
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(tree, cams, tau_R, tau, counts, gpu_frame_ms, frames=(0, 1, 2, 3)):
+    """The oracle (all four stages) on the first fly-through frames, on every
+    host core this process may use (its OpenMP build: the same operations per
+    node, Gaussian and tile) and on one thread; each frame's counts checked
+    against the GPU's."""
+    import oracle
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    res = {}
+    for label, n in (("all_cores", cores), ("one_thread", None)):
+        used = oracle.set_threads(n)
+        per = []
+        for k in frames:
+            t1 = time.perf_counter()
+            ref = oracle.render_frame(tree, cams[k], tau_R, tau)
+            per.append(time.perf_counter() - t1)
+            assert ref["sel_idx"].size == counts[k]["n_sel"] and ref["keys"].size == counts[k]["n_pairs"], k
+        res[label] = dict(threads=used, s_per_frame=per)
+        log(f"  oracle ({label}, {used} threads): {np.mean(per):.2f} s/frame")
+    oracle.set_threads(None)
+    allc = res["all_cores"]
+    sec = float(np.mean(allc["s_per_frame"]))
+    return dict(value=1.0 / sec, unit="frames/s", cores=allc["threads"], kind="oracle",
+                sample=f"fly-through frames {list(frames)}, all four stages, C oracle with OpenMP on "
+                       f"{allc['threads']} threads (os.cpu_count() {os.cpu_count()}, {cpu_model()})",
+                ms_per_frame=1e3 * sec, ms_per_frame_one_thread=1e3 * float(np.mean(res["one_thread"]["s_per_frame"])),
+                one_thread_value=1.0 / float(np.mean(res["one_thread"]["s_per_frame"])),
+                per_frame_s=dict(all_cores=allc["s_per_frame"], one_thread=res["one_thread"]["s_per_frame"]),
+                gpu_ms_per_frame_same_frames=float(np.mean([gpu_frame_ms[k] for k in frames])),
+                cpu_model=cpu_model(), nproc=os.cpu_count())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +418,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy three times (calibrates HBM counters)")
     args = ap.parse_args()
@@ -258,7 +433,8 @@ def main():
     torch.cuda.set_device(0)
     fg.lib()
     with open(os.path.join(ROOT, "tests", "golden", "city_tau.json")) as f:
-        tau = float(json.load(f)["city20m"]["tau"])
+        stored = json.load(f)["city20m"]
+    tau = float(stored["tau"])
     tau_R = synth.TAU_R
 
     t0 = time.time()
@@ -374,20 +550,15 @@ def main():
                     ops_per_launch=tot["blend_ops"] / f)
 
     pipelined = measure_pipelined(torch, dtree, cams, fb, tau_R, tau, K)
+    gtc = measure_gtc_prepass(torch, dtree, fb, tau, float(stored["G_bar"]))
+    serial = measure_serial_filter(torch, dtree, cams, fb, tau_R)
+    sweep = None if args.no_sweep else measure_lambda_sweep(torch, dtree, cams, fb, tau_R, gtc["G_bar"])
     batched = None if args.no_batch else measure_batch(torch, dtree, tau_R, tau)
     fwd_bwd = None if args.no_backward else measure_fwd_bwd(torch)
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        log("CPU oracle on frame 0 ...")
-        t1 = time.perf_counter()
-        ref = oracle.render_frame(tree, cams[0], tau_R, tau)
-        dt = time.perf_counter() - t1
-        assert ref["sel_idx"].size == counts[0]["n_sel"] and ref["keys"].size == counts[0]["n_pairs"]
-        cpu = dict(value=1.0 / dt, unit="frames/s", cores=1, kind="oracle",
-                   sample=f"frame 0 of the fly-through, all four stages, single-threaded C ({dt:.1f} s)")
-        log(f"  oracle frame 0: {dt:.1f} s")
+        cpu = cpu_baseline(tree, cams, tau_R, tau, counts, frame_ms)
 
     cnt = {k: [c[k] for c in counts] for k in counts[0]}
     out = {
@@ -407,6 +578,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "two_frames_in_flight": pipelined,
+        "gtc_prepass": gtc,
+        "serial_filter": serial,
+        "lambda_sweep": sweep,
         "batched_views": batched,
         "fwd_bwd_ms_per_view": fwd_bwd,
     }

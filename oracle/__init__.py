@@ -3,8 +3,10 @@
 Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package. The product path (the HIP
 library ``libfg.so`` and its Python binding) never imports it, and the two
-share no code: this package wraps ``fg_oracle.c``, a plain single-threaded C
-implementation written from the paper (see the header of that file).
+share no code: this package wraps ``fg_oracle.c``, a plain C implementation
+written from the paper (see the header of that file), single-threaded by
+default; ``set_threads(n)`` switches to the OpenMP build of the same source,
+used only to time the oracle on all host cores (results are bit-identical).
 """
 from __future__ import annotations
 
@@ -17,17 +19,31 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "fg_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")  # same source with -fopenmp: for timing on all cores
 
-_lib = None
+_libs = {}
+_threads = None  # None: the plain single-threaded build; n: the OpenMP build with n threads
 
 
 def build() -> str:
-    """Compile the oracle with IEEE binary32 semantics (no contraction, no fast math)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-           "-fno-finite-math-only", "-Wall", "-o", LIB + ".tmp", SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    """Compile the oracle with IEEE binary32 semantics (no contraction, no fast
+    math): the plain build the tests use, and an OpenMP build of the same
+    source for the benchmark's timing (bit-identical results)."""
+    base = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+            "-fno-finite-math-only", "-Wall"]
+    for out, extra in ((LIB, ["-Wno-unknown-pragmas"]), (LIB_OMP, ["-fopenmp"])):
+        subprocess.run(base + extra + ["-o", out + ".tmp", SRC, "-lm"], check=True)
+        os.replace(out + ".tmp", out)
     return LIB
+
+
+def set_threads(n=None) -> int:
+    """n = None: the plain single-threaded oracle (the default); n >= 1: the
+    OpenMP build with n threads. Returns the thread count in use."""
+    global _threads
+    _threads = n
+    L = lib()
+    return int(L.fgo_set_threads(int(n))) if n is not None else 1
 
 
 class _Tree(C.Structure):
@@ -50,11 +66,11 @@ SPLAT_DTYPE = np.dtype([("u", "<f4"), ("v", "<f4"), ("A", "<f4"), ("B", "<f4"), 
 
 
 def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    path = LIB if _threads is None else LIB_OMP
+    if path not in _libs:
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
             build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(path)
         vp, i64, f32 = C.c_void_p, C.c_int64, C.c_float
         L.fgo_exp.restype = f32; L.fgo_exp.argtypes = [f32]
         L.fgo_log.restype = f32; L.fgo_log.argtypes = [f32]
@@ -72,9 +88,10 @@ def lib():
         L.fgo_kpc.argtypes = [vp, vp, vp, vp, vp]
         L.fgo_activate.argtypes = [vp, vp, i64, vp, vp]
         L.fgo_replay64.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.fgo_set_threads.restype = C.c_int; L.fgo_set_threads.argtypes = [C.c_int]
         assert L.fgo_splat_size() == SPLAT_DTYPE.itemsize
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _ptr(a: np.ndarray):

@@ -24,11 +24,19 @@
  * the operation order written here, round-to-nearest, no contraction
  * (-ffp-contract=off), correctly rounded division and square root, and two
  * transcendental functions defined below from published methods).
+ *
+ * Threads: built with -fopenmp (the timing build), the loops over nodes,
+ * selected Gaussians and tiles whose iterations write disjoint outputs are
+ * shared among threads. Each unit is still evaluated by the same operations
+ * in the same order, so results are bit-identical to the plain build.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct fgo_tree {
     int64_t n;               /* nodes */
@@ -221,6 +229,7 @@ static int node_frustum(const fgo_tree* t, const fgo_camera* c, int64_t n, float
  * bit 3 = selected (R&L and no ancestor passes R&L). */
 void fgo_node_predicates(const fgo_tree* t, const fgo_camera* c, float tau_R, uint8_t* out)
 {
+    #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < t->n; n++) {
         float pc[3];
         int f = node_frustum(t, c, n, pc);
@@ -229,12 +238,29 @@ void fgo_node_predicates(const fgo_tree* t, const fgo_camera* c, float tau_R, ui
         int rl = f && (leaf || small);
         out[n] = (uint8_t)(f | (small << 1) | (rl << 2));
     }
+    uint8_t* selv = (uint8_t*)malloc((size_t)(t->n > 0 ? t->n : 1));
+    #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < t->n; n++) {
         int sel = (out[n] >> 2) & 1;
         for (int32_t a = t->parent[n]; sel && a >= 0; a = t->parent[a])
             if ((out[a] >> 2) & 1) sel = 0;
-        out[n] |= (uint8_t)(sel << 3);
+        selv[n] = (uint8_t)sel;
     }
+    for (int64_t n = 0; n < t->n; n++) out[n] |= (uint8_t)(selv[n] << 3);
+    free(selv);
+}
+
+/* Threads for the loops marked above (the -fopenmp build); returns the count
+ * that will be used (always 1 in the plain build). */
+int fgo_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* R&L + Ancestor filter for every node independently, then the selected
@@ -398,6 +424,7 @@ static void preprocess_one(const fgo_tree* t, const fgo_camera* c, float tau, in
 void fgo_preprocess(const fgo_tree* t, const fgo_camera* c, float tau, const uint32_t* sel_idx, int64_t n_sel,
                     fgo_splat* out)
 {
+    #pragma omp parallel for schedule(dynamic, 4096)
     for (int64_t i = 0; i < n_sel; i++) preprocess_one(t, c, tau, (int64_t)sel_idx[i], &out[i]);
 }
 
@@ -508,9 +535,9 @@ void fgo_render(const fgo_splat* s, const uint32_t* vals, const uint32_t* ranges
 {
     int W = c->width, H = c->height;
     int Wt = (W + 15) / 16, Ht = (H + 15) / 16;
-    for (int ty = 0; ty < Ht; ty++)
-        for (int tx = 0; tx < Wt; tx++) {
-            int t = ty * Wt + tx;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < Wt * Ht; t++) {
+            int ty = t / Wt, tx = t % Wt;
             for (int py = ty * 16; py < ty * 16 + 16 && py < H; py++)
                 for (int px = tx * 16; px < tx * 16 + 16 && px < W; px++) {
                     float C[3], T;
@@ -568,9 +595,9 @@ void fgo_kpc(const fgo_splat* s, const uint32_t* vals, const uint32_t* ranges, c
     for (int t = 0; t < Wt * Ht; t++)
         if (ranges[2 * t + 1] > np) np = ranges[2 * t + 1];
     for (uint32_t k = 0; k < np; k++) kpc[k] = 0.0;
-    for (int ty = 0; ty < Ht; ty++)
-        for (int tx = 0; tx < Wt; tx++) {
-            int t = ty * Wt + tx;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < Wt * Ht; t++) {
+            int ty = t / Wt, tx = t % Wt;
             for (int py = ty * 16; py < ty * 16 + 16 && py < H; py++)
                 for (int px = tx * 16; px < tx * 16 + 16 && px < W; px++) {
                     float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
