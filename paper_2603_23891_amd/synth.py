@@ -17,8 +17,11 @@ Tree layout (the one the C-ABI reads):
   (uint8: bit 0 = leaf, bits 1-4 = depth).
 
 The tree model follows the paper's hierarchical Gaussian tree (Sec. 3.1,
-"Hierarchical Gaussian Tree"): every node is a complete Gaussian. Parents are
-built bottom-up as moment-matched merges of their (up to 8) children.
+"Hierarchical Gaussian Tree"): every node is a complete Gaussian. The city
+trees are built bottom-up (parents are moment-matched merges of their up to 8
+children); ``topdown_tree`` builds the paper's own canonical construction top
+down (children placed at oriented offsets of the parent, shrunk by gamma,
+inheriting rotation, colour and opacity).
 """
 from __future__ import annotations
 
@@ -422,6 +425,70 @@ def flythrough(n_frames: int, seed: int = 1, n_ctrl: int = 8, half_extent: float
     return cams
 
 
+@dataclasses.dataclass
+class TopDownSpec:
+    """A tree built top-down by the canonical recursive construction of
+    Sec. 3.1: every parent v places 8 children at mu_v + R(q_v) o_k, o_k the
+    eight sign combinations of (s_x/2, s_y/2, s_z/2) of the parent's scale;
+    each child's scale is gamma * s_v, and its rotation, colour and opacity are
+    the parent's."""
+    n_roots: int
+    depth: int                     # levels below the roots; leaves at this depth
+    box: Sequence[float]           # root centres: x, y uniform in [-h, h], z uniform in [0, z_max]
+    root_scale: Sequence[float]    # (s_x, s_y, s_z) of every root, world units
+    gamma: float = 0.5
+    logit_mu: float = 0.0
+    logit_sd: float = 1.5
+    sh_degree: int = 3
+    sh_sd: float = 0.3
+    seed: int = 0
+
+
+def topdown_tree(spec: TopDownSpec) -> Tree:
+    """Level order, the 8 children of a node contiguous (in sign order) in the
+    next level. Roots: seeded centres in the box, rotations about the vertical
+    axis only (uniform yaw), opacity sigmoid(N(logit_mu, logit_sd)), SH
+    coefficients N(0, sh_sd)."""
+    rng = np.random.default_rng(spec.seed)
+    R0 = spec.n_roots
+    hx, hy, zmax = spec.box
+    mean = np.stack([rng.uniform(-hx, hx, R0), rng.uniform(-hy, hy, R0), rng.uniform(0.0, zmax, R0)], 1)
+    yaw = rng.uniform(-math.pi, math.pi, R0)
+    quat = np.stack([np.cos(yaw / 2), np.zeros(R0), np.zeros(R0), np.sin(yaw / 2)], 1)  # (w, x, y, z)
+    rot = Rotation.from_quat(quat[:, [1, 2, 3, 0]]).as_matrix()                      # [R0, 3, 3]
+    scale = np.tile(np.asarray(spec.root_scale, np.float64), (R0, 1))
+    op = _sigmoid(rng.normal(spec.logit_mu, spec.logit_sd, R0))
+    K = SH_COEFFS[spec.sh_degree]
+    sh = rng.normal(0.0, spec.sh_sd, (R0, K, 3))
+    signs = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], np.float64)  # [8, 3]
+    # R(q_v) o_k for a root's own scale; a node at level l has scale gamma^l s_root
+    # and its root's rotation, so its children's offsets are gamma^l times these
+    root_off = np.einsum("rij,rkj->rki", rot, signs[None, :, :] * (scale[:, None, :] / 2.0))  # [R0, 8, 3]
+    levels = [(mean, scale, np.arange(R0), np.full(R0, -1, np.int64))]  # (means, scales, root id, parent)
+    offs = [0, R0]
+    for lvl in range(spec.depth):
+        pm, ps, proot, _ = levels[-1]
+        m = pm.shape[0]
+        cm = pm[:, None, :] + (spec.gamma ** lvl) * root_off[proot]         # mu_v + R(q_v) o_k
+        cs = np.repeat(ps * spec.gamma, 8, axis=0)
+        croot = np.repeat(proot, 8)
+        par = offs[-2] + np.repeat(np.arange(m), 8)
+        levels.append((cm.reshape(-1, 3), cs, croot, par))
+        offs.append(offs[-1] + 8 * m)
+    N = offs[-1]
+    mean_all = np.concatenate([l[0] for l in levels], 0)
+    scale_all = np.concatenate([l[1] for l in levels], 0)
+    root_all = np.concatenate([l[2] for l in levels], 0)
+    parent = np.concatenate([l[3] for l in levels], 0).astype(np.int32)
+    depth = np.concatenate([np.full(l[0].shape[0], d, np.uint8) for d, l in enumerate(levels)])
+    flags = ((depth == spec.depth).astype(np.uint8) | (depth << 1)).astype(np.uint8)
+    sizes = [int(l[0].shape[0]) for l in levels]
+    return Tree(mean=mean_all.T.astype(np.float32).copy(), scale=scale_all.T.astype(np.float32).copy(),
+                quat=quat.astype(np.float32).T.copy()[:, root_all], opacity=op.astype(np.float32)[root_all],
+                sh=sh.astype(np.float32)[root_all], parent=parent, flags=flags, sh_degree=spec.sh_degree,
+                n_internal_span=int(offs[-2]), max_depth=spec.depth, level_sizes=sizes)
+
+
 # --------------------------------------------------------------------------
 # named workloads
 # --------------------------------------------------------------------------
@@ -434,6 +501,15 @@ CITY1M = CitySpec(n_leaves=1_000_000, box=(100.0, 100.0, 30.0), n_blobs=64, blob
                   leaf_log_scale_mu=-3.5, seed=0)
 CITY20M = CitySpec(n_leaves=17_500_000, box=(300.0, 300.0, 50.0), n_blobs=256, blob_sigma=(6.0, 6.0, 0.02),
                    leaf_log_scale_mu=-3.5, seed=0)
+# The canonical top-down construction (Sec. 3.1) on the city's footprint:
+# 32768 flat roots of 0.7 m half-extent, three levels of 8 children (19.2M
+# nodes), leaves 9 cm across, opacity logits N(2.5, 0.5) inherited down each
+# tree. The construction stacks children at +-s_z/2, so every level doubles
+# the coincident layers: the scene is congested by design, its GTC is low and
+# its threshold tau (Eq. (8)) high. With tau_R = 3 px the fly-through's cuts
+# keep leaves near the camera and their parents farther away.
+TOPDOWN20M = TopDownSpec(n_roots=32768, depth=3, box=(240.0, 240.0, 10.0), root_scale=(0.7, 0.7, 0.05),
+                         logit_mu=2.5, logit_sd=0.5, seed=0)
 CITY_PITCH_DEG = -20.0
 CITY_ALTITUDE = 40.0
 LAMBDA_G = 0.2   # Sec. 4.1: shrink aggressiveness used in all experiments
