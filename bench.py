@@ -123,6 +123,38 @@ def measure_pipelined(torch, dtree, cams, fb0, tau_R, tau, K):
     return dict(frames_in_flight=2, streams=2, frames=K, fps=K / wall, ms_per_frame=1e3 * wall / K)
 
 
+def measure_graph_flythrough(torch, dtree, cams, tau_R, tau, K):
+    """The same fly-through with the frame captured once as a HIP graph (the
+    four stages, one view) and replayed per frame after a device-to-device
+    copy of that frame's pose into the graph's camera array (poses prepared on
+    the device beforehand). Reported beside `value`."""
+    from paper_2603_23891_amd import batch, fg
+    br = batch.BatchedRenderer(dtree, [cams[0]], cap_sel=8_000_000, cap_pairs=48_000_000)
+    arr, _ = fg.camera_array(list(cams))
+    poses = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).cuda().view(len(cams), -1)
+    br.capture(tau_R, tau)
+
+    def frame(k):
+        br.cams_dev.copy_(poses[k % len(cams)])
+        br.replay()
+
+    for k in range(3):
+        frame(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        frame(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ns, npairs, status = br.counts()
+    assert status == 0, status
+    log(f"graph replay per frame: {K / wall:.1f} FPS")
+    out = dict(frames=K, fps=K / wall, ms_per_frame=1e3 * wall / K)
+    del br
+    torch.cuda.empty_cache()
+    return out
+
+
 def measure_gtc_prepass(torch, dtree, fb, tau_golden, G_golden):
     """The GTC pre-pass (Fig. 2(b)) on the GPU over the scene's 8 training
     views: filter, 3-sigma preprocess, sort and fg_gtc per view, then
@@ -242,6 +274,98 @@ def measure_lambda_sweep(torch, dtree, cams, fb, tau_R, G_bar, n_frames=16):
                 workload="first 16 frames of the 20M-node city fly-through, 1920x1080")
 
 
+def fps_over(torch, dtree, cams, fb, tau_R, tau, K):
+    """Frames per second over K frames of cams (wall time between device
+    synchronisations), and each frame's counts from an untimed second pass."""
+    from paper_2603_23891_amd import fg
+    for k in range(3):
+        fg.render_frame(dtree, cams[k % len(cams)], fb, tau_R, tau)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        fg.render_frame(dtree, cams[k % len(cams)], fb, tau_R, tau)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_sel, n_pairs = [], []
+    for k in range(min(K, len(cams))):
+        fg.render_frame(dtree, cams[k], fb, tau_R, tau)
+        c = fg.read_counts(fb)
+        assert c[2] == 0, (k, c)
+        n_sel.append(c[0])
+        n_pairs.append(c[1])
+    return dict(fps=K / wall, ms_per_frame=1e3 * wall / K, n_sel_mean=float(np.mean(n_sel)),
+                n_pairs_mean=float(np.mean(n_pairs)))
+
+
+def measure_topdown(torch, tau_R, stored, K):
+    """The second tree workload: the canonical top-down construction of
+    Sec. 3.1 (4096 roots, four levels of 8 children, 19.2M nodes) on the same
+    fly-through; its GTC threshold from the GPU pre-pass over the same 8
+    training views, checked against the oracle's stored value."""
+    from paper_2603_23891_amd import fg, synth
+    t0 = time.time()
+    tree = synth.topdown_tree(synth.TOPDOWN20M)
+    dtree = fg.DeviceTree(tree)
+    log(f"top-down tree: {tree.n_nodes} nodes, levels {tree.level_sizes}, {time.time() - t0:.1f} s")
+    cams = synth.city20m_frames(64)
+    fb = fg.FrameBuffers(dtree, 1920, 1080, cap_sel=10_000_000, cap_pairs=48_000_000)
+    gb = fg.scene_tau(dtree, synth.city20m_training_views(8), fb, synth.LAMBDA_G, tau_R)
+    torch.cuda.synchronize()
+    assert not gb.status.any(), gb.status
+    tau = float(gb.tau.item())
+    out = dict(nodes=tree.n_nodes, levels=tree.level_sizes, tau_gpu=tau, G_bar_gpu=float(gb.g_bar.item()))
+    if stored is not None:
+        out["tau_stored"] = float(stored["tau"])
+        out["tau_rel_err"] = abs(tau - out["tau_stored"]) / out["tau_stored"]
+        assert out["tau_rel_err"] <= 5e-6, out
+    out["gtc"] = fps_over(torch, dtree, cams, fb, tau_R, tau, K)
+    out["3sigma"] = fps_over(torch, dtree, cams, fb, tau_R, 0.0, K)
+    # cut levels of the middle frame
+    fg.filter_stage(dtree, cams[32], fb, tau_R)
+    n_sel = fg.read_counts(fb)[0]
+    sel = fb.sel_idx[:n_sel].cpu().numpy()
+    offs = np.cumsum([0] + tree.level_sizes)
+    out["frame32_selected_per_level"] = np.bincount(np.searchsorted(offs, sel, side="right") - 1,
+                                                    minlength=len(tree.level_sizes)).tolist()
+    out["workload"] = "top-down canonical tree (Sec. 3.1), 19.2M nodes, 64-frame 1080p fly-through"
+    log(f"top-down: {out['gtc']['fps']:.1f} FPS with GTC tau {tau:.5f}, {out['3sigma']['fps']:.1f} FPS at 3 sigma")
+    del dtree, fb, gb
+    torch.cuda.empty_cache()
+    return out
+
+
+def measure_flat3dgs(torch, stored, K):
+    """No LoD (the 3DGS rows of the Fig. 5 table): the 2M-Gaussian flat set, all
+    root leaves, rendered by the same four stages under the 3-sigma rule, the
+    fixed 1/255 threshold and its own GTC threshold (GPU pre-pass over its
+    view, checked against the oracle's stored value)."""
+    from paper_2603_23891_amd import diff, fg, synth
+    g = synth.flat_gaussians(2_000_000, seed=0)
+    dev = [torch.from_numpy(a).cuda() for a in (g.mean, g.log_scale, g.quat, g.logit, g.sh)]
+    t = diff._FlatTree(2_000_000, g.sh_degree, "cuda")
+    t.mean, t.quat, t.sh = dev[0], dev[2], dev[4]
+    fg.fg_activate(fg.params_struct(*dev, g.sh_degree), t.scale, t.opacity)
+    cam = synth.city1m_yaw_views()[3]
+    fb = fg.FrameBuffers(t, 1920, 1080, cap_sel=2_000_000, cap_pairs=24_000_000)
+    gb = fg.scene_tau(t, [cam], fb, synth.LAMBDA_G, 1e30)
+    torch.cuda.synchronize()
+    assert not gb.status.any(), gb.status
+    tau = float(gb.tau.item())
+    out = dict(n_gaussians=2_000_000, tau_gpu=tau)
+    if stored is not None:
+        out["tau_stored"] = float(stored["tau"])
+        out["tau_rel_err"] = abs(tau - out["tau_stored"]) / out["tau_stored"]
+        assert out["tau_rel_err"] <= 5e-6, out
+    for name, tv in (("3sigma", 0.0), ("1/255", 1.0 / 255.0), ("gtc", tau)):
+        out[name] = fps_over(torch, t, [cam], fb, 1e30, tv, K)
+    out["workload"] = "2M flat Gaussians (no LoD), SH3, one 1920x1080 view"
+    log(f"flat 3DGS: {out['3sigma']['fps']:.1f} / {out['1/255']['fps']:.1f} / {out['gtc']['fps']:.1f} FPS "
+        f"(3 sigma / 1/255 / GTC tau {tau:.5f})")
+    del dev, t, fb, gb
+    torch.cuda.empty_cache()
+    return out
+
+
 def measure_fwd_bwd(torch):
     """Differentiable forward + backward of 2M raw Gaussians (SH degree 3) at
     1920x1080 against a seeded uniform target with an L1 loss: ms per view for
@@ -314,15 +438,17 @@ def measure_fwd_bwd(torch):
 
 def measure_batch(torch, dtree, tau_R, tau):
     """32 fly-through views with yaw jitter and mixed resolutions (720p to
-    2160p, global tile ids) rendered as one batch: node-major filter, per-view
-    stages, the batch replayed as one HIP graph after autotuning the blend chunk
-    and radix digit width. Compared with the same 32 views rendered one by one,
-    eagerly, with the default knobs."""
+    2160p, global tile ids) rendered as one batch: one node-major filter, one
+    projection, one sort of all views' pairs and one blend launch over the
+    (view, tile) queue, replayed as one HIP graph after autotuning the blend
+    chunk and radix digit width. Compared with the same 32 views rendered one
+    by one, eagerly, with the default knobs. The batch's sort is also timed
+    alone (its HBM fraction at this scale, tens of millions of pairs)."""
+    import dataclasses
     from paper_2603_23891_amd import batch, fg, synth
     cams = synth.city20m_batch_views(32)
     px = np.array([c.width * c.height for c in cams], np.float64)
-    caps = [int(max(4_000_000, 4 * p)) for p in px]
-    br = batch.BatchedRenderer(dtree, cams, cap_sel=12_000_000, cap_pairs=caps)
+    br = batch.BatchedRenderer(dtree, cams, cap_sel=8_000_000, cap_pairs=128_000_000, cap_items=64_000_000)
     stream = torch.cuda.current_stream()
 
     def timed(fn, reps):
@@ -336,34 +462,58 @@ def measure_batch(torch, dtree, tau_R, tau):
         torch.cuda.synchronize()
         return e[0].elapsed_time(e[1]) / reps
 
-    # one view at a time, default knobs (each view's filter is its own call)
+    # one view at a time, default knobs: one frame buffer per resolution
+    singles = [dataclasses.replace(c, tile_base=0) for c in cams]
+    fbs = {}
+    for c in singles:
+        if (c.width, c.height) not in fbs:
+            fbs[(c.width, c.height)] = fg.FrameBuffers(dtree, c.width, c.height, cap_sel=8_000_000,
+                                                       cap_pairs=48_000_000)
+
     def one_by_one():
-        for v, cam in enumerate(cams):
-            vb = br.views[v]
-            sel = br.sel_idx[v * br.cap_sel:(v + 1) * br.cap_sel]
-            ns = br.n_sel[v:v + 1]
-            fg.fg_filter(dtree, cam, tau_R, br.sel_bits, sel, br.cap_sel, ns, br.status, br.filter_ws)
-            fg.fg_preprocess(dtree, cam, tau, sel, ns, br.cap_sel, vb.splats, br.status)
-            fg.fg_sort(vb.splats, ns, br.cap_sel, cam, vb.tile_keys, vb.vals, vb.cap_pairs, vb.n_pairs, vb.ranges,
-                       br.status, vb.sort_ws)
-            fg.fg_render(vb.splats, vb.vals, vb.ranges, cam, (0.0, 0.0, 0.0), vb.image, vb.final_T, vb.n_contrib,
-                         vb.cap_pairs, None, br.status, vb.render_ws)
+        for c in singles:
+            fg.render_frame(dtree, c, fbs[(c.width, c.height)], tau_R, tau)
 
     single_ms = timed(one_by_one, 3)
+    for fb in fbs.values():
+        assert fg.read_counts(fb)[2] == 0
+    del fbs
+    torch.cuda.empty_cache()
     eager_ms = timed(lambda: br.run(tau_R, tau), 3)
     tuned = batch.autotune(br, tau_R, tau, chunks=(128, 256, 512), radix_bits=(6, 7, 8), repeats=2)
     br.capture(tau_R, tau)
     graph_ms = timed(br.replay, 5)
     ns, npairs, status = br.counts()
     assert status == 0, f"batch status {status}"
-    out = dict(views=len(cams), megapixels=float(px.sum() / 1e6), tiles=int(sum(c.n_tiles for c in cams)),
+    # the sort stage of the batch alone, and the byte model of its traffic
+    fg.fg_filter(dtree, cams, tau_R, br.sel_bits, br.sel_idx, br.cap_sel, br.n_sel, br.status, br.filter_ws,
+                 cams_dev=br.cams_dev)
+    fg.fg_preprocess(dtree, cams, tau, br.sel_idx, br.n_sel, br.cap_sel, br.splats, br.status, cams_dev=br.cams_dev)
+
+    def sort_only():
+        fg.fg_sort(br.splats, br.n_sel, br.cap_sel, cams, br.tile_keys, br.vals, br.cap_pairs, br.n_pairs, br.ranges,
+                   br.status, br.sort_ws, br.tune, cap_items=br.cap_items)
+
+    sort_ms = timed(sort_only, 5)
+    n_vis = sum(int(torch.count_nonzero(br.splats.tiles[v * br.cap_sel:v * br.cap_sel + int(ns[v])]).item())
+                for v in range(len(cams)))
+    n_tiles = int(sum(c.n_tiles for c in cams))
+    tile_bits = max(1, int(n_tiles - 1 + cams[0].tile_base).bit_length())
+    bits = br.tune.radix_bits or (tile_bits + (tile_bits + 7) // 8 - 1) // ((tile_bits + 7) // 8)
+    passes = int(np.ceil(tile_bits / bits))
+    sbytes = sort_bytes(int(ns.sum()), n_vis, int(npairs.sum()), passes, n_tiles)
+    sort_gbs = sbytes / (sort_ms * 1e-3) / 1e9
+    out = dict(views=len(cams), megapixels=float(px.sum() / 1e6), tiles=n_tiles,
                one_by_one_ms=single_ms, batched_eager_ms=eager_ms, batched_graph_ms=graph_ms,
                views_per_s=len(cams) / (graph_ms * 1e-3), ms_per_view=graph_ms / len(cams),
                tuned=dict(render_batch=tuned["render_batch"], radix_bits=tuned["radix_bits"]),
-               n_sel_mean=float(ns.mean()), n_pairs_total=int(npairs.sum()),
+               n_sel_mean=float(ns.mean()), n_pairs_total=int(npairs.sum()), n_vis_total=n_vis,
+               sort=dict(ms=sort_ms, bytes=sbytes, achieved_GBs=sort_gbs, frac=sort_gbs / HBM_PEAK_GBS,
+                         tile_passes=passes),
                workload="32 views of the 20M-node city, yaw jitter +-15 deg, resolutions 720p/1080p/1440p/2160p")
     log(f"batch: {graph_ms:.2f} ms per 32-view graph ({out['views_per_s']:.0f} views/s), "
-        f"eager {eager_ms:.2f} ms, one by one {single_ms:.2f} ms, tuned {out['tuned']}")
+        f"eager {eager_ms:.2f} ms, one by one {single_ms:.2f} ms, tuned {out['tuned']}; "
+        f"sort {sort_ms:.3f} ms for {npairs.sum() / 1e6:.1f}M pairs ({sort_gbs:.0f} GB/s)")
     del br
     torch.cuda.empty_cache()
     return out
@@ -419,6 +569,8 @@ def main():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-flat", action="store_true")
+    ap.add_argument("--no-topdown", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy three times (calibrates HBM counters)")
     args = ap.parse_args()
@@ -550,9 +702,14 @@ def main():
                     ops_per_launch=tot["blend_ops"] / f)
 
     pipelined = measure_pipelined(torch, dtree, cams, fb, tau_R, tau, K)
+    graphed = measure_graph_flythrough(torch, dtree, cams, tau_R, tau, K)
     gtc = measure_gtc_prepass(torch, dtree, fb, tau, float(stored["G_bar"]))
     serial = measure_serial_filter(torch, dtree, cams, fb, tau_R)
     sweep = None if args.no_sweep else measure_lambda_sweep(torch, dtree, cams, fb, tau_R, gtc["G_bar"])
+    with open(os.path.join(ROOT, "tests", "golden", "city_tau.json")) as f:
+        stored_all = json.load(f)
+    flat = None if args.no_flat else measure_flat3dgs(torch, stored_all.get("flat2m"), K)
+    topdown = None if args.no_topdown else measure_topdown(torch, tau_R, stored_all.get("topdown20m"), K)
     batched = None if args.no_batch else measure_batch(torch, dtree, tau_R, tau)
     fwd_bwd = None if args.no_backward else measure_fwd_bwd(torch)
 
@@ -578,9 +735,12 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "two_frames_in_flight": pipelined,
+        "graph_replay_per_frame": graphed,
         "gtc_prepass": gtc,
         "serial_filter": serial,
         "lambda_sweep": sweep,
+        "flat_3dgs": flat,
+        "topdown_tree": topdown,
         "batched_views": batched,
         "fwd_bwd_ms_per_view": fwd_bwd,
     }

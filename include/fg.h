@@ -26,6 +26,16 @@
  *    the current HIP device. Structs themselves (fg_tree, fg_camera,
  *    fg_splats, fg_tune) are passed by host pointer and read during the call
  *    only; the library keeps no reference to them.
+ *  - Views: the stages take an array of n_views cameras (host). Per-view
+ *    data lie at fixed strides: selections and splats at cap_sel entries per
+ *    view, counts n_sel[v]; fg_sort and fg_render treat the views as one
+ *    frame whose tiles have consecutive global ids (cams[v].tile_base =
+ *    cams[v-1].tile_base + tiles of view v-1), so one pair list, one range
+ *    array and one blend launch serve them all. fg_filter and fg_preprocess
+ *    also accept cams_dev, a device copy of the cameras whose pose (R, t,
+ *    campos) the kernels read at run time, so that a captured graph replays
+ *    with poses written into it between replays (intrinsics and sizes are
+ *    those of the host array, captured with the graph).
  *  - The caller owns every buffer. The library allocates nothing in these
  *    calls; scratch memory comes in through (ws, ws_bytes), sized by the
  *    matching *_workspace_size function. Workspace contents need no
@@ -78,6 +88,7 @@ extern "C" {
                                        longer than max_depth */
 #define FG_STATUS_GTC_UNDEFINED 8u  /* fg_gtc_tau: no view holds a Gaussian-tile
                                        pair, so G_bar (Eq. (8)) is undefined */
+#define FG_STATUS_ITEM_OVERFLOW 16u /* fg_sort: more tile-covering splats than cap_items */
 
 /* ---- inputs ------------------------------------------------------------ */
 
@@ -166,13 +177,14 @@ size_t fg_filter_workspace_size(int64_t n_nodes, int64_t n_internal_span, int32_
  * words, bit n%32 of word n/32 = sel(n); sel_idx + v*cap_sel, the selected
  * node ids in ascending order; n_sel[v] the number selected. *status
  * (device u32) is set to 0, then FG_STATUS_SEL_OVERFLOW / FG_STATUS_BAD_PARENT
- * as they occur.
+ * as they occur. cams_dev: NULL, or the views' poses in device memory (see
+ * the conventions above).
  * Errors: FG_ERR_INVALID_ARG for null pointers, n_views < 1 or cap_sel < 0,
  * FG_ERR_INVALID_TREE for n_nodes out of range, n_internal_span outside
  * [0, n_nodes] or max_depth outside 0..15, FG_ERR_WORKSPACE. */
-int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float tau_R, uint32_t* sel_bits,
-              uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status, void* ws, size_t ws_bytes,
-              void* stream);
+int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, const fg_camera* cams_dev, float tau_R,
+              uint32_t* sel_bits, uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status, void* ws,
+              size_t ws_bytes, void* stream);
 
 /* fg_filter without a workspace argument, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses
@@ -190,9 +202,9 @@ int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float
  * race on it and give undefined selections. Calls ordered on one stream are
  * safe; no contents carry over from one call to the next. */
 #define FG_NOALLOC_SCRATCH_BYTES (16u << 20)
-int fg_filter_noalloc(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float tau_R,
-                      uint32_t* sel_bits, uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status,
-                      void* stream);
+int fg_filter_noalloc(const fg_tree* tree, const fg_camera* cams, int32_t n_views, const fg_camera* cams_dev,
+                      float tau_R, uint32_t* sel_bits, uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel,
+                      uint32_t* status, void* stream);
 
 /* ---- the serial level-wise filter (the scheme Sec. 3.2 replaces) -------- */
 
@@ -236,7 +248,9 @@ int fg_filter_levelwise(const fg_tree* tree, const int32_t* child_offs, const in
 
 /* ---- stage 2: projection and shrunk extents (Sec. 3.1, Sec. 3.3) -------- */
 
-/* For i < min(*n_sel, cap_sel), node g = sel_idx[i]: camera-space centre,
+/* For each view v (cams[v], pose from cams_dev + v when cams_dev is given) and
+ * i < min(n_sel[v], cap_sel), node g = sel_idx[v*cap_sel + i], written to
+ * splat entry v*cap_sel + i of out: camera-space centre,
  * Sigma_2D (+0.3 px^2), conic = Sigma_2D^-1 (dropped when det <= 0), 2D mean,
  * depth, colour 0.5 + sum_k sh_k Y_k(d) clamped at 0 with d the unit vector
  * from campos to the mean and Y the orthonormal real SH basis, and the
@@ -247,52 +261,66 @@ int fg_filter_levelwise(const fg_tree* tree, const int32_t* child_offs, const in
  * (Sec. 3.3 "Gaussian Shrinking Strategy"; tau = lambda_G / G_bar, Eq. (8),
  * or 1/255 for a fixed threshold). The rectangle holds every tile whose
  * 16-px square meets [u - r, u + r] x [v - r, v + r]. Only the tile set
- * shrinks; blending still evaluates the full Gaussian.
+ * shrinks; blending still evaluates the full Gaussian. Views are processed
+ * 8 per launch.
  * Errors: FG_ERR_INVALID_ARG, FG_ERR_UNSUPPORTED (sh_degree > 3). */
-int fg_preprocess(const fg_tree* tree, const fg_camera* cam, float tau, const uint32_t* sel_idx,
-                  const uint32_t* n_sel, int64_t cap_sel, const fg_splats* out, uint32_t* status, void* stream);
+int fg_preprocess(const fg_tree* tree, const uint32_t* sel_idx, const uint32_t* n_sel, int64_t cap_sel,
+                  const fg_camera* cams, int32_t n_views, const fg_camera* cams_dev, float tau,
+                  const fg_splats* out, uint32_t* status, void* stream);
 
 /* ---- stage 3: key emission, sort, ranges ------------------------------ */
 
 /* Scratch bytes fg_sort needs. */
-size_t fg_sort_workspace_size(int64_t cap_sel, int64_t cap_pairs, const fg_camera* cam);
+size_t fg_sort_workspace_size(int64_t cap_sel, int32_t n_views, int64_t cap_items, int64_t cap_pairs);
 
-/* Orders the Gaussian-tile pairs by the key (tile id, depth bits) and then
- * by splat index: splat i contributes one pair per tile of its rectangle.
- * Outputs (device): tile_keys [cap_pairs] the sorted tile ids
- * (tile_base + ty*Wt + tx), vals [cap_pairs] the matching splat indices (the
- * full 64-bit key of entry k is tile_keys[k] << 32 | bits(depth[vals[k]]));
- * *n_pairs (device u32); ranges [n_tiles][2] = [start, end) of each of this
- * view's tiles in the sorted list ([0, 0) for an empty tile).
- * Method: the splats that cover a tile are packed in index order and
+/* Orders the Gaussian-tile pairs of all views by the key (global tile id,
+ * depth bits) and then by splat index: splat j of view v (global splat index
+ * v*cap_sel + j, j < n_sel[v]) contributes one pair per tile of its rectangle.
+ * Outputs (device): tile_keys [cap_pairs] the sorted global tile ids
+ * (tile_base + ty*Wt + tx of the splat's view), vals [cap_pairs] the matching
+ * global splat indices (the full 64-bit key of entry k is
+ * tile_keys[k] << 32 | bits(depth[vals[k]])); *n_pairs (device u32);
+ * ranges [n_tiles][2] over the tiles of all views in global id order
+ * (entry t is global tile cams[0].tile_base + t): [start, end) in the sorted
+ * list, [0, 0) for an empty tile.
+ * Method: the splats that cover a tile are packed in (view, index) order and
  * stably radix-sorted by depth; an exclusive prefix scan of their tile counts
  * in that order places their pairs (key emission), and a stable radix sort of
  * the pairs by tile id gives the (tile, depth, index) order (LDS-staged LSD
- * passes throughout).
- * Errors: FG_ERR_INVALID_ARG, FG_ERR_WORKSPACE; FG_STATUS_PAIR_OVERFLOW
- * on the device when the pairs exceed cap_pairs. */
-int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t cap_sel, const fg_camera* cam,
-            uint32_t* tile_keys, uint32_t* vals, int64_t cap_pairs, uint32_t* n_pairs, uint32_t* ranges,
-            uint32_t* status, void* ws, size_t ws_bytes, const fg_tune* tune, void* stream);
+ * passes throughout). cap_items bounds the tile-covering splats of all views
+ * together (cap_sel for one view).
+ * Errors: FG_ERR_INVALID_ARG (also for global tile ids that are not
+ * consecutive from view to view), FG_ERR_UNSUPPORTED (n_views > 64,
+ * n_views*cap_sel >= 2^32), FG_ERR_WORKSPACE; on the device
+ * FG_STATUS_PAIR_OVERFLOW when the pairs exceed cap_pairs (n_pairs then holds
+ * the required count) and FG_STATUS_ITEM_OVERFLOW when the tile-covering
+ * splats exceed cap_items. */
+int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t cap_sel, const fg_camera* cams,
+            int32_t n_views, int64_t cap_items, uint32_t* tile_keys, uint32_t* vals, int64_t cap_pairs,
+            uint32_t* n_pairs, uint32_t* ranges, uint32_t* status, void* ws, size_t ws_bytes, const fg_tune* tune,
+            void* stream);
 
 /* ---- stage 4: blending, Eq. (2) --------------------------------------- */
 
-/* Scratch bytes fg_render needs for this image size and pair capacity. */
-size_t fg_render_workspace_size(const fg_camera* cam, int64_t cap_pairs, const fg_tune* tune);
+/* Scratch bytes fg_render needs for these views and pair capacity. */
+size_t fg_render_workspace_size(const fg_camera* cams, int32_t n_views, int64_t cap_pairs, const fg_tune* tune);
 
 /* For every pixel of tile t, front to back over ranges[t]:
  *   power = -0.5 (A dx^2 + C dy^2) - B dx dy, d = (u, v) - pixel centre;
  *   skip if power > 0; alpha = min(0.99, opacity exp(power)), skip if
  *   alpha < 1/255; stop before a splat that would take T below 1e-4;
  *   C += rgb alpha T; T *= (1 - alpha).
- * Outputs (device): image [3][H][W] = C + T bg; final_T [H][W];
- * n_contrib [H][W] = 1 + position (within the tile's range) of the last
- * splat blended, 0 if none. bg is a host array of 3 floats. cap_pairs is
- * the capacity the sort ran with (it bounds the range lengths and sizes the
- * workspace). Long ranges are cut into chunks whose skip tests run in
- * parallel (a first launch writes per-pixel pass masks); the transmittance
- * chain still runs in list order, so results are those of one sequential
- * pass.
+ * Outputs (device), per view v with P_v the pixels of the views before it:
+ * image + 3*P_v, [3][H][W] = C + T bg; final_T + P_v, [H][W];
+ * n_contrib + P_v, [H][W] = 1 + position (within the tile's range) of the
+ * last splat blended, 0 if none. bg is a host array of 3 floats. vals and
+ * ranges are fg_sort's for the same views (global splat indices, tiles in
+ * global id order). cap_pairs is the capacity the sort ran with (it bounds
+ * the range lengths and sizes the workspace). The tiles of all views form
+ * one work queue of one persistent blend launch. Long ranges are cut into
+ * chunks whose skip tests run in parallel (a first launch writes per-pixel
+ * pass masks); the transmittance chain still runs in list order, so results
+ * are those of one sequential pass.
  * frag_stats: NULL, or 8 device counters that the call adds to (the caller
  * zeroes them): [0] (pixel, splat) tests evaluated, [1] tests that reach the
  * exponential (-5.6 <= power <= 0), [2] tests with alpha >= 1/255, [3] splats
@@ -301,10 +329,10 @@ size_t fg_render_workspace_size(const fg_camera* cam, int64_t cap_pairs, const f
  * not depend on whether counting is on.
  * status is reserved (not written). Errors: FG_ERR_INVALID_ARG,
  * FG_ERR_WORKSPACE. */
-int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
-              const float bg[3], float* image, float* final_T, uint32_t* n_contrib, int64_t cap_pairs,
-              unsigned long long* frag_stats, uint32_t* status, void* ws, size_t ws_bytes, const fg_tune* tune,
-              void* stream);
+int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cams,
+              int32_t n_views, const float bg[3], float* image, float* final_T, uint32_t* n_contrib,
+              int64_t cap_pairs, unsigned long long* frag_stats, uint32_t* status, void* ws, size_t ws_bytes,
+              const fg_tune* tune, void* stream);
 
 /* ---- GTC pre-pass and the scene threshold (Sec. 3.3, Fig. 2(b)) -------- */
 

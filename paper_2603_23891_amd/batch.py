@@ -1,12 +1,19 @@
-"""Batched multi-view rendering: one node-major filter pass for all views,
-per-view projection, sort and blend, the whole batch captured in one HIP graph,
-and an autotuner for the speed-only knobs (blend chunk size, radix digit
-width).
+"""Batched multi-view rendering: V views of one tree as one frame.
+
+The views go through the four stages together: one node-major filter call
+(passes of up to eight views), one projection call, one sort of every view's
+Gaussian-tile pairs under global tile ids, and one blend whose persistent
+workgroups take (view, tile) work items from a single queue. The cameras'
+poses live in a device array that the filter and projection kernels read, so a
+batch captured in a HIP graph replays with new poses written into that array
+(intrinsics and image sizes are fixed at capture). ``autotune`` picks the
+speed-only knobs (blend chunk, radix digit width).
 
 Marshalling and scheduling only: every stage runs in libfg's kernels.
 """
 from __future__ import annotations
 
+import ctypes as C
 import json
 import os
 from typing import Dict, List, Optional, Sequence, Tuple
@@ -16,76 +23,112 @@ import torch
 
 from . import fg
 
-
-class ViewBuffers:
-    """Per-view projection / sort / blend buffers (capacities fixed)."""
-
-    def __init__(self, cam, cap_sel: int, cap_pairs: int, device="cuda"):
-        width, height = cam.width, cam.height
-        self.width, self.height = width, height
-        self.cap_sel, self.cap_pairs = cap_sel, cap_pairs
-        i32 = torch.int32
-        self.splats = fg.Splats(cap_sel, device)
-        self.tile_keys = torch.empty(max(cap_pairs, 1), dtype=i32, device=device)
-        self.vals = torch.empty(max(cap_pairs, 1), dtype=i32, device=device)
-        n_tiles = ((width + 15) // 16) * ((height + 15) // 16)
-        self.ranges = torch.empty((n_tiles, 2), dtype=i32, device=device)
-        self.n_pairs = torch.zeros(1, dtype=i32, device=device)
-        self.sort_ws = torch.empty(fg.fg_sort_workspace_size(cap_sel, cap_pairs, cam), dtype=torch.uint8,
-                                   device=device)
-        rw = max(fg.fg_render_workspace_size(cam, cap_pairs, fg.tune_struct(c)) for c in (128, 256, 512))
-        self.render_ws = torch.empty(rw, dtype=torch.uint8, device=device)
-        self.image = torch.empty((3, height, width), dtype=torch.float32, device=device)
-        self.final_T = torch.empty((height, width), dtype=torch.float32, device=device)
-        self.n_contrib = torch.empty((height, width), dtype=i32, device=device)
+# fields of fg_camera that a replay keeps from capture time (everything but the pose)
+_FIXED = ("fx", "fy", "cx", "cy", "width", "height", "znear", "kx", "ky", "tile_base")
 
 
 class BatchedRenderer:
-    """Renders V views of one device-resident tree per call of ``run``."""
+    """Renders V views of one device-resident tree per call of ``run``.
 
-    def __init__(self, tree: fg.DeviceTree, cams: Sequence, cap_sel: int, cap_pairs: Sequence[int] | int,
-                 device="cuda", n_streams: int = 4):
+    cap_sel: selected-node capacity per view; cap_pairs: pair capacity of the
+    whole batch; cap_items: capacity for the tile-covering splats of all views
+    (default: V * cap_sel). The views' global tile ids must be consecutive
+    (cams[v].tile_base = cams[v-1].tile_base + tiles of view v-1)."""
+
+    def __init__(self, tree: fg.DeviceTree, cams: Sequence, cap_sel: int, cap_pairs: int,
+                 cap_items: Optional[int] = None, device="cuda"):
         self.tree, self.cams = tree, list(cams)
         V = len(self.cams)
+        self.n_views = V
         self.cap_sel = int(cap_sel)
-        caps = [int(cap_pairs)] * V if isinstance(cap_pairs, int) else [int(c) for c in cap_pairs]
+        self.cap_pairs = int(cap_pairs)
+        self.cap_items = int(cap_items) if cap_items is not None else V * self.cap_sel
+        self.tile0 = np.zeros(V + 1, np.int64)
+        self.pix0 = np.zeros(V + 1, np.int64)
+        for v, c in enumerate(self.cams):
+            nt = ((c.width + 15) // 16) * ((c.height + 15) // 16)
+            if c.tile_base != self.cams[0].tile_base + self.tile0[v]:
+                raise ValueError("views need consecutive global tile ids")
+            self.tile0[v + 1] = self.tile0[v] + nt
+            self.pix0[v + 1] = self.pix0[v] + c.width * c.height
         N = tree.n_nodes
+        i32 = torch.int32
         self.words = (N + 31) // 32
-        self.sel_bits = torch.empty(V * max(self.words, 1), dtype=torch.int32, device=device)
-        self.sel_idx = torch.empty(V * max(self.cap_sel, 1), dtype=torch.int32, device=device)
-        self.n_sel = torch.zeros(V, dtype=torch.int32, device=device)
-        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        self.sel_bits = torch.empty(V * max(self.words, 1), dtype=i32, device=device)
+        self.sel_idx = torch.empty(V * max(self.cap_sel, 1), dtype=i32, device=device)
+        self.n_sel = torch.zeros(V, dtype=i32, device=device)
+        self.status = torch.zeros(1, dtype=i32, device=device)
         self.filter_ws = torch.empty(fg.fg_filter_workspace_size(N, tree.n_internal_span, V), dtype=torch.uint8,
                                      device=device)
-        self.views = [ViewBuffers(c, self.cap_sel, caps[i], device) for i, c in enumerate(self.cams)]
+        self.splats = fg.Splats(V * max(self.cap_sel, 1), device)
+        self.tile_keys = torch.empty(max(self.cap_pairs, 1), dtype=i32, device=device)
+        self.vals = torch.empty(max(self.cap_pairs, 1), dtype=i32, device=device)
+        self.n_pairs = torch.zeros(1, dtype=i32, device=device)
+        self.ranges = torch.empty((int(self.tile0[-1]), 2), dtype=i32, device=device)
+        self.sort_ws = torch.empty(fg.fg_sort_workspace_size(self.cap_sel, V, self.cap_items, self.cap_pairs),
+                                   dtype=torch.uint8, device=device)
+        rw = max(fg.fg_render_workspace_size(self.cams, self.cap_pairs, fg.tune_struct(c)) for c in (128, 256, 512))
+        self.render_ws = torch.empty(rw, dtype=torch.uint8, device=device)
+        P = int(self.pix0[-1])
+        self.image = torch.empty(3 * P, dtype=torch.float32, device=device)
+        self.final_T = torch.empty(P, dtype=torch.float32, device=device)
+        self.n_contrib = torch.empty(P, dtype=i32, device=device)
+        arr, _ = fg.camera_array(self.cams)
+        self.cams_dev = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).to(device)
         self.graph: Optional[torch.cuda.CUDAGraph] = None
         self.tune = fg.tune_struct()
-        # views run on n_streams streams (default priority) after the shared
-        # filter, so one view's long blend tail overlaps other views' work
-        self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, n_streams))]
 
+    # -- per-view views of the packed outputs --------------------------------
+    def view_image(self, v: int) -> torch.Tensor:
+        c = self.cams[v]
+        a = int(self.pix0[v])
+        return self.image[3 * a:3 * a + 3 * c.width * c.height].view(3, c.height, c.width)
+
+    def view_final_T(self, v: int) -> torch.Tensor:
+        c = self.cams[v]
+        a = int(self.pix0[v])
+        return self.final_T[a:a + c.width * c.height].view(c.height, c.width)
+
+    def view_n_contrib(self, v: int) -> torch.Tensor:
+        c = self.cams[v]
+        a = int(self.pix0[v])
+        return self.n_contrib[a:a + c.width * c.height].view(c.height, c.width)
+
+    def view_ranges(self, v: int) -> torch.Tensor:
+        return self.ranges[int(self.tile0[v]):int(self.tile0[v + 1])]
+
+    # -- poses -----------------------------------------------------------------
+    def set_poses(self, cams: Sequence, stream=None):
+        """Write new poses (R, t, campos) into the device camera array, stream-
+        ordered (a later run or graph replay on the same stream uses them).
+        Every other camera field must equal the batch's."""
+        cams = list(cams)
+        if len(cams) != self.n_views:
+            raise ValueError("one camera per view")
+        for a, b in zip(cams, self.cams):
+            for k in _FIXED:
+                if getattr(a, k) != getattr(b, k):
+                    raise ValueError(f"camera field {k} differs from the batch's; only poses can change")
+        arr, _ = fg.camera_array(cams)
+        host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).pin_memory()
+        s = stream or torch.cuda.current_stream()
+        with torch.cuda.stream(s):
+            self.cams_dev.copy_(host, non_blocking=True)
+        self._staging = host  # kept alive until the next call (the copy is asynchronous)
+
+    # -- the batch -------------------------------------------------------------
     def run(self, tau_R: float = 3.0, tau: float = 0.0, bg=(0.0, 0.0, 0.0), tune: Optional[fg.FgTune] = None):
-        """Enqueue the whole batch (no host synchronisation): the node-major
-        filter on the current stream, then the views' projection, sort and
-        blend spread over the batch's streams, which the current stream joins
-        at the end. Graph capture records the fork and join."""
+        """Enqueue the whole batch on the current stream (no host
+        synchronisation): filter, projection, sort and blend of all views."""
         tune = tune or self.tune
-        main = torch.cuda.current_stream()
         fg.fg_filter(self.tree, self.cams, tau_R, self.sel_bits, self.sel_idx, self.cap_sel, self.n_sel,
-                     self.status, self.filter_ws, stream=main)
-        for st in self.streams:
-            st.wait_stream(main)
-        for v, (cam, vb) in enumerate(zip(self.cams, self.views)):
-            st = self.streams[v % len(self.streams)]
-            sel = self.sel_idx[v * self.cap_sel:(v + 1) * self.cap_sel]
-            nsel = self.n_sel[v:v + 1]
-            fg.fg_preprocess(self.tree, cam, tau, sel, nsel, self.cap_sel, vb.splats, self.status, stream=st)
-            fg.fg_sort(vb.splats, nsel, self.cap_sel, cam, vb.tile_keys, vb.vals, vb.cap_pairs, vb.n_pairs,
-                       vb.ranges, self.status, vb.sort_ws, tune, stream=st)
-            fg.fg_render(vb.splats, vb.vals, vb.ranges, cam, bg, vb.image, vb.final_T, vb.n_contrib, vb.cap_pairs,
-                         None, self.status, vb.render_ws, tune, stream=st)
-        for st in self.streams:
-            main.wait_stream(st)
+                     self.status, self.filter_ws, cams_dev=self.cams_dev)
+        fg.fg_preprocess(self.tree, self.cams, tau, self.sel_idx, self.n_sel, self.cap_sel, self.splats,
+                         self.status, cams_dev=self.cams_dev)
+        fg.fg_sort(self.splats, self.n_sel, self.cap_sel, self.cams, self.tile_keys, self.vals, self.cap_pairs,
+                   self.n_pairs, self.ranges, self.status, self.sort_ws, tune, cap_items=self.cap_items)
+        fg.fg_render(self.splats, self.vals, self.ranges, self.cams, bg, self.image, self.final_T, self.n_contrib,
+                     self.cap_pairs, None, self.status, self.render_ws, tune)
 
     def capture(self, tau_R: float = 3.0, tau: float = 0.0, bg=(0.0, 0.0, 0.0),
                 tune: Optional[fg.FgTune] = None) -> torch.cuda.CUDAGraph:
@@ -107,22 +150,26 @@ class BatchedRenderer:
         self.graph.replay()
 
     def counts(self) -> Tuple[np.ndarray, np.ndarray, int]:
-        """(n_sel per view, n_pairs per view, status), synchronising."""
+        """(n_sel per view, pairs per view, status), synchronising. A view's
+        pairs are the contiguous run of the sorted list its tiles cover."""
         ns = self.n_sel.cpu().numpy().view(np.uint32).astype(np.int64)
-        npairs = np.array([int(vb.n_pairs.cpu().numpy().view(np.uint32)[0]) for vb in self.views])
-        return ns, npairs, int(self.status.cpu().numpy().view(np.uint32)[0])
+        r = self.ranges.cpu().numpy().view(np.uint32).astype(np.int64)
+        per = np.zeros(self.n_views, np.int64)
+        for v in range(self.n_views):
+            rv = r[int(self.tile0[v]):int(self.tile0[v + 1])]
+            per[v] = int((rv[:, 1] - rv[:, 0]).sum())
+        return ns, per, int(self.status.cpu().numpy().view(np.uint32)[0])
 
 
-def _digest(br: BatchedRenderer) -> List[np.ndarray]:
-    return [np.concatenate([vb.image.cpu().numpy().ravel().view(np.uint32),
-                            vb.n_contrib.cpu().numpy().ravel().view(np.uint32)]) for vb in br.views]
+def _digest(br: BatchedRenderer) -> np.ndarray:
+    return np.concatenate([br.image.cpu().numpy().view(np.uint32), br.n_contrib.cpu().numpy().view(np.uint32)])
 
 
 def autotune(br: BatchedRenderer, tau_R: float = 3.0, tau: float = 0.0, chunks=(128, 256, 512),
              radix_bits=(6, 7, 8), repeats: int = 3, cache_path: Optional[str] = None,
              cache_key: Optional[str] = None) -> Dict:
-    """Times every (blend chunk, radix digit width) candidate on the batch and
-    keeps the fastest. Every candidate must give bit-identical images and
+    """Times every (blend chunk B, radix digit width) candidate on the batch
+    and keeps the fastest. Every candidate must give bit-identical images and
     contributor counts (the knobs change speed only)."""
     if cache_path and cache_key and os.path.exists(cache_path):
         with open(cache_path) as f:
@@ -141,7 +188,7 @@ def autotune(br: BatchedRenderer, tau_R: float = 3.0, tau: float = 0.0, chunks=(
             dig = _digest(br)
             if ref is None:
                 ref = dig
-            elif not all(np.array_equal(a, r) for a, r in zip(dig, ref)):
+            elif not np.array_equal(dig, ref):
                 raise RuntimeError(f"tuning candidate chunk={c} radix_bits={b} changed the output")
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
             ev[0].record(stream)

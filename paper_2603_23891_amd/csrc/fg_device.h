@@ -97,6 +97,19 @@ inline Cam make_cam(const fg_camera& c)
     return k;
 }
 
+// The pose (R, t, camera centre) of a camera in device memory replaces c's;
+// intrinsics and image size stay those of c.
+__device__ __forceinline__ void pose_from(Cam& c, const fg_camera* __restrict__ d)
+{
+#pragma unroll
+    for (int i = 0; i < 9; i++) c.R[i] = d->R[i];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        c.t[i] = d->t[i];
+        c.campos[i] = d->campos[i];
+    }
+}
+
 // x_c = R x_w + t, each row summed left to right.
 __device__ __forceinline__ void to_camera(const Cam& c, float mx, float my, float mz, float& x, float& y, float& z)
 {

@@ -76,7 +76,8 @@ __device__ __forceinline__ void store_wave_bits(uint32_t* __restrict__ words, in
 template <int NV>
 __global__ __launch_bounds__(kBlock) void k_small(const float* __restrict__ mean, const float* __restrict__ scale,
                                                   const float* __restrict__ quat, const uint8_t* __restrict__ flags,
-                                                  int64_t N, int64_t span, CamSet cams, int nv, float tau_R,
+                                                  int64_t N, int64_t span, CamSet cams,
+                                                  const fg_camera* __restrict__ dcams, int nv, float tau_R,
                                                   uint32_t* __restrict__ small_bits, int64_t words,
                                                   uint32_t* __restrict__ status, bool reset_status)
 {
@@ -90,16 +91,18 @@ __global__ __launch_bounds__(kBlock) void k_small(const float* __restrict__ mean
 #pragma unroll
         for (int v = 0; v < NV; v++) {
             if (v >= nv) break;
+            fgd::Cam cam = cams.c[v];
+            if (dcams) fgd::pose_from(cam, dcams + v);
             float x, y, z;
-            fgd::to_camera(cams.c[v], mx, my, mz, x, y, z);
-            if (fgd::in_frustum(cams.c[v], x, y, z)) {
+            fgd::to_camera(cam, mx, my, mz, x, y, z);
+            if (fgd::in_frustum(cam, x, y, z)) {
                 if (!have_cov) {
                     fgd::covariance3d(scale[n], scale[N + n], scale[2 * N + n], quat[n], quat[N + n],
                                       quat[2 * N + n], quat[3 * N + n], S);
                     have_cov = true;
                 }
                 float a, b, c;
-                fgd::covariance2d(cams.c[v], x, y, z, S, a, b, c);
+                fgd::covariance2d(cam, x, y, z, S, a, b, c);
                 if (3.0f * sqrtf(fgd::lambda_max(a, b, c)) <= tau_R) small |= 1u << v;
             }
         }
@@ -156,7 +159,8 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
                                                    const uint8_t* __restrict__ flags,
                                                    const uint32_t* __restrict__ small_bits,
                                                    const uint32_t* __restrict__ blocked_bits, int64_t words,
-                                                   int64_t N, int64_t span, CamSet cams, int nv,
+                                                   int64_t N, int64_t span, CamSet cams,
+                                                   const fg_camera* __restrict__ dcams, int nv,
                                                    uint32_t* __restrict__ sel_bits, int64_t sel_words,
                                                    uint32_t* __restrict__ tile_cnt, int64_t n_tiles,
                                                    uint32_t* __restrict__ status)
@@ -220,9 +224,11 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
             bool sel = false;
             if (n < N && !((cull[r] >> v) & 1u)) {
                 if (fl[r] & 1u) {  // leaf: RL = in frustum
+                    fgd::Cam cam = cams.c[v];
+                    if (dcams) fgd::pose_from(cam, dcams + v);
                     float x, y, z;
-                    fgd::to_camera(cams.c[v], mx[r], my[r], mz[r], x, y, z);
-                    sel = fgd::in_frustum(cams.c[v], x, y, z);
+                    fgd::to_camera(cam, mx[r], my[r], mz[r], x, y, z);
+                    sel = fgd::in_frustum(cam, x, y, z);
                 } else {  // internal: RL = small
                     sel = bit_of(small_bits + v * words, n);
                 }
@@ -368,19 +374,20 @@ size_t carve(void* base, int64_t N, int64_t span, int n_views, FilterWs* w)
 }
 
 template <int NV>
-void launch_pass(const fg_tree* tree, const CamSet& cs, int nv, float tau_R, uint32_t* sel_bits, int64_t sel_words,
+void launch_pass(const fg_tree* tree, const CamSet& cs, const fg_camera* dcams, int nv, float tau_R,
+                 uint32_t* sel_bits, int64_t sel_words,
                  uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status, bool reset_status,
                  const FilterWs& w, int64_t N, int64_t span, int64_t n_tiles, hipStream_t s)
 {
     if (span > 0) {
         const dim3 g((unsigned)((span + kBlock - 1) / kBlock));
         hipLaunchKernelGGL(k_small<NV>, g, dim3(kBlock), 0, s, tree->mean, tree->scale, tree->quat, tree->flags, N,
-                           span, cs, nv, tau_R, w.small_bits, w.words, status, reset_status);
+                           span, cs, dcams, nv, tau_R, w.small_bits, w.words, status, reset_status);
         hipLaunchKernelGGL(k_blocked<NV>, g, dim3(kBlock), 0, s, tree->parent, tree->flags, w.small_bits, w.words,
                            span, tree->max_depth, nv, w.blocked_bits, status);
     }
     hipLaunchKernelGGL(k_select<NV>, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, tree->mean, tree->parent,
-                       tree->flags, w.small_bits, w.blocked_bits, w.words, N, span, cs, nv, sel_bits, sel_words,
+                       tree->flags, w.small_bits, w.blocked_bits, w.words, N, span, cs, dcams, nv, sel_bits, sel_words,
                        w.tile_cnt, n_tiles, status);
     hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)nv), dim3(kScanThreads), 0, s, w.tile_cnt, n_tiles, n_sel,
                        cap_sel, status);
@@ -406,8 +413,9 @@ int check_filter_args(const fg_tree* tree, const fg_camera* cams, int32_t n_view
 }
 
 // The launches of one filter call on a workspace already checked for size.
-int run_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float tau_R, uint32_t* sel_bits,
-               uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status, void* ws, void* stream)
+int run_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, const fg_camera* cams_dev, float tau_R,
+               uint32_t* sel_bits, uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status, void* ws,
+               void* stream)
 {
     const int64_t N = tree->n_nodes, span = tree->n_internal_span;
     FilterWs w;
@@ -430,10 +438,11 @@ int run_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, floa
         uint32_t* si = sel_idx ? sel_idx + (int64_t)v0 * cap_sel : nullptr;
         uint32_t* ns = n_sel + v0;
         const bool rs = first && span > 0;
-        if (nv == 1) launch_pass<1>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
-        else if (nv == 2) launch_pass<2>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
-        else if (nv <= 4) launch_pass<4>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
-        else launch_pass<8>(tree, cs, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
+        const fg_camera* dc = cams_dev ? cams_dev + v0 : nullptr;
+        if (nv == 1) launch_pass<1>(tree, cs, dc, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
+        else if (nv == 2) launch_pass<2>(tree, cs, dc, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
+        else if (nv <= 4) launch_pass<4>(tree, cs, dc, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
+        else launch_pass<8>(tree, cs, dc, nv, tau_R, sb, sel_words, si, cap_sel, ns, status, rs, w, N, span, n_tiles, s);
     }
     return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
 }
@@ -447,15 +456,15 @@ extern "C" size_t fg_filter_workspace_size(int64_t n_nodes, int64_t n_internal_s
     return carve(nullptr, n_nodes, n_internal_span, n_views, &w);
 }
 
-extern "C" int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float tau_R,
-                         uint32_t* sel_bits, uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel, uint32_t* status,
-                         void* ws, size_t ws_bytes, void* stream)
+extern "C" int fg_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, const fg_camera* cams_dev,
+                         float tau_R, uint32_t* sel_bits, uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel,
+                         uint32_t* status, void* ws, size_t ws_bytes, void* stream)
 {
     const int rc = check_filter_args(tree, cams, n_views, sel_bits, sel_idx, cap_sel, n_sel, status);
     if (rc != FG_OK) return rc;
     FilterWs w;
     if (!ws || ws_bytes < carve(nullptr, tree->n_nodes, tree->n_internal_span, n_views, &w)) return FG_ERR_WORKSPACE;
-    return run_filter(tree, cams, n_views, tau_R, sel_bits, sel_idx, cap_sel, n_sel, status, ws, stream);
+    return run_filter(tree, cams, n_views, cams_dev, tau_R, sel_bits, sel_idx, cap_sel, n_sel, status, ws, stream);
 }
 
 // ---- fg_filter_noalloc: the same filter on a fixed device array -----------
@@ -477,9 +486,9 @@ hipError_t g_scratch_err[kMaxDevices];
 
 }  // namespace
 
-extern "C" int fg_filter_noalloc(const fg_tree* tree, const fg_camera* cams, int32_t n_views, float tau_R,
-                                 uint32_t* sel_bits, uint32_t* sel_idx, int64_t cap_sel, uint32_t* n_sel,
-                                 uint32_t* status, void* stream)
+extern "C" int fg_filter_noalloc(const fg_tree* tree, const fg_camera* cams, int32_t n_views,
+                                 const fg_camera* cams_dev, float tau_R, uint32_t* sel_bits, uint32_t* sel_idx,
+                                 int64_t cap_sel, uint32_t* n_sel, uint32_t* status, void* stream)
 {
     const int rc = check_filter_args(tree, cams, n_views, sel_bits, sel_idx, cap_sel, n_sel, status);
     if (rc != FG_OK) return rc;
@@ -494,6 +503,6 @@ extern "C" int fg_filter_noalloc(const fg_tree* tree, const fg_camera* cams, int
         g_scratch_ptr[dev] = p;
     });
     if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev]) return FG_ERR_HIP;
-    return run_filter(tree, cams, n_views, tau_R, sel_bits, sel_idx, cap_sel, n_sel, status, g_scratch_ptr[dev],
-                      stream);
+    return run_filter(tree, cams, n_views, cams_dev, tau_R, sel_bits, sel_idx, cap_sel, n_sel, status,
+                      g_scratch_ptr[dev], stream);
 }

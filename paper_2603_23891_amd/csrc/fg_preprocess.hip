@@ -2,7 +2,8 @@
 // rectangles under the opacity-aware shrink radius (Sec. 3.3).
 //
 // One thread per selected Gaussian, a grid-stride loop over the device-side
-// count. Node attributes are gathered through sel_idx: the three position
+// count; the y dimension of the grid runs over views (up to 8 per launch),
+// each with its own selection, count and splat planes at a stride of cap_sel. Node attributes are gathered through sel_idx: the three position
 // planes, scale and rotation planes, opacity, and the node's contiguous SH
 // block (192 B at degree 3, read as 16-byte vectors).
 #include "fg_device.h"
@@ -10,6 +11,11 @@
 namespace {
 
 constexpr int kBlock = 128;
+constexpr int kViewsPerLaunch = 8;
+
+struct CamSet {
+    fgd::Cam c[kViewsPerLaunch];
+};
 
 // Real spherical harmonics (orthonormal, closed-form Cartesian polynomials of
 // the unit direction), coefficient order (l, m = -l..l).
@@ -38,14 +44,23 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y)
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_preprocess(fg_tree tree, fgd::Cam cam, float tau,
-                                                       const uint32_t* __restrict__ sel_idx,
-                                                       const uint32_t* __restrict__ n_sel_p, int64_t cap_sel,
-                                                       fg_splats out)
+__global__ __launch_bounds__(kBlock) void k_preprocess(fg_tree tree, CamSet cams,
+                                                       const fg_camera* __restrict__ dcams, float tau,
+                                                       const uint32_t* __restrict__ sel_idx_all,
+                                                       const uint32_t* __restrict__ n_sel_all, int64_t cap_sel,
+                                                       fg_splats out_all)
 {
     constexpr int K = (D + 1) * (D + 1);
     const int64_t N = tree.n_nodes;
-    int64_t n_sel = (int64_t)*n_sel_p;
+    const int v = blockIdx.y;  // view within this launch
+    fgd::Cam cam = cams.c[0];
+#pragma unroll
+    for (int u = 1; u < kViewsPerLaunch; u++)
+        if (u == v) cam = cams.c[u];
+    if (dcams) fgd::pose_from(cam, dcams + v);
+    const uint32_t* __restrict__ sel_idx = sel_idx_all + (int64_t)v * cap_sel;
+    const int64_t o = (int64_t)v * cap_sel;  // this view's splat entries
+    int64_t n_sel = (int64_t)n_sel_all[v];
     if (n_sel > cap_sel) n_sel = cap_sel;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n_sel; i += (int64_t)gridDim.x * kBlock) {
         const int64_t g = sel_idx[i];
@@ -134,40 +149,56 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(fg_tree tree, fgd::Cam ca
                 rgbd.x = rgb[0]; rgbd.y = rgb[1]; rgbd.z = rgb[2];
             }
         }
-        reinterpret_cast<float2*>(out.xy)[i] = make_float2(xyo.x, xyo.y);
-        reinterpret_cast<float4*>(out.conic_o)[i] = co;
-        reinterpret_cast<float4*>(out.rgb_depth)[i] = rgbd;
-        reinterpret_cast<ushort4*>(out.rect)[i] = rect;
-        out.tiles[i] = tiles;
+        reinterpret_cast<float2*>(out_all.xy)[o + i] = make_float2(xyo.x, xyo.y);
+        reinterpret_cast<float4*>(out_all.conic_o)[o + i] = co;
+        reinterpret_cast<float4*>(out_all.rgb_depth)[o + i] = rgbd;
+        reinterpret_cast<ushort4*>(out_all.rect)[o + i] = rect;
+        out_all.tiles[o + i] = tiles;
     }
 }
 
 }  // namespace
 
-extern "C" int fg_preprocess(const fg_tree* tree, const fg_camera* cam, float tau, const uint32_t* sel_idx,
-                             const uint32_t* n_sel, int64_t cap_sel, const fg_splats* out, uint32_t* status,
-                             void* stream)
+extern "C" int fg_preprocess(const fg_tree* tree, const uint32_t* sel_idx, const uint32_t* n_sel, int64_t cap_sel,
+                             const fg_camera* cams, int32_t n_views, const fg_camera* cams_dev, float tau,
+                             const fg_splats* out, uint32_t* status, void* stream)
 {
     (void)status;
-    if (!tree || !cam || !n_sel || !out || cap_sel < 0) return FG_ERR_INVALID_ARG;
+    if (!tree || !cams || n_views < 1 || !n_sel || !out || cap_sel < 0) return FG_ERR_INVALID_ARG;
     if (cap_sel == 0) return FG_OK;
     if (!sel_idx || !out->xy || !out->conic_o || !out->rgb_depth || !out->rect || !out->tiles)
         return FG_ERR_INVALID_ARG;
     if (tree->sh_degree < 0 || tree->sh_degree > 3) return FG_ERR_UNSUPPORTED;
     if (tree->n_nodes > 0 && (!tree->mean || !tree->scale || !tree->quat || !tree->opacity || !tree->sh))
         return FG_ERR_INVALID_ARG;
-    if (cam->width <= 0 || cam->height <= 0 || cam->width > 32768 * 16 || cam->height > 32768 * 16)
-        return FG_ERR_UNSUPPORTED;
+    for (int v = 0; v < n_views; v++)
+        if (cams[v].width <= 0 || cams[v].height <= 0 || cams[v].width > 32768 * 16 || cams[v].height > 32768 * 16)
+            return FG_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
-    const fgd::Cam c = fgd::make_cam(*cam);
-    int64_t blocks = (cap_sel + kBlock - 1) / kBlock;
-    if (blocks > 32768) blocks = 32768;
-    const dim3 g((unsigned)blocks), b(kBlock);
-    switch (tree->sh_degree) {
-        case 0: hipLaunchKernelGGL(k_preprocess<0>, g, b, 0, s, *tree, c, tau, sel_idx, n_sel, cap_sel, *out); break;
-        case 1: hipLaunchKernelGGL(k_preprocess<1>, g, b, 0, s, *tree, c, tau, sel_idx, n_sel, cap_sel, *out); break;
-        case 2: hipLaunchKernelGGL(k_preprocess<2>, g, b, 0, s, *tree, c, tau, sel_idx, n_sel, cap_sel, *out); break;
-        default: hipLaunchKernelGGL(k_preprocess<3>, g, b, 0, s, *tree, c, tau, sel_idx, n_sel, cap_sel, *out); break;
+    for (int v0 = 0; v0 < n_views; v0 += kViewsPerLaunch) {
+        const int nv = n_views - v0 < kViewsPerLaunch ? n_views - v0 : kViewsPerLaunch;
+        CamSet cs;
+        for (int v = 0; v < kViewsPerLaunch; v++) cs.c[v] = fgd::make_cam(cams[v0 + (v < nv ? v : 0)]);
+        int64_t blocks = (cap_sel + kBlock - 1) / kBlock;
+        const int64_t max_blocks = 32768 / nv;
+        if (blocks > max_blocks) blocks = max_blocks;
+        const dim3 g((unsigned)blocks, (unsigned)nv), b(kBlock);
+        const fg_camera* dc = cams_dev ? cams_dev + v0 : nullptr;
+        const uint32_t* si = sel_idx + (int64_t)v0 * cap_sel;
+        const uint32_t* ns = n_sel + v0;
+        fg_splats o = *out;
+        const int64_t off = (int64_t)v0 * cap_sel;
+        o.xy += 2 * off;
+        o.conic_o += 4 * off;
+        o.rgb_depth += 4 * off;
+        o.rect += 4 * off;
+        o.tiles += off;
+        switch (tree->sh_degree) {
+            case 0: hipLaunchKernelGGL(k_preprocess<0>, g, b, 0, s, *tree, cs, dc, tau, si, ns, cap_sel, o); break;
+            case 1: hipLaunchKernelGGL(k_preprocess<1>, g, b, 0, s, *tree, cs, dc, tau, si, ns, cap_sel, o); break;
+            case 2: hipLaunchKernelGGL(k_preprocess<2>, g, b, 0, s, *tree, cs, dc, tau, si, ns, cap_sel, o); break;
+            default: hipLaunchKernelGGL(k_preprocess<3>, g, b, 0, s, *tree, cs, dc, tau, si, ns, cap_sel, o); break;
+        }
     }
     return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
 }

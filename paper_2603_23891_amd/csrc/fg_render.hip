@@ -61,11 +61,46 @@ struct Frag {
     unsigned n_eval, n_exp, n_pass, n_blend;
 };
 
+// The views of one call. Their tiles are numbered consecutively (view v owns
+// tiles tile0[v] .. tile0[v+1] of the call, in the order of its global tile
+// ids); view v's image is [3][H][W] at image + 3 * pix0[v], its final T and
+// contributor counts at + pix0[v].
+constexpr int kMaxViews = 64;
+struct RenderViews {
+    int n;
+    uint32_t tile0[kMaxViews + 1];
+    int W[kMaxViews], H[kMaxViews], Wt[kMaxViews];
+    int64_t pix0[kMaxViews];
+};
+
+// One tile's view and geometry.
+struct TileGeom {
+    int tx, ty, W, H;
+    int64_t pix0;
+};
+
+__device__ __forceinline__ TileGeom tile_geom(const RenderViews& V, uint32_t t)
+{
+    int lo = 0, hi = V.n;  // the view v with tile0[v] <= t < tile0[v+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (V.tile0[mid] <= t) lo = mid; else hi = mid;
+    }
+    const uint32_t lt = t - V.tile0[lo];
+    TileGeom g;
+    g.tx = (int)(lt % (uint32_t)V.Wt[lo]);
+    g.ty = (int)(lt / (uint32_t)V.Wt[lo]);
+    g.W = V.W[lo];
+    g.H = V.H[lo];
+    g.pix0 = V.pix0[lo];
+    return g;
+}
+
 // One workgroup per tile, after k_schedule: the final values of an empty
 // tile's pixels (background, T = 1, no contributor), so that the blend never
 // visits it, and the mask item -> tile map of a heavy tile's chunks.
 template <int CHUNK>
-__global__ __launch_bounds__(kThreads) void k_tile_prep(int64_t n_tiles, int W, int H, int Wt, float bg0,
+__global__ __launch_bounds__(kThreads) void k_tile_prep(int64_t n_tiles, RenderViews V, float bg0,
                                                         float bg1, float bg2, const uint32_t* __restrict__ nch,
                                                         const uint32_t* __restrict__ mfirst, int64_t max_mask_items,
                                                         uint32_t* __restrict__ mitem, float* __restrict__ image,
@@ -75,16 +110,18 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(int64_t n_tiles, int W, 
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const uint32_t c = nch[t];
         if (c == 0) {
-            const int px = (int)(t % Wt) * fgd::kTile + (int)threadIdx.x % fgd::kTile;
-            const int py = (int)(t / Wt) * fgd::kTile + (int)threadIdx.x / fgd::kTile;
-            if (px < W && py < H) {
-                const size_t o = (size_t)py * W + px;
-                const size_t plane = (size_t)W * H;
-                image[o] = bg0;
-                image[plane + o] = bg1;
-                image[2 * plane + o] = bg2;
-                final_T[o] = 1.0f;
-                n_contrib[o] = 0u;
+            const TileGeom g = tile_geom(V, (uint32_t)t);
+            const int px = g.tx * fgd::kTile + (int)threadIdx.x % fgd::kTile;
+            const int py = g.ty * fgd::kTile + (int)threadIdx.x / fgd::kTile;
+            if (px < g.W && py < g.H) {
+                const size_t o = (size_t)py * g.W + px;
+                const size_t plane = (size_t)g.W * g.H;
+                float* img = image + 3 * g.pix0;
+                img[o] = bg0;
+                img[plane + o] = bg1;
+                img[2 * plane + o] = bg2;
+                final_T[g.pix0 + o] = 1.0f;
+                n_contrib[g.pix0 + o] = 0u;
             }
         } else if (c > 1) {
             const uint32_t mf = mfirst[t];
@@ -380,13 +417,24 @@ __device__ __forceinline__ void flush_stats(const Frag& f, unsigned long long* f
     }
 }
 
+// alpha of a fragment that passed the skip tests (so -5.6 <= power <= 0):
+// the same expressions as pixel_alpha, hence the same value.
+__device__ __forceinline__ float passed_alpha(float2 mm, float4 co, float fpx, float fpy)
+{
+    const float dx = mm.x - fpx;
+    const float dy = mm.y - fpy;
+    const float power = -0.5f * ((co.x * dx) * dx + (co.z * dy) * dy) - (co.y * dx) * dy;
+    const float alpha = co.w * fgd::exp_neg_in_range(power);
+    return alpha < 0.99f ? alpha : 0.99f;
+}
+
 // Pass masks of the chunks of heavy tiles, one chunk per work item (their
 // splats are mostly small: splat-parallel); masks go to global memory
 // [word][pixel].
 template <int CHUNK, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_masks(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
                                                     const uint32_t* __restrict__ vals,
-                                                    const uint32_t* __restrict__ ranges, int W, int H, int Wt,
+                                                    const uint32_t* __restrict__ ranges, RenderViews V,
                                                     RenderWs ws, unsigned long long* __restrict__ frag_stats)
 {
     constexpr int kWords = CHUNK / 32;
@@ -403,10 +451,11 @@ __global__ __launch_bounds__(kThreads) void k_masks(const float2* __restrict__ x
         const uint32_t r0 = ranges[2 * tile], r1 = ranges[2 * tile + 1];
         const uint32_t start = r0 + chunk * CHUNK;
         const int cnt = (int)(r1 - start < (uint32_t)CHUNK ? r1 - start : (uint32_t)CHUNK);
-        const int tx = (int)(tile % (uint32_t)Wt), ty = (int)(tile / (uint32_t)Wt);
+        const TileGeom tg = tile_geom(V, tile);
+        const int tx = tg.tx, ty = tg.ty;
 #pragma unroll
         for (int w = 0; w < kWords; w++) s_mask[w * kThreads + tid] = 0u;
-        stage(xy, conic_o, nullptr, vals, start, cnt, tx, ty, W, H, s_xy, s_co, nullptr, s_box);
+        stage(xy, conic_o, nullptr, vals, start, cnt, tx, ty, tg.W, tg.H, s_xy, s_co, nullptr, s_box);
         __syncthreads();
         splat_masks<STATS>(s_xy, s_co, s_box, cnt, tx, ty, s_mask, f);
         __syncthreads();
@@ -416,17 +465,6 @@ __global__ __launch_bounds__(kThreads) void k_masks(const float2* __restrict__ x
         __syncthreads();
     }
     flush_stats<STATS, 3>(f, STATS ? frag_stats + 4 : frag_stats);
-}
-
-// alpha of a fragment that passed the skip tests (so -5.6 <= power <= 0):
-// the same expressions as pixel_alpha, hence the same value.
-__device__ __forceinline__ float passed_alpha(float2 mm, float4 co, float fpx, float fpy)
-{
-    const float dx = mm.x - fpx;
-    const float dy = mm.y - fpy;
-    const float power = -0.5f * ((co.x * dx) * dx + (co.z * dy) * dy) - (co.y * dx) * dy;
-    const float alpha = co.w * fgd::exp_neg_in_range(power);
-    return alpha < 0.99f ? alpha : 0.99f;
 }
 
 struct PixelState {
@@ -612,8 +650,8 @@ template <int CHUNK, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
                                                      const float4* __restrict__ rgb_depth,
                                                      const uint32_t* __restrict__ vals,
-                                                     const uint32_t* __restrict__ ranges, int64_t n_tiles, int W,
-                                                     int H, int Wt, float bg0, float bg1, float bg2, RenderWs ws,
+                                                     const uint32_t* __restrict__ ranges, int64_t n_tiles,
+                                                     RenderViews V, float bg0, float bg1, float bg2, RenderWs ws,
                                                      float* __restrict__ image, float* __restrict__ final_T,
                                                      uint32_t* __restrict__ n_contrib,
                                                      unsigned long long* __restrict__ frag_stats)
@@ -651,7 +689,8 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
         uint32_t next_item = 0;
         if (tid == 0 && nch <= 1) next_item = atomicAdd(&ws.counters[0], 1u);
         const uint32_t mf = nch > 1 ? ws.mfirst[tile] : 0u;
-        const int tx = (int)(tile % (uint32_t)Wt), ty = (int)(tile / (uint32_t)Wt);
+        const TileGeom tg = tile_geom(V, tile);
+        const int tx = tg.tx, ty = tg.ty, W = tg.W, H = tg.H;
         const int px = tx * fgd::kTile + lx;
         const int py = ty * fgd::kTile + ly;
         const bool inside = px < W && py < H;
@@ -743,11 +782,12 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
         if (inside) {
             const size_t o = (size_t)py * W + px;
             const size_t plane = (size_t)W * H;
-            image[o] = p.C0 + p.T * bg0;
-            image[plane + o] = p.C1 + p.T * bg1;
-            image[2 * plane + o] = p.C2 + p.T * bg2;
-            final_T[o] = p.T;
-            n_contrib[o] = p.last;
+            float* img = image + 3 * tg.pix0;
+            img[o] = p.C0 + p.T * bg0;
+            img[plane + o] = p.C1 + p.T * bg1;
+            img[2 * plane + o] = p.C2 + p.T * bg2;
+            final_T[tg.pix0 + o] = p.T;
+            n_contrib[tg.pix0 + o] = p.last;
         }
         __syncthreads();  // LDS and s_item are reused by the next tile
         if (tid == 0) s_item = nch <= 1 ? next_item : atomicAdd(&ws.counters[0], 1u);
@@ -796,62 +836,96 @@ bool save_of(const fg_tune* tune) { return tune && tune->save_state; }
 int mask_items_of(const fg_tune* tune) { return tune ? tune->mask_items : 0; }
 
 template <int CHUNK>
-void launch(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
+void launch(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const RenderViews& V,
             const float bg[3], float* image, float* final_T, uint32_t* n_contrib, unsigned long long* frag_stats,
             const RenderWs& w, int64_t n_tiles, int64_t max_mask_items, const fg_tune* tune, hipStream_t s)
 {
-    const int Wt = (cam->width + 15) / 16;
     hipLaunchKernelGGL(k_schedule<CHUNK>, dim3(1), dim3(kScanThreads), 0, s, ranges, n_tiles, max_mask_items, w.nch,
                        w.mfirst, w.order, w.counters);
     const unsigned gp = (unsigned)(n_tiles < 65536 ? n_tiles : 65536);
-    hipLaunchKernelGGL(k_tile_prep<CHUNK>, dim3(gp), dim3(kThreads), 0, s, n_tiles, cam->width, cam->height,
-                       Wt, bg[0], bg[1], bg[2], w.nch, w.mfirst, max_mask_items, w.mitem, image, final_T,
-                       n_contrib);
+    hipLaunchKernelGGL(k_tile_prep<CHUNK>, dim3(gp), dim3(kThreads), 0, s, n_tiles, V, bg[0], bg[1], bg[2], w.nch,
+                       w.mfirst, max_mask_items, w.mitem, image, final_T, n_contrib);
     const float2* xy = (const float2*)splats->xy;
     const float4* co = (const float4*)splats->conic_o;
     const float4* rgb = (const float4*)splats->rgb_depth;
     const unsigned gm = (unsigned)(max_mask_items < 4096 ? (max_mask_items < 1 ? 1 : max_mask_items) : 4096);
     const unsigned gr = (unsigned)(n_tiles < 4096 ? n_tiles : 4096);
     if (frag_stats) {
-        hipLaunchKernelGGL((k_masks<CHUNK, true>), dim3(gm), dim3(kThreads), 0, s, xy, co, vals, ranges, cam->width,
-                           cam->height, Wt, w, frag_stats);
+        hipLaunchKernelGGL((k_masks<CHUNK, true>), dim3(gm), dim3(kThreads), 0, s, xy, co, vals, ranges, V, w,
+                           frag_stats);
         hipLaunchKernelGGL((k_render<CHUNK, true>), dim3(gr), dim3(kThreads), 0, s, xy, co, rgb, vals, ranges, n_tiles,
-                           cam->width, cam->height, Wt, bg[0], bg[1], bg[2], w, image, final_T, n_contrib, frag_stats);
+                           V, bg[0], bg[1], bg[2], w, image, final_T, n_contrib, frag_stats);
     } else {
-        hipLaunchKernelGGL((k_masks<CHUNK, false>), dim3(gm), dim3(kThreads), 0, s, xy, co, vals, ranges, cam->width,
-                           cam->height, Wt, w, frag_stats);
+        hipLaunchKernelGGL((k_masks<CHUNK, false>), dim3(gm), dim3(kThreads), 0, s, xy, co, vals, ranges, V, w,
+                           frag_stats);
         const bool timed = tune && tune->blend_events[0] && tune->blend_events[1];
         if (timed) (void)hipEventRecord((hipEvent_t)tune->blend_events[0], s);
         hipLaunchKernelGGL((k_render<CHUNK, false>), dim3(gr), dim3(kThreads), 0, s, xy, co, rgb, vals, ranges, n_tiles,
-                           cam->width, cam->height, Wt, bg[0], bg[1], bg[2], w, image, final_T, n_contrib, frag_stats);
+                           V, bg[0], bg[1], bg[2], w, image, final_T, n_contrib, frag_stats);
         if (timed) (void)hipEventRecord((hipEvent_t)tune->blend_events[1], s);
     }
 }
 
 }  // namespace
 
-extern "C" size_t fg_render_workspace_size(const fg_camera* cam, int64_t cap_pairs, const fg_tune* tune)
+namespace {
+
+// The views' geometry and total tile count (-1: invalid views: sizes, more
+// than kMaxViews, or global tile ids that are not consecutive from view to
+// view).
+int64_t make_views(const fg_camera* cams, int32_t n_views, RenderViews* V)
 {
-    if (!cam || cam->width <= 0 || cam->height <= 0 || cap_pairs < 0) return 0;
-    const int64_t n_tiles = (int64_t)((cam->width + 15) / 16) * ((cam->height + 15) / 16);
+    if (!cams || n_views < 1 || n_views > kMaxViews) return -1;
+    int64_t total = 0, pix = 0;
+    V->n = n_views;
+    for (int v = 0; v < n_views; v++) {
+        const fg_camera& c = cams[v];
+        if (c.width <= 0 || c.height <= 0) return -1;
+        if ((int64_t)c.tile_base != (int64_t)cams[0].tile_base + total) return -1;
+        V->tile0[v] = (uint32_t)total;
+        V->W[v] = c.width;
+        V->H[v] = c.height;
+        V->Wt[v] = (c.width + 15) / 16;
+        V->pix0[v] = pix;
+        total += (int64_t)V->Wt[v] * ((c.height + 15) / 16);
+        pix += (int64_t)c.width * c.height;
+        if (total >= ((int64_t)1 << 31)) return -1;
+    }
+    V->tile0[n_views] = (uint32_t)total;
+    for (int v = n_views; v < kMaxViews; v++) {
+        V->tile0[v + 1] = (uint32_t)total;
+        V->W[v] = V->H[v] = V->Wt[v] = 1;
+        V->pix0[v] = pix;
+    }
+    return total;
+}
+
+}  // namespace
+
+extern "C" size_t fg_render_workspace_size(const fg_camera* cams, int32_t n_views, int64_t cap_pairs,
+                                           const fg_tune* tune)
+{
+    RenderViews V;
+    const int64_t n_tiles = make_views(cams, n_views, &V);
+    if (n_tiles < 0 || cap_pairs < 0) return 0;
     RenderWs w;
     int64_t mi;
     return carve(nullptr, n_tiles, cap_pairs, chunk_of(tune), save_of(tune), mask_items_of(tune), &w, &mi);
 }
 
-extern "C" int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
-                         const float bg[3], float* image, float* final_T, uint32_t* n_contrib, int64_t cap_pairs,
-                         unsigned long long* frag_stats, uint32_t* status, void* ws, size_t ws_bytes,
-                         const fg_tune* tune, void* stream)
+extern "C" int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges,
+                         const fg_camera* cams, int32_t n_views, const float bg[3], float* image, float* final_T,
+                         uint32_t* n_contrib, int64_t cap_pairs, unsigned long long* frag_stats, uint32_t* status,
+                         void* ws, size_t ws_bytes, const fg_tune* tune, void* stream)
 {
     (void)status;
-    if (!splats || !ranges || !cam || !bg || !image || !final_T || !n_contrib || cap_pairs < 0)
+    if (!splats || !ranges || !cams || !bg || !image || !final_T || !n_contrib || cap_pairs < 0)
         return FG_ERR_INVALID_ARG;
-    if (cam->width <= 0 || cam->height <= 0) return FG_ERR_INVALID_ARG;
+    RenderViews V;
+    const int64_t n_tiles = make_views(cams, n_views, &V);
+    if (n_tiles < 0) return FG_ERR_INVALID_ARG;
     const int chunk = chunk_of(tune);
     if (chunk != 128 && chunk != 256 && chunk != 512) return FG_ERR_INVALID_ARG;
-    const int64_t n_tiles = (int64_t)((cam->width + 15) / 16) * ((cam->height + 15) / 16);
-    if (n_tiles >= ((int64_t)1 << 31)) return FG_ERR_UNSUPPORTED;
     RenderWs w;
     int64_t max_mask_items;
     const bool save = save_of(tune);
@@ -860,11 +934,11 @@ extern "C" int fg_render(const fg_splats* splats, const uint32_t* vals, const ui
     carve(ws, n_tiles, cap_pairs, chunk, save, mask_items_of(tune), &w, &max_mask_items);
     hipStream_t s = (hipStream_t)stream;
     switch (chunk) {
-        case 128: launch<128>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
+        case 128: launch<128>(splats, vals, ranges, V, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
                               max_mask_items, tune, s); break;
-        case 512: launch<512>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
+        case 512: launch<512>(splats, vals, ranges, V, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
                               max_mask_items, tune, s); break;
-        default: launch<256>(splats, vals, ranges, cam, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
+        default: launch<256>(splats, vals, ranges, V, bg, image, final_T, n_contrib, frag_stats, w, n_tiles,
                              max_mask_items, tune, s); break;
     }
     return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;

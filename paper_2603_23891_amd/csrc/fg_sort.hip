@@ -31,6 +31,8 @@
 // between counting and writing.
 #include "fg_device.h"
 
+#include <algorithm>
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -85,20 +87,20 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
     return m;
 }
 
-template <int BITS>
+template <int BITS, int IPT>
 __global__ __launch_bounds__(kThreads) void k_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_p,
                                                    int64_t cap, int shift, uint32_t* __restrict__ hist)
 {
     constexpr int R = 1 << BITS;
     __shared__ uint32_t h[R];
     const int64_t n = count_of(n_p, cap);
-    const int64_t n_tiles = (n + kTileItems - 1) / kTileItems;
+    const int64_t n_tiles = (n + (kThreads * IPT) - 1) / (kThreads * IPT);
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         for (int d = threadIdx.x; d < R; d += kThreads) h[d] = 0;
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kIPT; r++) {
-            const int64_t idx = tile * kTileItems + r * kThreads + threadIdx.x;
+        for (int r = 0; r < IPT; r++) {
+            const int64_t idx = tile * (kThreads * IPT) + r * kThreads + threadIdx.x;
             const bool valid = idx < n;
             const uint32_t d = valid ? (keys[idx] >> shift) & (R - 1) : 0u;
             if (valid) atomicAdd(&h[d], 1u);
@@ -110,12 +112,13 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint32_t* __restrict__ 
 }
 
 // One workgroup per digit: exclusive scan of hist[digit][0..n_tiles) in place.
+template <int IPT>
 __global__ __launch_bounds__(kThreads) void k_rowscan(const uint32_t* __restrict__ n_p, int64_t cap,
                                                       uint32_t* __restrict__ hist, uint32_t* __restrict__ digit_total)
 {
     __shared__ uint32_t s_wave[kWaves];
     const int64_t n = count_of(n_p, cap);
-    const int64_t n_tiles = (n + kTileItems - 1) / kTileItems;
+    const int64_t n_tiles = (n + (kThreads * IPT) - 1) / (kThreads * IPT);
     uint32_t* row = hist + (int64_t)blockIdx.x * n_tiles;
     const int64_t per = (n_tiles + kThreads - 1) / kThreads;
     const int64_t lo = threadIdx.x * per;
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_rowscan(const uint32_t* __restrict
     if (threadIdx.x == 0) digit_total[blockIdx.x] = total;
 }
 
-template <int BITS>
+template <int BITS, int IPT>
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                       uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                       const uint32_t* __restrict__ n_p, int64_t cap, int shift,
@@ -155,13 +158,13 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
     __shared__ uint32_t s_base[R];
     __shared__ uint32_t s_start[R];
     // per (round, wave, digit): the group's count, then its exclusive offset
-    // among the tile's items of that digit (at most kTileItems: fits 16 bits)
-    __shared__ uint16_t s_cnt[kIPT][kWaves][R];
-    __shared__ uint32_t s_keys[kTileItems];
-    __shared__ uint32_t s_vals[kTileItems];
+    // among the tile's items of that digit (at most (kThreads * IPT): fits 16 bits)
+    __shared__ uint16_t s_cnt[IPT][kWaves][R];
+    __shared__ uint32_t s_keys[(kThreads * IPT)];
+    __shared__ uint32_t s_vals[(kThreads * IPT)];
     __shared__ uint32_t s_wave[kWaves];
     const int64_t n = count_of(n_p, cap);
-    const int64_t n_tiles = (n + kTileItems - 1) / kTileItems;
+    const int64_t n_tiles = (n + (kThreads * IPT) - 1) / (kThreads * IPT);
     const int tid = threadIdx.x;
     const int wave = tid / fgd::kWave;
     {
@@ -171,24 +174,24 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
         if (tid < R) s_base[tid] = e;
     }
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        uint32_t k[kIPT], v[kIPT], below[kIPT];
+        uint32_t k[IPT], v[IPT], below[IPT];
 #pragma unroll
-        for (int r = 0; r < kIPT; r++) {
-            const int64_t idx = tile * kTileItems + r * kThreads + tid;
+        for (int r = 0; r < IPT; r++) {
+            const int64_t idx = tile * (kThreads * IPT) + r * kThreads + tid;
             const bool valid = idx < n;
             k[r] = valid ? kin[idx] : 0xFFFFFFFFu;
             v[r] = valid ? vin[idx] : 0u;
         }
         {
             uint32_t* c32 = reinterpret_cast<uint32_t*>(&s_cnt[0][0][0]);
-            for (int i = tid; i < kIPT * kWaves * R / 2; i += kThreads) c32[i] = 0u;
+            for (int i = tid; i < IPT * kWaves * R / 2; i += kThreads) c32[i] = 0u;
         }
         __syncthreads();
         // every wave ranks its items of every round among equal digits
         // (ballot match), with no barrier between rounds
 #pragma unroll
-        for (int r = 0; r < kIPT; r++) {
-            const int64_t idx = tile * kTileItems + r * kThreads + tid;
+        for (int r = 0; r < IPT; r++) {
+            const int64_t idx = tile * (kThreads * IPT) + r * kThreads + tid;
             const bool valid = idx < n;
             const uint32_t d = (k[r] >> shift) & (R - 1);
             const uint64_t m = match_digit<BITS>(d, valid);
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
         uint32_t run = 0;
         if (tid < R) {
 #pragma unroll
-            for (int r = 0; r < kIPT; r++)
+            for (int r = 0; r < IPT; r++)
 #pragma unroll
                 for (int w = 0; w < kWaves; w++) {
                     const uint32_t c = s_cnt[r][w][tid];
@@ -215,8 +218,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kIPT; r++) {
-            const int64_t idx = tile * kTileItems + r * kThreads + tid;
+        for (int r = 0; r < IPT; r++) {
+            const int64_t idx = tile * (kThreads * IPT) + r * kThreads + tid;
             if (idx < n) {
                 const uint32_t d = (k[r] >> shift) & (R - 1);
                 const uint32_t pos = s_start[d] + s_cnt[r][wave][d] + below[r];
@@ -225,9 +228,9 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
             }
         }
         __syncthreads();
-        const int64_t cnt = n - tile * kTileItems < kTileItems ? n - tile * kTileItems : kTileItems;
+        const int64_t cnt = n - tile * (kThreads * IPT) < (kThreads * IPT) ? n - tile * (kThreads * IPT) : (kThreads * IPT);
 #pragma unroll
-        for (int r = 0; r < kIPT; r++) {
+        for (int r = 0; r < IPT; r++) {
             const int p = r * kThreads + tid;
             if (p < cnt) {
                 const uint32_t key = s_keys[p];
@@ -241,47 +244,115 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
     }
 }
 
-// Sum of v[0 .. k) over the workgroup (every thread gets it).
-__device__ __forceinline__ unsigned long long block_prefix(const uint32_t* __restrict__ v, int64_t k,
-                                                           unsigned long long* s_red)
+// The views of one call: their splats lie at stride cap_sel in the splat
+// planes (view v's splat j is global splat v * cap_sel + j), and their tiles
+// have the consecutive global ids tile_base[v] + ty * Wt[v] + tx.
+constexpr int kMaxViews = 64;
+struct SortViews {
+    int n;
+    uint32_t cap_sel;
+    uint32_t Wt[kMaxViews];
+    uint32_t tile_base[kMaxViews];
+};
+
+// s_seg[v] = sum over views u < v of min(n_sel[u], cap_sel) (v = 0 .. n): the
+// position of view v's first splat among the concatenated selections. Read by
+// the first wave; ends with a barrier.
+__device__ __forceinline__ void load_segments(const uint32_t* __restrict__ n_sel, const SortViews& V,
+                                              uint32_t* s_seg)
 {
-    unsigned long long x = 0;
-    for (int64_t i0 = threadIdx.x; i0 < k; i0 += 4 * kThreads) {  // 4 independent loads per step
-        uint32_t a[4];
+    if (threadIdx.x < fgd::kWave) {
+        const int lane = fgd::lane_id();
+        uint32_t c = 0;
+        if (lane < V.n) {
+            c = n_sel[lane];
+            c = c < V.cap_sel ? c : V.cap_sel;
+        }
+        uint32_t x = c;
 #pragma unroll
-        for (int u = 0; u < 4; u++) a[u] = i0 + u * kThreads < k ? v[i0 + u * kThreads] : 0u;
-#pragma unroll
-        for (int u = 0; u < 4; u++) x += a[u];
+        for (int d = 1; d < fgd::kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, fgd::kWave);
+            if (lane >= d) x += y;
+        }
+        if (lane == 0) s_seg[0] = 0u;
+        if (lane < V.n) s_seg[lane + 1] = x;
     }
-#pragma unroll
-    for (int d = fgd::kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, fgd::kWave);
-    if (fgd::lane_id() == 0) s_red[threadIdx.x / fgd::kWave] = x;
     __syncthreads();
-    unsigned long long t = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; w++) t += s_red[w];
-    __syncthreads();
-    return t;
 }
 
-// Per 1024 splats (index order): how many cover at least one tile. Also
-// clears the tile ranges of this view.
-__global__ __launch_bounds__(kThreads) void k_vis_count(const uint32_t* __restrict__ tiles,
-                                                        const uint32_t* __restrict__ n_p, int64_t cap,
-                                                        uint32_t* __restrict__ vcnt, uint32_t* __restrict__ ranges,
-                                                        int64_t n_tiles)
+// Global splat index of concatenated selection item i (i < s_seg[n]).
+__device__ __forceinline__ uint32_t item_splat(uint32_t i, const uint32_t* s_seg, const SortViews& V)
+{
+    int lo = 0, hi = V.n;  // the last view v with s_seg[v] <= i
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_seg[mid] <= i) lo = mid; else hi = mid;
+    }
+    return (uint32_t)lo * V.cap_sel + (i - s_seg[lo]);
+}
+
+// One workgroup: cnt[0 .. *nblk_items / per) becomes its exclusive prefix sum
+// in place, *total the sum (and *total_out, when given, a copy of it clamped
+// to 32 bits; overflow of cap sets status bit). The number of blocks is
+// derived from the item count that the previous kernel counted over.
+__global__ __launch_bounds__(kThreads) void k_block_scan(uint32_t* __restrict__ cnt, const uint32_t* __restrict__ n_items,
+                                                         int64_t per, int64_t cap_items, uint32_t* __restrict__ total,
+                                                         uint32_t* __restrict__ total_out, int64_t cap_total,
+                                                         uint32_t* __restrict__ status, uint32_t overflow_bit)
 {
     __shared__ uint32_t s_wave[kWaves];
-    const int64_t n = count_of(n_p, cap);
-    const int64_t nblk = (n + kTileItems - 1) / kTileItems;
+    const int64_t n = count_of(n_items, cap_items);
+    const int64_t nblk = (n + per - 1) / per;
+    const int tid = threadIdx.x;
+    unsigned long long carry = 0;
+    for (int64_t base = 0; base < nblk; base += (int64_t)kThreads * 8) {
+        uint32_t c[8];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int64_t i = base + (int64_t)tid * 8 + k;
+            c[k] = i < nblk ? cnt[i] : 0u;
+            sum += c[k];
+        }
+        uint32_t tot;
+        unsigned long long run = carry + block_excl_scan(sum, s_wave, tot);
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int64_t i = base + (int64_t)tid * 8 + k;
+            if (i < nblk) cnt[i] = (uint32_t)run;
+            run += c[k];
+        }
+        carry += tot;
+    }
+    if (tid == 0) {
+        const uint32_t t32 = (uint32_t)(carry < 0xFFFFFFFFull ? carry : 0xFFFFFFFFull);
+        *total = t32;
+        if (total_out) *total_out = t32;
+        if ((long long)carry > cap_total) atomicOr(status, overflow_bit);
+    }
+}
+
+// Per 1024 items of the concatenated selections: how many cover at least one
+// tile. Also clears the tile ranges of every view.
+__global__ __launch_bounds__(kThreads) void k_vis_count(const uint32_t* __restrict__ tiles,
+                                                        const uint32_t* __restrict__ n_sel, SortViews V,
+                                                        uint32_t* __restrict__ vcnt, uint32_t* __restrict__ n_items,
+                                                        uint32_t* __restrict__ ranges, int64_t n_tiles)
+{
+    __shared__ uint32_t s_wave[kWaves];
+    __shared__ uint32_t s_seg[kMaxViews + 1];
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < 2 * n_tiles; t += (int64_t)gridDim.x * kThreads)
         ranges[t] = 0u;
+    load_segments(n_sel, V, s_seg);
+    const int64_t n = s_seg[V.n];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_items = (uint32_t)n;
+    const int64_t nblk = (n + kTileItems - 1) / kTileItems;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         uint32_t c = 0;
 #pragma unroll
         for (int r = 0; r < kIPT; r++) {
             const int64_t j = blk * kTileItems + r * kThreads + threadIdx.x;
-            if (j < n && tiles[j] != 0u) ++c;
+            if (j < n && tiles[item_splat((uint32_t)j, s_seg, V)] != 0u) ++c;
         }
         uint32_t total;
         block_excl_scan(c, s_wave, total);
@@ -289,30 +360,33 @@ __global__ __launch_bounds__(kThreads) void k_vis_count(const uint32_t* __restri
     }
 }
 
-// Packs the splats that cover a tile, in index order: dkey = depth bits,
-// dval = splat index; *n_vis = their number. A block's packed run is
-// assembled in LDS, then written with consecutive lanes on consecutive
-// addresses.
+// Packs the splats that cover a tile, in concatenated order (view, then
+// index): dkey = depth bits, dval = global splat index, at the block's offset
+// (vcnt, scanned). A block's packed run is assembled in LDS, then written
+// with consecutive lanes on consecutive addresses.
 __global__ __launch_bounds__(kThreads) void k_vis_pack(const float4* __restrict__ rgb_depth,
                                                        const uint32_t* __restrict__ tiles,
-                                                       const uint32_t* __restrict__ n_p, int64_t cap,
-                                                       const uint32_t* __restrict__ vcnt, uint32_t* __restrict__ dkey,
-                                                       uint32_t* __restrict__ dval, uint32_t* __restrict__ n_vis)
+                                                       const uint32_t* __restrict__ n_sel, SortViews V,
+                                                       const uint32_t* __restrict__ voff, int64_t cap_items,
+                                                       uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval)
 {
     __shared__ uint32_t s_wave[kWaves];
-    __shared__ unsigned long long s_red[kWaves];
+    __shared__ uint32_t s_seg[kMaxViews + 1];
     __shared__ uint32_t s_k[kTileItems];
     __shared__ uint32_t s_v[kTileItems];
-    const int64_t n = count_of(n_p, cap);
+    load_segments(n_sel, V, s_seg);
+    const int64_t n = s_seg[V.n];
     const int64_t nblk = (n + kTileItems - 1) / kTileItems;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const unsigned long long base = block_prefix(vcnt, blk, s_red);
+        const uint32_t base = voff[blk];
         const int64_t j0 = blk * kTileItems + (int64_t)threadIdx.x * kIPT;
         uint32_t c = 0;
         bool vis[kIPT];
+        uint32_t g[kIPT];
 #pragma unroll
         for (int r = 0; r < kIPT; r++) {
-            vis[r] = j0 + r < n && tiles[j0 + r] != 0u;
+            g[r] = j0 + r < n ? item_splat((uint32_t)(j0 + r), s_seg, V) : 0u;
+            vis[r] = j0 + r < n && tiles[g[r]] != 0u;
             c += vis[r] ? 1u : 0u;
         }
         uint32_t total;
@@ -320,21 +394,18 @@ __global__ __launch_bounds__(kThreads) void k_vis_pack(const float4* __restrict_
 #pragma unroll
         for (int r = 0; r < kIPT; r++) {
             if (vis[r]) {
-                s_k[off] = __float_as_uint(rgb_depth[j0 + r].w);
-                s_v[off] = (uint32_t)(j0 + r);
+                s_k[off] = __float_as_uint(rgb_depth[g[r]].w);
+                s_v[off] = g[r];
                 ++off;
             }
         }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < total; i += kThreads) {
-            dkey[base + i] = s_k[i];
-            dval[base + i] = s_v[i];
-        }
+        for (uint32_t i = threadIdx.x; i < total; i += kThreads)
+            if ((int64_t)base + i < cap_items) {
+                dkey[base + i] = s_k[i];
+                dval[base + i] = s_v[i];
+            }
         __syncthreads();
-    }
-    if (blockIdx.x == 0) {
-        const unsigned long long t = block_prefix(vcnt, nblk, s_red);
-        if (threadIdx.x == 0) *n_vis = (uint32_t)t;
     }
 }
 
@@ -367,20 +438,18 @@ __global__ __launch_bounds__(kThreads) void k_count_reduce(const uint32_t* __res
 }
 
 // Per 1024 splats in depth order: every splat's output offset (the block's
-// offset, summed from the earlier blocks' totals, plus an exclusive scan
-// within the block), then the block's pairs are written with thread k taking
-// output positions k, k + 256, ...: a binary search over the offsets finds
-// the splat, and the position within its rectangle (rows, then columns)
-// gives the tile. Block 0 also stores n_pairs and flags an overflow.
+// offset from the scanned block sums, plus an exclusive scan within the
+// block), then the block's pairs are written with thread k taking output
+// positions k, k + 256, ...: a binary search over the offsets finds the
+// splat, and the position within its rectangle (rows, then columns) gives
+// the tile, numbered in its view's global tile ids.
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order,
                                                    const ushort4* __restrict__ rect_d, const uint32_t* __restrict__ n_p,
-                                                   int64_t cap, const uint32_t* __restrict__ bsum, int64_t cap_pairs,
-                                                   int Wt, uint32_t tile_base, uint32_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals, uint32_t* __restrict__ n_pairs,
-                                                   uint32_t* __restrict__ status)
+                                                   int64_t cap, const uint32_t* __restrict__ boff, int64_t cap_pairs,
+                                                   SortViews V, uint32_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals)
 {
     __shared__ uint32_t s_wave[kWaves];
-    __shared__ unsigned long long s_red[kWaves];
     __shared__ uint32_t s_off[kEmitItems + 1];
     __shared__ uint32_t s_g[kEmitItems];
     __shared__ ushort4 s_rect[kEmitItems];
@@ -388,7 +457,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
     const int64_t nblk = (n + kEmitItems - 1) / kEmitItems;
     const int tid = threadIdx.x;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const unsigned long long base = block_prefix(bsum, blk, s_red);
+        const unsigned long long base = boff[blk];
         const int64_t j0 = blk * kEmitItems + (int64_t)tid * kEmitIPT;
         uint32_t c[kEmitIPT];
         uint32_t sum = 0;
@@ -423,23 +492,25 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
             }
             ushort4 q = s_rect[lo];
             uint32_t w = (uint32_t)(q.z - q.x);
+            uint32_t gv = s_g[lo] / V.cap_sel;
             const uint32_t local = o0 - s_off[lo];
             uint32_t ty = q.y + local / w, tx = q.x + local % w;
-            const int n = total - o0 < (uint32_t)kEmitRun ? (int)(total - o0) : kEmitRun;
-            for (int r = 0; r < n; r++) {
+            const int m = total - o0 < (uint32_t)kEmitRun ? (int)(total - o0) : kEmitRun;
+            for (int r = 0; r < m; r++) {
                 const unsigned long long dst = base + o0 + (uint32_t)r;
                 if (dst < (unsigned long long)cap_pairs) {
-                    keys[dst] = tile_base + ty * (uint32_t)Wt + tx;
+                    keys[dst] = V.tile_base[gv] + ty * V.Wt[gv] + tx;
                     vals[dst] = s_g[lo];
                 }
-                if (r + 1 < n && ++tx == q.z) {
+                if (r + 1 < m && ++tx == q.z) {
                     tx = q.x;
-                    if (++ty == q.w) {  // next splat with a tile (one exists: r + 1 < n)
+                    if (++ty == q.w) {  // next splat with a tile (one exists: r + 1 < m)
                         do {
                             ++lo;
                         } while (s_off[lo + 1] == s_off[lo]);
                         q = s_rect[lo];
                         w = (uint32_t)(q.z - q.x);
+                        gv = s_g[lo] / V.cap_sel;
                         tx = q.x;
                         ty = q.y;
                     }
@@ -447,13 +518,6 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
             }
         }
         __syncthreads();
-    }
-    if (blockIdx.x == 0) {
-        const unsigned long long t = block_prefix(bsum, nblk, s_red);
-        if (tid == 0) {
-            *n_pairs = (uint32_t)(t < 0xFFFFFFFFull ? t : 0xFFFFFFFFull);
-            if ((long long)t > cap_pairs) atomicOr(status, FG_STATUS_PAIR_OVERFLOW);
-        }
     }
 }
 
@@ -478,114 +542,160 @@ int64_t tiles_for(int64_t n) { return (n + kTileItems - 1) / kTileItems; }
 // has an even number of passes and ends in buffer 0, after which buffer 1
 // (8 bytes per splat) holds the rectangles in depth order.
 struct SortWs {
-    uint32_t *dkey0, *dval0, *dkey1, *dval1, *bsum, *kalt, *valt, *hist, *digit_total, *vcnt, *n_vis;
+    uint32_t *dkey0, *dval0, *dkey1, *dval1, *bsum, *kalt, *valt, *hist, *digit_total, *vcnt, *counts;
     ushort4* rect_d;
 };
+// counts[0]: concatenated selection items, [1]: tile-covering splats packed
 
-size_t carve(void* base, int64_t cap_sel, int64_t cap_pairs, SortWs* w)
+size_t carve(void* base, int64_t sel_items, int64_t cap_items, int64_t cap_pairs, SortWs* w)
 {
-    const int64_t ht = tiles_for(cap_sel > cap_pairs ? cap_sel : cap_pairs);
-    const int64_t blk_items = kTileItems < kEmitItems ? kTileItems : kEmitItems;  // vcnt and bsum entries
-    const size_t nblk = (size_t)((cap_sel + blk_items - 1) / blk_items + 1);
+    const int64_t ht = tiles_for(cap_items > cap_pairs ? cap_items : cap_pairs);
+    const size_t nblk_sel = (size_t)((sel_items + kTileItems - 1) / kTileItems + 1);
+    const size_t nblk_emit = (size_t)((cap_items + kEmitItems - 1) / kEmitItems + 1);
     const size_t sizes[10] = {
-        (size_t)cap_sel * 4, (size_t)cap_sel * 4, (size_t)cap_sel * 8, nblk * 4,
+        (size_t)cap_items * 4, (size_t)cap_items * 4, (size_t)cap_items * 8, nblk_emit * 4,
         (size_t)cap_pairs * 4, (size_t)cap_pairs * 4,
-        (size_t)256 * (size_t)(ht + 1) * 4, (size_t)256 * 4, nblk * 4, 4};
+        (size_t)256 * (size_t)(ht + 1) * 4, (size_t)256 * 4, nblk_sel * 4, 16};
     uint32_t** dst[10] = {&w->dkey0, &w->dval0, &w->dkey1, &w->bsum, &w->kalt, &w->valt, &w->hist,
-                          &w->digit_total, &w->vcnt, &w->n_vis};
+                          &w->digit_total, &w->vcnt, &w->counts};
     size_t off = 0;
     for (int i = 0; i < 10; i++) {
         if (base) *dst[i] = (uint32_t*)((char*)base + off);
         off += align_up(sizes[i] + 4);
     }
     if (base) {
-        w->dval1 = w->dkey1 + cap_sel;
+        w->dval1 = w->dkey1 + cap_items;
         w->rect_d = reinterpret_cast<ushort4*>(w->dkey1);
     }
     return off;
 }
 
-template <int BITS>
-void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint32_t* n_p,
-                int64_t cap, int shift, const SortWs& w, hipStream_t s)
+// Items per thread of a radix pass: 4 (1024-item tiles) for one view, whose
+// counts are a few million; 16 (4096-item tiles) for a batch of views with a
+// capacity of tens of millions, where a scatter tile's 256 digit runs would
+// otherwise average four items (16-byte writes into 128-byte lines). Chosen
+// from the call's shape on the host (the counts stay on the device).
+constexpr int64_t kBigSort = (int64_t)4 << 20;
+
+template <int BITS, int IPT>
+void radix_pass_ipt(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint32_t* n_p,
+                    int64_t cap, int shift, const SortWs& w, hipStream_t s)
 {
-    int64_t grid = tiles_for(cap);
+    int64_t grid = (cap + kThreads * IPT - 1) / (kThreads * IPT);
     if (grid > 4096) grid = 4096;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_hist<BITS>, dim3((unsigned)grid), dim3(kThreads), 0, s, kin, n_p, cap, shift, w.hist);
-    hipLaunchKernelGGL(k_rowscan, dim3(1u << BITS), dim3(kThreads), 0, s, n_p, cap, w.hist, w.digit_total);
-    hipLaunchKernelGGL(k_scatter<BITS>, dim3((unsigned)grid), dim3(kThreads), 0, s, kin, vin, kout, vout, n_p, cap,
-                       shift, w.hist, w.digit_total);
+    hipLaunchKernelGGL((k_hist<BITS, IPT>), dim3((unsigned)grid), dim3(kThreads), 0, s, kin, n_p, cap, shift, w.hist);
+    hipLaunchKernelGGL(k_rowscan<IPT>, dim3(1u << BITS), dim3(kThreads), 0, s, n_p, cap, w.hist, w.digit_total);
+    hipLaunchKernelGGL((k_scatter<BITS, IPT>), dim3((unsigned)grid), dim3(kThreads), 0, s, kin, vin, kout, vout, n_p,
+                       cap, shift, w.hist, w.digit_total);
+}
+
+template <int BITS>
+void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint32_t* n_p,
+                int64_t cap, int shift, bool big, const SortWs& w, hipStream_t s)
+{
+    if (big) radix_pass_ipt<BITS, 16>(kin, vin, kout, vout, n_p, cap, shift, w, s);
+    else radix_pass_ipt<BITS, 4>(kin, vin, kout, vout, n_p, cap, shift, w, s);
 }
 
 void radix_pass_bits(int bits, const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                     const uint32_t* n_p, int64_t cap, int shift, const SortWs& w, hipStream_t s)
+                     const uint32_t* n_p, int64_t cap, int shift, bool big, const SortWs& w, hipStream_t s)
 {
     switch (bits) {
-        case 4: radix_pass<4>(kin, vin, kout, vout, n_p, cap, shift, w, s); break;
-        case 5: radix_pass<5>(kin, vin, kout, vout, n_p, cap, shift, w, s); break;
-        case 6: radix_pass<6>(kin, vin, kout, vout, n_p, cap, shift, w, s); break;
-        case 7: radix_pass<7>(kin, vin, kout, vout, n_p, cap, shift, w, s); break;
-        default: radix_pass<8>(kin, vin, kout, vout, n_p, cap, shift, w, s); break;
+        case 4: radix_pass<4>(kin, vin, kout, vout, n_p, cap, shift, big, w, s); break;
+        case 5: radix_pass<5>(kin, vin, kout, vout, n_p, cap, shift, big, w, s); break;
+        case 6: radix_pass<6>(kin, vin, kout, vout, n_p, cap, shift, big, w, s); break;
+        case 7: radix_pass<7>(kin, vin, kout, vout, n_p, cap, shift, big, w, s); break;
+        default: radix_pass<8>(kin, vin, kout, vout, n_p, cap, shift, big, w, s); break;
     }
+}
+
+// Validates the views of a sort or render call: sizes, consecutive global
+// tile ids (view v's first tile follows view v-1's last). Returns the total
+// tile count, or -1.
+int64_t views_tiles(const fg_camera* cams, int32_t n_views)
+{
+    if (!cams || n_views < 1 || n_views > kMaxViews) return -1;
+    int64_t total = 0;
+    for (int v = 0; v < n_views; v++) {
+        if (cams[v].width <= 0 || cams[v].height <= 0) return -1;
+        const int64_t nt = (int64_t)((cams[v].width + 15) / 16) * ((cams[v].height + 15) / 16);
+        if ((int64_t)cams[v].tile_base != (int64_t)cams[0].tile_base + total) return -1;
+        total += nt;
+    }
+    if ((uint64_t)cams[0].tile_base + (uint64_t)total - 1 > 0xFFFFFFFFull) return -1;
+    return total;
 }
 
 }  // namespace
 
-extern "C" size_t fg_sort_workspace_size(int64_t cap_sel, int64_t cap_pairs, const fg_camera* cam)
+extern "C" size_t fg_sort_workspace_size(int64_t cap_sel, int32_t n_views, int64_t cap_items, int64_t cap_pairs)
 {
-    (void)cam;
-    if (cap_sel < 0 || cap_pairs < 0) return 0;
+    if (cap_sel < 0 || n_views < 1 || cap_items < 0 || cap_pairs < 0) return 0;
     SortWs w;
-    return carve(nullptr, cap_sel, cap_pairs, &w);
+    return carve(nullptr, cap_sel * n_views, cap_items, cap_pairs, &w);
 }
 
-extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t cap_sel, const fg_camera* cam,
-                       uint32_t* tile_keys, uint32_t* vals, int64_t cap_pairs, uint32_t* n_pairs, uint32_t* ranges,
-                       uint32_t* status, void* ws, size_t ws_bytes, const fg_tune* tune, void* stream)
+extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t cap_sel, const fg_camera* cams,
+                       int32_t n_views, int64_t cap_items, uint32_t* tile_keys, uint32_t* vals, int64_t cap_pairs,
+                       uint32_t* n_pairs, uint32_t* ranges, uint32_t* status, void* ws, size_t ws_bytes,
+                       const fg_tune* tune, void* stream)
 {
-    if (!splats || !n_sel || !cam || !n_pairs || !ranges || !status || cap_sel < 0 || cap_pairs < 0)
+    if (!splats || !n_sel || !cams || !n_pairs || !ranges || !status || cap_sel < 0 || cap_pairs < 0 ||
+        cap_items < 0 || n_views < 1)
         return FG_ERR_INVALID_ARG;
-    if (cap_sel >= ((int64_t)1 << 31) || cap_pairs >= ((int64_t)1 << 32) - 1) return FG_ERR_UNSUPPORTED;
+    if (n_views > kMaxViews || cap_sel * n_views >= ((int64_t)1 << 32) || cap_items >= ((int64_t)1 << 31) ||
+        cap_pairs >= ((int64_t)1 << 32) - 1)
+        return FG_ERR_UNSUPPORTED;
     if (cap_pairs > 0 && (!tile_keys || !vals)) return FG_ERR_INVALID_ARG;
     if (cap_sel > 0 && (!splats->rgb_depth || !splats->rect || !splats->tiles)) return FG_ERR_INVALID_ARG;
-    if (cam->width <= 0 || cam->height <= 0) return FG_ERR_INVALID_ARG;
+    const int64_t n_tiles = views_tiles(cams, n_views);
+    if (n_tiles < 0) return FG_ERR_INVALID_ARG;
     int bits = 0;  // 0: the narrowest digit that needs no more passes than 8-bit digits
     if (tune && tune->radix_bits) {
         if (tune->radix_bits < 4 || tune->radix_bits > 8) return FG_ERR_INVALID_ARG;
         bits = tune->radix_bits;
     }
     SortWs w;
-    const size_t need = carve(nullptr, cap_sel, cap_pairs, &w);
+    const size_t need = carve(nullptr, cap_sel * n_views, cap_items, cap_pairs, &w);
     if (!ws || ws_bytes < need) return FG_ERR_WORKSPACE;
-    carve(ws, cap_sel, cap_pairs, &w);
+    carve(ws, cap_sel * n_views, cap_items, cap_pairs, &w);
+    SortViews V;
+    V.n = n_views;
+    V.cap_sel = (uint32_t)cap_sel;
+    for (int v = 0; v < kMaxViews; v++) {
+        V.Wt[v] = v < n_views ? (uint32_t)((cams[v].width + 15) / 16) : 0u;
+        V.tile_base[v] = v < n_views ? cams[v].tile_base : 0u;
+    }
     hipStream_t s = (hipStream_t)stream;
-    const int Wt = (cam->width + 15) / 16, Ht = (cam->height + 15) / 16;
-    const int64_t n_tiles = (int64_t)Wt * Ht;
-    const uint64_t max_tile = (uint64_t)cam->tile_base + (uint64_t)n_tiles - 1;
-    if (max_tile > 0xFFFFFFFFull) return FG_ERR_UNSUPPORTED;
+    const uint64_t max_tile = (uint64_t)cams[0].tile_base + (uint64_t)n_tiles - 1;
 
-    // 1. splats that cover a tile, packed in index order, then their depth
-    //    order (4 passes of 8 bits, result back in buffer 0)
-    int64_t gb = (cap_sel + kTileItems - 1) / kTileItems;
-    const int64_t gclr = (2 * n_tiles + kThreads - 1) / kThreads;
-    int64_t gc = gb > gclr ? gb : gclr;
-    if (gc > 4096) gc = 4096;
-    if (gc < 1) gc = 1;
-    if (gb > 4096) gb = 4096;
-    if (gb < 1) gb = 1;
-    hipLaunchKernelGGL(k_vis_count, dim3((unsigned)gc), dim3(kThreads), 0, s, splats->tiles, n_sel, cap_sel, w.vcnt,
-                       ranges, n_tiles);
-    hipLaunchKernelGGL(k_vis_pack, dim3((unsigned)gb), dim3(kThreads), 0, s, (const float4*)splats->rgb_depth,
-                       splats->tiles, n_sel, cap_sel, w.vcnt, w.dkey0, w.dval0, w.n_vis);
+    // 1. splats that cover a tile, packed in (view, index) order, then their
+    //    depth order (4 passes of 8 bits, result back in buffer 0)
+    auto grid_for = [](int64_t items, int64_t per) {
+        int64_t g = (items + per - 1) / per;
+        return (unsigned)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+    };
+    const int64_t sel_items = cap_sel * n_views;
+    const unsigned gc = std::max(grid_for(sel_items, kTileItems), grid_for(2 * n_tiles, kThreads));
+    hipLaunchKernelGGL(k_vis_count, dim3(gc), dim3(kThreads), 0, s, splats->tiles, n_sel, V, w.vcnt, w.counts, ranges,
+                       n_tiles);
+    hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(kThreads), 0, s, w.vcnt, w.counts, (int64_t)kTileItems, sel_items,
+                       w.counts + 1, (uint32_t*)nullptr, cap_items, status, FG_STATUS_ITEM_OVERFLOW);
+    hipLaunchKernelGGL(k_vis_pack, dim3(grid_for(sel_items, kTileItems)), dim3(kThreads), 0, s,
+                       (const float4*)splats->rgb_depth, splats->tiles, n_sel, V, w.vcnt, cap_items, w.dkey0, w.dval0);
+    uint32_t* n_vis = w.counts + 1;
     for (int p = 0; p < 4; p++) {
         const bool even = (p % 2) == 0;
         radix_pass<8>(even ? w.dkey0 : w.dkey1, even ? w.dval0 : w.dval1, even ? w.dkey1 : w.dkey0,
-                      even ? w.dval1 : w.dval0, w.n_vis, cap_sel, 8 * p, w, s);
+                      even ? w.dval1 : w.dval0, n_vis, cap_items, 8 * p, n_views > 1 && cap_items >= kBigSort, w, s);
     }
     // 2. tile counts in depth order and key emission
-    hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)gb), dim3(kThreads), 0, s, w.dval0,
-                       (const ushort4*)splats->rect, w.n_vis, cap_sel, w.bsum, w.rect_d);
+    const unsigned gv = grid_for(cap_items, kEmitItems);
+    hipLaunchKernelGGL(k_count_reduce, dim3(gv), dim3(kThreads), 0, s, w.dval0, (const ushort4*)splats->rect, n_vis,
+                       cap_items, w.bsum, w.rect_d);
+    hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(kThreads), 0, s, w.bsum, n_vis, (int64_t)kEmitItems, cap_items,
+                       n_pairs, (uint32_t*)nullptr, cap_pairs, status, FG_STATUS_PAIR_OVERFLOW);
     int tile_bits = 1;
     while (tile_bits < 32 && (max_tile >> tile_bits) != 0) ++tile_bits;
     if (bits == 0) {
@@ -597,22 +707,20 @@ extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t c
     // emit into the buffer that the last pass will not write
     uint32_t* ek = cap_pairs == 0 ? nullptr : (passes % 2) ? w.kalt : tile_keys;
     uint32_t* ev = cap_pairs == 0 ? nullptr : (passes % 2) ? w.valt : vals;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)gb), dim3(kThreads), 0, s, w.dval0, w.rect_d, w.n_vis, cap_sel,
-                       w.bsum, cap_pairs, Wt, cam->tile_base, ek, ev, n_pairs, status);
+    hipLaunchKernelGGL(k_emit, dim3(gv), dim3(kThreads), 0, s, w.dval0, w.rect_d, n_vis, cap_items, w.bsum, cap_pairs,
+                       V, ek, ev);
     if (cap_pairs > 0) {
         // 3. stable sort of the pairs by tile id
         uint32_t *ka = ek, *va = ev, *kb = (ek == tile_keys) ? w.kalt : tile_keys, *vb = (ev == vals) ? w.valt : vals;
         for (int p = 0; p < passes; p++) {
-            radix_pass_bits(bits, ka, va, kb, vb, n_pairs, cap_pairs, bits * p, w, s);
+            radix_pass_bits(bits, ka, va, kb, vb, n_pairs, cap_pairs, bits * p, n_views > 1 && cap_pairs >= kBigSort,
+                            w, s);
             uint32_t* t;
             t = ka; ka = kb; kb = t;
             t = va; va = vb; vb = t;
         }
-        int64_t gr = (cap_pairs + 255) / 256;
-        if (gr > 4096) gr = 4096;
-        hipLaunchKernelGGL(k_ranges, dim3((unsigned)gr), dim3(256), 0, s, tile_keys, n_pairs, cap_pairs, cam->tile_base,
-                           n_tiles, ranges);
+        hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap_pairs, 256)), dim3(256), 0, s, tile_keys, n_pairs, cap_pairs,
+                           cams[0].tile_base, n_tiles, ranges);
     }
-    (void)Ht;
     return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
 }

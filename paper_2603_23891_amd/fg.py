@@ -26,6 +26,7 @@ FG_STATUS_SEL_OVERFLOW = 1
 FG_STATUS_PAIR_OVERFLOW = 2
 FG_STATUS_BAD_PARENT = 4
 FG_STATUS_GTC_UNDEFINED = 8
+FG_STATUS_ITEM_OVERFLOW = 16
 
 
 class FgError(RuntimeError):
@@ -89,9 +90,9 @@ def lib():
         L.fg_filter_workspace_size.restype = C.c_size_t
         L.fg_filter_workspace_size.argtypes = [i64, i64, C.c_int32]
         L.fg_filter.restype = i32
-        L.fg_filter.argtypes = [vp, vp, C.c_int32, f32, vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
+        L.fg_filter.argtypes = [vp, vp, C.c_int32, vp, f32, vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
         L.fg_filter_noalloc.restype = i32
-        L.fg_filter_noalloc.argtypes = [vp, vp, C.c_int32, f32, vp, vp, i64, vp, vp, vp]
+        L.fg_filter_noalloc.argtypes = [vp, vp, C.c_int32, vp, f32, vp, vp, i64, vp, vp, vp]
         L.fg_children_workspace_size.restype = C.c_size_t
         L.fg_children_workspace_size.argtypes = [i64]
         L.fg_children.restype = i32
@@ -101,15 +102,15 @@ def lib():
         L.fg_filter_levelwise.restype = i32
         L.fg_filter_levelwise.argtypes = [vp, vp, vp, vp, f32, vp, vp, vp, vp, C.c_size_t, vp, vp]
         L.fg_preprocess.restype = i32
-        L.fg_preprocess.argtypes = [vp, vp, f32, vp, vp, i64, vp, vp, vp]
+        L.fg_preprocess.argtypes = [vp, vp, vp, i64, vp, C.c_int32, vp, f32, vp, vp, vp]
         L.fg_sort_workspace_size.restype = C.c_size_t
-        L.fg_sort_workspace_size.argtypes = [i64, i64, vp]
+        L.fg_sort_workspace_size.argtypes = [i64, C.c_int32, i64, i64]
         L.fg_sort.restype = i32
-        L.fg_sort.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp, vp, C.c_size_t, vp, vp]
+        L.fg_sort.argtypes = [vp, vp, i64, vp, C.c_int32, i64, vp, vp, i64, vp, vp, vp, vp, C.c_size_t, vp, vp]
         L.fg_render.restype = i32
         L.fg_render_workspace_size.restype = C.c_size_t
-        L.fg_render_workspace_size.argtypes = [vp, i64, vp]
-        L.fg_render.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, C.c_size_t, vp, vp]
+        L.fg_render_workspace_size.argtypes = [vp, C.c_int32, i64, vp]
+        L.fg_render.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp, i64, vp, vp, vp, C.c_size_t, vp, vp]
         L.fg_gtc.restype = i32
         L.fg_gtc.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, C.c_int32, vp, vp]
         L.fg_gtc_tau.restype = i32
@@ -144,6 +145,12 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return C.c_void_p(stream.cuda_stream)
+
+
+def camera_array(cams):
+    """A single camera or a sequence of cameras as a ctypes FgCamera array."""
+    cams = list(cams) if isinstance(cams, (list, tuple)) else [cams]
+    return (FgCamera * len(cams))(*[camera_struct(c) for c in cams]), len(cams)
 
 
 def camera_struct(cam) -> FgCamera:
@@ -223,30 +230,29 @@ def fg_filter_workspace_size(n_nodes: int, n_internal_span: int, n_views: int = 
     return int(lib().fg_filter_workspace_size(n_nodes, n_internal_span, n_views))
 
 
-def fg_sort_workspace_size(cap_sel: int, cap_pairs: int, cam) -> int:
-    cs = camera_struct(cam)
-    return int(lib().fg_sort_workspace_size(cap_sel, cap_pairs, _ref(cs)))
+def fg_sort_workspace_size(cap_sel: int, n_views: int, cap_items: int, cap_pairs: int) -> int:
+    return int(lib().fg_sort_workspace_size(cap_sel, n_views, cap_items, cap_pairs))
 
 
 def fg_filter(tree: DeviceTree, cams, tau_R: float, sel_bits, sel_idx, cap_sel: int, n_sel, status, ws,
-              stream=None):
-    """cams: one camera or a sequence of cameras (node-major multi-view filter)."""
-    cams = list(cams) if isinstance(cams, (list, tuple)) else [cams]
+              stream=None, cams_dev=None):
+    """cams: one camera or a sequence of cameras (node-major multi-view filter);
+    cams_dev: None or a device tensor holding the cameras' fg_camera records
+    (their poses are read on the device)."""
+    arr, n = camera_array(cams)
     ts = tree.struct()
-    arr = (FgCamera * len(cams))(*[camera_struct(c) for c in cams])
-    _check(lib().fg_filter(_ref(ts), C.cast(arr, C.c_void_p), len(cams), C.c_float(tau_R), _p(sel_bits),
+    _check(lib().fg_filter(_ref(ts), C.cast(arr, C.c_void_p), n, _p(cams_dev), C.c_float(tau_R), _p(sel_bits),
                            _p(sel_idx), cap_sel, _p(n_sel), _p(status), _p(ws), ws.numel() * ws.element_size(),
                            _stream(stream)), "fg_filter")
 
 
 def fg_filter_noalloc(tree: DeviceTree, cams, tau_R: float, sel_bits, sel_idx, cap_sel: int, n_sel, status,
-                      stream=None):
+                      stream=None, cams_dev=None):
     """fg_filter on the library's fixed per-device scratch array (no workspace argument)."""
-    cams = list(cams) if isinstance(cams, (list, tuple)) else [cams]
+    arr, n = camera_array(cams)
     ts = tree.struct()
-    arr = (FgCamera * len(cams))(*[camera_struct(c) for c in cams])
-    _check(lib().fg_filter_noalloc(_ref(ts), C.cast(arr, C.c_void_p), len(cams), C.c_float(tau_R), _p(sel_bits),
-                                   _p(sel_idx), cap_sel, _p(n_sel), _p(status), _stream(stream)),
+    _check(lib().fg_filter_noalloc(_ref(ts), C.cast(arr, C.c_void_p), n, _p(cams_dev), C.c_float(tau_R),
+                                   _p(sel_bits), _p(sel_idx), cap_sel, _p(n_sel), _p(status), _stream(stream)),
            "fg_filter_noalloc")
 
 
@@ -279,32 +285,39 @@ class TreeChildren:
         self.ws = torch.empty(lib().fg_filter_levelwise_workspace_size(N), dtype=torch.uint8, device=device)
 
 
-def fg_preprocess(tree: DeviceTree, cam, tau: float, sel_idx, n_sel, cap_sel: int, out: Splats, status,
-                  stream=None):
-    ts, cs, ss = tree.struct(), camera_struct(cam), out.struct()
-    _check(lib().fg_preprocess(_ref(ts), _ref(cs), C.c_float(tau), _p(sel_idx), _p(n_sel), cap_sel, _ref(ss),
-                               _p(status), _stream(stream)), "fg_preprocess")
+def fg_preprocess(tree: DeviceTree, cams, tau: float, sel_idx, n_sel, cap_sel: int, out: Splats, status,
+                  stream=None, cams_dev=None):
+    arr, n = camera_array(cams)
+    ts, ss = tree.struct(), out.struct()
+    _check(lib().fg_preprocess(_ref(ts), _p(sel_idx), _p(n_sel), cap_sel, C.cast(arr, C.c_void_p), n, _p(cams_dev),
+                               C.c_float(tau), _ref(ss), _p(status), _stream(stream)), "fg_preprocess")
 
 
-def fg_sort(splats: Splats, n_sel, cap_sel: int, cam, tile_keys, vals, cap_pairs: int, n_pairs, ranges, status, ws,
-            tune: Optional[FgTune] = None, stream=None):
-    ss, cs = splats.struct(), camera_struct(cam)
-    _check(lib().fg_sort(_ref(ss), _p(n_sel), cap_sel, _ref(cs), _p(tile_keys), _p(vals), cap_pairs, _p(n_pairs),
-                         _p(ranges), _p(status), _p(ws), ws.numel() * ws.element_size(),
-                         _ref(tune) if tune is not None else None, _stream(stream)), "fg_sort")
+def fg_sort(splats: Splats, n_sel, cap_sel: int, cams, tile_keys, vals, cap_pairs: int, n_pairs, ranges, status, ws,
+            tune: Optional[FgTune] = None, stream=None, cap_items: Optional[int] = None):
+    """cap_items: bound on the tile-covering splats of all views (default: cap_sel per view)."""
+    arr, n = camera_array(cams)
+    ss = splats.struct()
+    cap_items = cap_sel * n if cap_items is None else cap_items
+    _check(lib().fg_sort(_ref(ss), _p(n_sel), cap_sel, C.cast(arr, C.c_void_p), n, cap_items, _p(tile_keys),
+                         _p(vals), cap_pairs, _p(n_pairs), _p(ranges), _p(status), _p(ws),
+                         ws.numel() * ws.element_size(), _ref(tune) if tune is not None else None, _stream(stream)),
+           "fg_sort")
 
 
-def fg_render_workspace_size(cam, cap_pairs: int, tune: Optional[FgTune] = None) -> int:
-    cs = camera_struct(cam)
-    return int(lib().fg_render_workspace_size(_ref(cs), cap_pairs, _ref(tune) if tune is not None else None))
+def fg_render_workspace_size(cams, cap_pairs: int, tune: Optional[FgTune] = None) -> int:
+    arr, n = camera_array(cams)
+    return int(lib().fg_render_workspace_size(C.cast(arr, C.c_void_p), n, cap_pairs,
+                                              _ref(tune) if tune is not None else None))
 
 
-def fg_render(splats: Splats, vals, ranges, cam, bg: Sequence[float], image, final_T, n_contrib, cap_pairs: int,
+def fg_render(splats: Splats, vals, ranges, cams, bg: Sequence[float], image, final_T, n_contrib, cap_pairs: int,
               frag_stats, status, ws, tune: Optional[FgTune] = None, stream=None):
-    ss, cs = splats.struct(), camera_struct(cam)
+    arr, n = camera_array(cams)
+    ss = splats.struct()
     bgv = (C.c_float * 3)(*[float(b) for b in bg])
-    _check(lib().fg_render(_ref(ss), _p(vals), _p(ranges), _ref(cs), C.cast(bgv, C.c_void_p), _p(image),
-                           _p(final_T), _p(n_contrib), cap_pairs, _p(frag_stats), _p(status), _p(ws),
+    _check(lib().fg_render(_ref(ss), _p(vals), _p(ranges), C.cast(arr, C.c_void_p), n, C.cast(bgv, C.c_void_p),
+                           _p(image), _p(final_T), _p(n_contrib), cap_pairs, _p(frag_stats), _p(status), _p(ws),
                            ws.numel() * ws.element_size(), _ref(tune) if tune is not None else None,
                            _stream(stream)), "fg_render")
 
@@ -351,8 +364,8 @@ class FrameBuffers:
             R = np.eye(3, dtype=np.float32).reshape(9); t = np.zeros(3, np.float32); campos = t
             fx = fy = cx = cy = 1.0; znear = 0.2; kx = ky = 1.0; tile_base = 0
         _C.width, _C.height = width, height
-        self.sort_ws = torch.empty(fg_sort_workspace_size(self.cap_sel, self.cap_pairs, _C), dtype=torch.uint8,
-                                   device=device)
+        self.sort_ws = torch.empty(fg_sort_workspace_size(self.cap_sel, 1, self.cap_sel, self.cap_pairs),
+                                   dtype=torch.uint8, device=device)
         rw = max(fg_render_workspace_size(_C, self.cap_pairs, tune_struct(c, save_state=save_state))
                  for c in (128, 256, 512))
         self.render_ws = torch.empty(rw, dtype=torch.uint8, device=device)

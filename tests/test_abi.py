@@ -69,11 +69,14 @@ def test_workspace_sizes_are_monotone_and_reject_bad_sizes():
     c = fg.fg_filter_workspace_size(100000, 10000, 8)
     assert 0 < a < b < c
     cam = cam_1080p()
-    s1 = fg.fg_sort_workspace_size(1000, 5000, cam)
-    s2 = fg.fg_sort_workspace_size(100000, 500000, cam)
-    assert 0 < s1 < s2
-    assert fg.fg_sort_workspace_size(-1, 5, cam) == 0
+    s1 = fg.fg_sort_workspace_size(1000, 1, 1000, 5000)
+    s2 = fg.fg_sort_workspace_size(100000, 1, 100000, 500000)
+    s3 = fg.fg_sort_workspace_size(100000, 8, 100000, 500000)
+    assert 0 < s1 < s2 < s3
+    assert fg.fg_sort_workspace_size(-1, 1, 5, 5) == 0 and fg.fg_sort_workspace_size(5, 0, 5, 5) == 0
     r = [fg.fg_render_workspace_size(cam, 1 << 20, fg.tune_struct(k)) for k in (128, 256, 512)]
+    assert fg.fg_render_workspace_size([cam_1080p(0), cam_1080p(8160)], 1 << 20) > r[1]
+    assert fg.fg_render_workspace_size([cam_1080p(0), cam_1080p(5)], 1 << 20) == 0  # tile ids not consecutive
     assert all(x > 0 for x in r)
     assert fg.fg_render_workspace_size(cam, -1) == 0
     assert fg.lib().fg_render_backward_workspace_size(1000) >= 1000 * 9 * 4
@@ -82,13 +85,15 @@ def test_workspace_sizes_are_monotone_and_reject_bad_sizes():
 def test_entry_points_reject_missing_arguments_on_the_host(lib):
     cam = fg.camera_struct(cam_1080p())
     # null inputs are refused before any device work
-    assert lib.fg_filter(None, None, 1, C.c_float(3.0), None, None, 0, None, None, None, 0, None) == FG_ERR_INVALID_ARG
-    assert lib.fg_preprocess(None, C.byref(cam), C.c_float(0.0), None, None, 0, None, None, None) == FG_ERR_INVALID_ARG
-    assert lib.fg_sort(None, None, 0, C.byref(cam), None, None, 0, None, None, None, None, 0, None,
+    assert lib.fg_filter(None, None, 1, None, C.c_float(3.0), None, None, 0, None, None, None, 0,
+                         None) == FG_ERR_INVALID_ARG
+    assert lib.fg_preprocess(None, None, None, 0, C.byref(cam), 1, None, C.c_float(0.0), None, None,
+                             None) == FG_ERR_INVALID_ARG
+    assert lib.fg_sort(None, None, 0, C.byref(cam), 1, 0, None, None, 0, None, None, None, None, 0, None,
                        None) == FG_ERR_INVALID_ARG
     bg = (C.c_float * 3)(0.0, 0.0, 0.0)
-    assert lib.fg_render(None, None, None, C.byref(cam), C.cast(bg, C.c_void_p), None, None, None, 0, None, None,
-                         None, 0, None, None) == FG_ERR_INVALID_ARG
+    assert lib.fg_render(None, None, None, C.byref(cam), 1, C.cast(bg, C.c_void_p), None, None, None, 0, None,
+                         None, None, 0, None, None) == FG_ERR_INVALID_ARG
 
 
 def test_tune_struct_layout():
@@ -108,7 +113,7 @@ def test_filter_rejects_inconsistent_trees_on_the_host(lib):
     def call(n_nodes, span, max_depth):
         t = fg.FgTree(n_nodes=n_nodes, n_internal_span=span, sh_degree=0, max_depth=max_depth, mean=fake,
                       scale=fake, quat=fake, opacity=fake, sh=fake, parent=fake, flags=fake)
-        return lib.fg_filter(C.byref(t), C.cast(cam, C.c_void_p), 1, C.c_float(3.0), C.c_void_p(fake),
+        return lib.fg_filter(C.byref(t), C.cast(cam, C.c_void_p), 1, None, C.c_float(3.0), C.c_void_p(fake),
                              C.c_void_p(fake), 16, C.c_void_p(fake), C.c_void_p(fake), C.c_void_p(fake), 1 << 30,
                              None)
 
@@ -132,8 +137,9 @@ def test_filter_noalloc_rejects_problems_beyond_its_scratch_on_the_host(lib):
     def call(n_nodes, span):
         t = fg.FgTree(n_nodes=n_nodes, n_internal_span=span, sh_degree=0, max_depth=8, mean=fake, scale=fake,
                       quat=fake, opacity=fake, sh=fake, parent=fake, flags=fake)
-        return lib.fg_filter_noalloc(C.byref(t), C.cast(cam, C.c_void_p), 1, C.c_float(3.0), C.c_void_p(fake),
-                                     C.c_void_p(fake), 16, C.c_void_p(fake), C.c_void_p(fake), None)
+        return lib.fg_filter_noalloc(C.byref(t), C.cast(cam, C.c_void_p), 1, None, C.c_float(3.0),
+                                     C.c_void_p(fake), C.c_void_p(fake), 16, C.c_void_p(fake), C.c_void_p(fake),
+                                     None)
 
     FG_ERR_SCRATCH, FG_ERR_INVALID_TREE = -6, -2
     limit = 16 << 20
@@ -141,5 +147,6 @@ def test_filter_noalloc_rejects_problems_beyond_its_scratch_on_the_host(lib):
     assert fg.fg_filter_workspace_size(big, big, 1) > limit
     assert call(big, big) == FG_ERR_SCRATCH
     assert call(100, 101) == FG_ERR_INVALID_TREE
-    assert lib.fg_filter_noalloc(None, None, 1, C.c_float(3.0), None, None, 0, None, None, None) == FG_ERR_INVALID_ARG
+    assert lib.fg_filter_noalloc(None, None, 1, None, C.c_float(3.0), None, None, 0, None, None,
+                                 None) == FG_ERR_INVALID_ARG
     assert b"fixed scratch" in lib.fg_status_string(FG_ERR_SCRATCH)

@@ -77,13 +77,20 @@ def test_multiview_filter(dtree, n_views):
 
 
 def read_view(br, v):
-    vb = br.views[v]
+    """View v's part of the batch's outputs, in the oracle's per-view terms:
+    its contiguous run of the sorted pair list (global tile ids kept), splat
+    indices and ranges relative to the view."""
     u32 = lambda t: t.cpu().numpy().view(np.uint32)
     ns = int(u32(br.n_sel)[v])
-    npairs = int(u32(vb.n_pairs)[0])
-    return dict(sel_idx=u32(br.sel_idx)[v * br.cap_sel: v * br.cap_sel + ns], n_pairs=npairs,
-                tile_keys=u32(vb.tile_keys)[:npairs], vals=u32(vb.vals)[:npairs], ranges=u32(vb.ranges).reshape(-1, 2),
-                image=vb.image.cpu().numpy(), final_T=vb.final_T.cpu().numpy(), n_contrib=u32(vb.n_contrib))
+    r = u32(br.view_ranges(v)).astype(np.int64).reshape(-1, 2)
+    nz = r[:, 1] > r[:, 0]
+    lo = int(r[nz, 0].min()) if nz.any() else 0
+    hi = int(r[nz, 1].max()) if nz.any() else 0
+    rel = np.where(nz[:, None], r - lo, 0).astype(np.uint32)
+    return dict(sel_idx=u32(br.sel_idx)[v * br.cap_sel: v * br.cap_sel + ns], n_pairs=hi - lo,
+                tile_keys=u32(br.tile_keys)[lo:hi], vals=u32(br.vals)[lo:hi] - np.uint32(v * br.cap_sel),
+                ranges=rel, image=br.view_image(v).cpu().numpy(), final_T=br.view_final_T(v).cpu().numpy(),
+                n_contrib=u32(br.view_n_contrib(v)))
 
 
 def check_view(g, o):
@@ -100,18 +107,15 @@ def check_view(g, o):
 def snapshot(br):
     """Every output a batch defines: images, contributor counts, the sorted
     values up to n_pairs (the rest of the buffer is never written), ranges."""
-    out = []
-    for vb in br.views:
-        n = int(vb.n_pairs.item())
-        out.append(torch.cat([vb.image.reshape(-1).view(torch.int32), vb.n_contrib.reshape(-1), vb.vals[:n],
-                              vb.ranges.reshape(-1), vb.n_pairs]).clone())
-    return out + [br.n_sel.clone()]
+    n = int(br.n_pairs.item())
+    return [br.image.view(torch.int32).clone(), br.n_contrib.clone(), br.vals[:n].clone(), br.ranges.clone(),
+            br.n_pairs.clone(), br.n_sel.clone()]
 
 
 def test_batched_renderer_parity_and_graph(dtree):
     cams = views(6)
     tau_R, tau, bg = 3.0, 0.01, (0.1, 0.2, 0.3)
-    br = batch.BatchedRenderer(dtree, cams, cap_sel=TREE.n_nodes, cap_pairs=1 << 21)
+    br = batch.BatchedRenderer(dtree, cams, cap_sel=TREE.n_nodes, cap_pairs=1 << 22)
     br.run(tau_R, tau, bg)
     torch.cuda.synchronize()
     ns, npairs, status = br.counts()
@@ -123,11 +127,10 @@ def test_batched_renderer_parity_and_graph(dtree):
     br.capture(tau_R, tau, bg)
     other = torch.randn(1 << 20, device="cuda")
     for r in range(3):
-        for vb in br.views:
-            vb.image.zero_()
-            vb.n_contrib.zero_()
-            vb.vals.zero_()
-            vb.ranges.zero_()
+        br.image.zero_()
+        br.n_contrib.zero_()
+        br.vals.zero_()
+        br.ranges.zero_()
         br.n_sel.zero_()
         torch.cuda.synchronize()
         br.replay()
@@ -139,9 +142,66 @@ def test_batched_renderer_parity_and_graph(dtree):
     assert int(br.status.item()) == 0
 
 
+def moved(cams, seed):
+    """The same views (intrinsics, sizes, tile ids) at new seeded poses."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in cams:
+        yaw = np.pi / 2 + rng.uniform(-0.5, 0.5)
+        pitch = np.radians(rng.uniform(-35, -10))
+        pos = (rng.uniform(-10, 10), -rng.uniform(30, 60), rng.uniform(5, 20))
+        out.append(synth.make_camera(synth.yaw_pitch_rotation(yaw, pitch), pos, c.width, c.height,
+                                     tile_base=c.tile_base))
+    return out
+
+
+def test_graph_replays_new_poses_from_the_device_camera_array(dtree):
+    """A batch captured once replays with poses written into its device camera
+    array between replays (with eager work in between); every replay equals
+    the oracle's frames at the new poses, and returning to earlier poses gives
+    the earlier outputs bit for bit."""
+    cams = views(5, seed=21)
+    tau_R, tau = 3.0, 0.02
+    br = batch.BatchedRenderer(dtree, cams, cap_sel=TREE.n_nodes, cap_pairs=1 << 22)
+    br.capture(tau_R, tau)
+    first = None
+    other = torch.randn(1 << 18, device="cuda")
+    for step, seed in enumerate((101, 202, 303, None)):
+        poses = cams if seed is None else moved(cams, seed)
+        br.set_poses(poses)
+        br.replay()
+        other = other * 0.5 + 1.0
+        torch.cuda.synchronize()
+        assert int(br.status.item()) == 0
+        if step == 0:
+            first = snapshot(br)
+        for v, cam in enumerate(poses):
+            check_view(read_view(br, v), oracle.render_frame(TREE, cam, tau_R, tau))
+    br.set_poses(moved(cams, 101))
+    br.replay()
+    torch.cuda.synchronize()
+    for a, b in zip(snapshot(br), first):
+        assert torch.equal(a, b)
+
+
+def test_device_poses_drive_filter_and_projection(dtree):
+    """fg_filter and fg_preprocess take the pose from the device camera array,
+    not from the host cameras (which then only give sizes and intrinsics)."""
+    cams = views(3, seed=5)
+    real = moved(cams, 7)
+    br = batch.BatchedRenderer(dtree, cams, cap_sel=TREE.n_nodes, cap_pairs=1 << 22)
+    br.set_poses(real)
+    br.run(3.0, 0.0)
+    torch.cuda.synchronize()
+    for v, cam in enumerate(real):
+        check_view(read_view(br, v), oracle.render_frame(TREE, cam, 3.0, 0.0))
+    with pytest.raises(ValueError):
+        br.set_poses([synth.make_camera(np.eye(3), (0, 0, 0), 17, 9)] * 3)
+
+
 def test_autotune_identical_outputs_and_cache(dtree, tmp_path):
     cams = views(3, seed=11)
-    br = batch.BatchedRenderer(dtree, cams, cap_sel=TREE.n_nodes, cap_pairs=1 << 21)
+    br = batch.BatchedRenderer(dtree, cams, cap_sel=TREE.n_nodes, cap_pairs=1 << 22)
     path = str(tmp_path / "tune.json")
     res = batch.autotune(br, 3.0, 0.0, chunks=(128, 256, 512), radix_bits=(4, 6, 8), repeats=1,
                          cache_path=path, cache_key="block40k")
