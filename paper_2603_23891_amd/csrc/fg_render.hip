@@ -55,6 +55,7 @@ struct RenderWs {
     uint32_t* counters;   // [0] ticket, [1] heavy tiles, [2] mask items (clamped), [3] tiles with splats
     uint32_t* masks;      // [max_mask_items][CHUNK/32][256]
     float* state;         // with save_state: [max_mask_items][4][256] T, C0, C1, C2 after each chunk; else null
+    uint32_t* sched;      // [3][tile blocks] block totals of the many-tile schedule
 };
 
 struct Frag {
@@ -228,6 +229,147 @@ __global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __res
         counters[1] = (uint32_t)s_carry;
         counters[2] = (int64_t)items < max_mask_items ? items : (uint32_t)max_mask_items;
         counters[3] = (uint32_t)s_carry + (uint32_t)(s_carry >> 32);
+    }
+}
+
+// The same schedule for many tiles (a batch of views), in three launches:
+// per block of 8192 tiles the chunk counts and the block's totals (heavy
+// tiles, light tiles, mask items); one workgroup scans the block totals; each
+// block then writes its part of order[] and mfirst[] from its base. Results
+// equal k_schedule's.
+constexpr int kSchedTiles = 8 * kScanThreads;
+
+template <int CHUNK>
+__global__ __launch_bounds__(kScanThreads) void k_sched_count(const uint32_t* __restrict__ ranges, int64_t n_tiles,
+                                                              uint32_t* __restrict__ nch,
+                                                              uint32_t* __restrict__ bsum)
+{
+    __shared__ uint32_t s_h[kScanThreads / fgd::kWave], s_l[kScanThreads / fgd::kWave],
+        s_m[kScanThreads / fgd::kWave];
+    const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
+    const int64_t base = (int64_t)blockIdx.x * kSchedTiles;
+    uint32_t h = 0, l = 0, m = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const int64_t t = base + (int64_t)tid * 8 + k;
+        const uint32_t c = t < n_tiles ? (ranges[2 * t + 1] - ranges[2 * t] + CHUNK - 1) / CHUNK : 0u;
+        if (t < n_tiles) nch[t] = c;
+        if (c > 1) {
+            h += 1u;
+            m += c;
+        } else if (c == 1) {
+            l += 1u;
+        }
+    }
+#pragma unroll
+    for (int d = fgd::kWave / 2; d > 0; d >>= 1) {
+        h += __shfl_xor(h, d, fgd::kWave);
+        l += __shfl_xor(l, d, fgd::kWave);
+        m += __shfl_xor(m, d, fgd::kWave);
+    }
+    if (lane == 0) {
+        s_h[wave] = h;
+        s_l[wave] = l;
+        s_m[wave] = m;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t th = 0, tl = 0, tm = 0;
+        for (int w = 0; w < kScanThreads / fgd::kWave; w++) {
+            th += s_h[w];
+            tl += s_l[w];
+            tm += s_m[w];
+        }
+        bsum[3 * blockIdx.x] = th;
+        bsum[3 * blockIdx.x + 1] = tl;
+        bsum[3 * blockIdx.x + 2] = tm;
+    }
+}
+
+// One thread: exclusive scan of the blocks' totals in place, and the counters.
+__global__ void k_sched_scan(uint32_t* __restrict__ bsum, int64_t nb, int64_t max_mask_items,
+                             uint32_t* __restrict__ counters)
+{
+    if (threadIdx.x != 0) return;
+    uint32_t h = 0, l = 0, m = 0;
+    for (int64_t b = 0; b < nb; b++) {
+        const uint32_t a0 = bsum[3 * b], a1 = bsum[3 * b + 1], a2 = bsum[3 * b + 2];
+        bsum[3 * b] = h;
+        bsum[3 * b + 1] = l;
+        bsum[3 * b + 2] = m;
+        h += a0;
+        l += a1;
+        m += a2;
+    }
+    counters[0] = 0u;
+    counters[1] = h;
+    counters[2] = (int64_t)m < max_mask_items ? m : (uint32_t)max_mask_items;
+    counters[3] = h + l;
+}
+
+template <int CHUNK>
+__global__ __launch_bounds__(kScanThreads) void k_sched_write(int64_t n_tiles, const uint32_t* __restrict__ nch,
+                                                              const uint32_t* __restrict__ bsum,
+                                                              uint32_t* __restrict__ mfirst,
+                                                              uint32_t* __restrict__ order)
+{
+    __shared__ unsigned long long s_wave[kScanThreads / fgd::kWave];
+    __shared__ uint32_t s_wave_m[kScanThreads / fgd::kWave];
+    const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
+    const int64_t base = (int64_t)blockIdx.x * kSchedTiles;
+    uint32_t c[8];
+    unsigned long long sum = 0;  // low 32: heavy tiles, high 32: light tiles
+    uint32_t msum = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const int64_t t = base + (int64_t)tid * 8 + k;
+        c[k] = t < n_tiles ? nch[t] : 0u;
+        if (c[k] > 1) {
+            sum += 1ull;
+            msum += c[k];
+        } else if (c[k] == 1) {
+            sum += 1ull << 32;
+        }
+    }
+    unsigned long long x = sum;
+    uint32_t xm = msum;
+#pragma unroll
+    for (int d = 1; d < fgd::kWave; d <<= 1) {
+        const unsigned long long y = __shfl_up(x, d, fgd::kWave);
+        const uint32_t ym = __shfl_up(xm, d, fgd::kWave);
+        if (lane >= d) {
+            x += y;
+            xm += ym;
+        }
+    }
+    if (lane == fgd::kWave - 1) {
+        s_wave[wave] = x;
+        s_wave_m[wave] = xm;
+    }
+    __syncthreads();
+    unsigned long long run = (unsigned long long)bsum[3 * blockIdx.x] |
+                             ((unsigned long long)bsum[3 * blockIdx.x + 1] << 32);
+    uint32_t mf = bsum[3 * blockIdx.x + 2];
+    for (int w = 0; w < wave; w++) {
+        run += s_wave[w];
+        mf += s_wave_m[w];
+    }
+    run += x - sum;
+    mf += xm - msum;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const int64_t t = base + (int64_t)tid * 8 + k;
+        if (t < n_tiles && c[k] > 0) {
+            if (c[k] > 1) {
+                order[(uint32_t)run] = (uint32_t)t;
+                mfirst[t] = mf;
+                run += 1ull;
+                mf += c[k];
+            } else {
+                order[n_tiles - 1 - (int64_t)(run >> 32)] = (uint32_t)t;
+                run += 1ull << 32;
+            }
+        }
     }
 }
 
@@ -817,13 +959,14 @@ size_t carve(void* base, int64_t n_tiles, int64_t cap_pairs, int chunk, bool sav
     if (mask_items > 0 && mask_items < cap) cap = mask_items;
     *max_mask_items = need < cap ? need : cap;
     const size_t state_bytes = save_state ? (size_t)*max_mask_items * 4 * kThreads * 4 : 0;
-    const size_t sizes[7] = {(size_t)n_tiles * 4, (size_t)n_tiles * 4, (size_t)n_tiles * 4,
+    const size_t sched_bytes = (size_t)3 * 4 * (size_t)((n_tiles + kSchedTiles - 1) / kSchedTiles + 1);
+    const size_t sizes[8] = {(size_t)n_tiles * 4, (size_t)n_tiles * 4, (size_t)n_tiles * 4,
                              (size_t)*max_mask_items * 4, 64, (size_t)*max_mask_items * (size_t)mask_bytes,
-                             state_bytes};
-    void** dst[7] = {(void**)&w->nch, (void**)&w->mfirst, (void**)&w->order, (void**)&w->mitem,
-                     (void**)&w->counters, (void**)&w->masks, (void**)&w->state};
+                             state_bytes, sched_bytes};
+    void** dst[8] = {(void**)&w->nch, (void**)&w->mfirst, (void**)&w->order, (void**)&w->mitem,
+                     (void**)&w->counters, (void**)&w->masks, (void**)&w->state, (void**)&w->sched};
     size_t off = 0;
-    for (int i = 0; i < 7; i++) {
+    for (int i = 0; i < 8; i++) {
         if (base) *dst[i] = (char*)base + off;
         off += align_up(sizes[i] + 4);
     }
@@ -840,8 +983,17 @@ void launch(const fg_splats* splats, const uint32_t* vals, const uint32_t* range
             const float bg[3], float* image, float* final_T, uint32_t* n_contrib, unsigned long long* frag_stats,
             const RenderWs& w, int64_t n_tiles, int64_t max_mask_items, const fg_tune* tune, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_schedule<CHUNK>, dim3(1), dim3(kScanThreads), 0, s, ranges, n_tiles, max_mask_items, w.nch,
-                       w.mfirst, w.order, w.counters);
+    if (n_tiles <= 4 * kSchedTiles) {
+        hipLaunchKernelGGL(k_schedule<CHUNK>, dim3(1), dim3(kScanThreads), 0, s, ranges, n_tiles, max_mask_items,
+                           w.nch, w.mfirst, w.order, w.counters);
+    } else {
+        const int64_t nb = (n_tiles + kSchedTiles - 1) / kSchedTiles;
+        hipLaunchKernelGGL(k_sched_count<CHUNK>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ranges, n_tiles, w.nch,
+                           w.sched);
+        hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(64), 0, s, w.sched, nb, max_mask_items, w.counters);
+        hipLaunchKernelGGL(k_sched_write<CHUNK>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, n_tiles, w.nch,
+                           w.sched, w.mfirst, w.order);
+    }
     const unsigned gp = (unsigned)(n_tiles < 65536 ? n_tiles : 65536);
     hipLaunchKernelGGL(k_tile_prep<CHUNK>, dim3(gp), dim3(kThreads), 0, s, n_tiles, V, bg[0], bg[1], bg[2], w.nch,
                        w.mfirst, max_mask_items, w.mitem, image, final_T, n_contrib);

@@ -213,3 +213,17 @@ def test_autotune_identical_outputs_and_cache(dtree, tmp_path):
     br.run(3.0, 0.0)
     torch.cuda.synchronize()
     check_view(read_view(br, 1), oracle.render_frame(TREE, cams[1], 3.0, 0.0))
+
+
+def test_many_tile_batch_schedule(dtree):
+    """More than 32768 tiles in one batch (three 2160p views): the blend's
+    schedule runs as per-block counts, a scan and per-block writes; every view
+    still equals the oracle."""
+    cams = views(3, sizes=((3840, 2160),), seed=31)
+    assert sum(c.n_tiles for c in cams) > 4 * 8192
+    br = batch.BatchedRenderer(dtree, cams, cap_sel=TREE.n_nodes, cap_pairs=1 << 23)
+    br.run(3.0, 0.01)
+    torch.cuda.synchronize()
+    assert br.counts()[2] == 0
+    for v, cam in enumerate(cams):
+        check_view(read_view(br, v), oracle.render_frame(TREE, cam, 3.0, 0.01))
