@@ -517,6 +517,41 @@ __device__ __forceinline__ void pair_masks(const float2* s_xy, const float4* s_c
     }
 }
 
+// Narrows [a, b], tile-relative columns of one box row, to the pixels whose
+// centre can pass the skip test of Eq. (2). power >= -5.6 is the ellipse
+// A dx^2 + 2 B dx dy + C dy^2 <= 11.2 (dx, dy: splat centre minus pixel
+// centre), so on a row at offset dy the passing pixel centres lie within
+// u + (B dy -+ sqrt(11.2 A - det dy^2)) / A, det = AC - B^2. The interval is
+// taken for the bound 11.2 * 1.01 and widened by a slack: for a conic with
+// B^2 <= 0.98 AC the float test's rounding moves the form by less than 1e-3,
+// far below the 0.11 added, which also covers the rounding of det, the
+// discriminant, the approximate reciprocal and square root here; so no pixel
+// the test keeps is dropped, and each pixel inside is still tested exactly.
+// Nearly degenerate or non-finite conics keep the whole row. a > b on return
+// when no pixel of the row can pass.
+__device__ __forceinline__ void row_span(float2 mm, float4 co, float fy, int tx, int& a, int& b)
+{
+    const float A = co.x, B = co.y, Cq = co.z;
+    if (!(A > 0.0f) || !(B * B <= 0.98f * (A * Cq))) return;
+    const float dy = mm.y - fy;
+    const float det = A * Cq - B * B;
+    const float disc = (11.2f * 1.01f) * A - det * (dy * dy);
+    if (disc < 0.0f) {
+        b = a - 1;
+        return;
+    }
+    const float inv = __builtin_amdgcn_rcpf(A);
+    const float half = __builtin_amdgcn_sqrtf(disc) * inv;
+    const float cen = (mm.x - (float)(tx * fgd::kTile) - 0.5f) + (B * dy) * inv;
+    const float slack = 0.05f + 1e-4f * (fabsf(cen) + half);
+    const float lo = ceilf(cen - half - slack), hi = floorf(cen + half + slack);
+    // clipped in float (a NaN bound keeps the box column) before converting
+    const float fa = fminf(fmaxf(lo, (float)a), (float)(b + 1));
+    const float fb = fmaxf(fminf(hi, (float)b), (float)(a - 1));
+    a = (int)fa;
+    b = (int)fb;
+}
+
 // Splat-parallel pass masks: each thread takes whole staged splats and tests
 // the pixels of its box (pixel_alpha), setting bit j of the pixel's mask word
 // j/32 (s_mask [word][pixel], zero on entry). Suits many small splats; a few
@@ -536,7 +571,9 @@ __device__ __forceinline__ void splat_masks(const float2* s_xy, const float4* s_
         uint32_t* mrow = s_mask + (j >> 5) * kThreads;
         for (int ly = y0; ly <= y1; ly++) {
             const float fy = (float)(ty * fgd::kTile + ly) + 0.5f;
-            for (int lx = x0; lx <= x1; lx++) {
+            int a = x0, b = x1;
+            row_span(mm, co, fy, tx, a, b);
+            for (int lx = a; lx <= b; lx++) {
                 float alpha;
                 if (pixel_alpha<STATS>(mm, co, (float)(tx * fgd::kTile + lx) + 0.5f, fy, alpha, f))
                     atomicOr(&mrow[ly * fgd::kTile + lx], bit);
@@ -779,7 +816,9 @@ __device__ __forceinline__ void wave_masks(const float2* w_xy, const float4* w_c
         uint32_t* mrow = w_mask + (j >> 5) * fgd::kWave;
         for (int ly = ya; ly <= yb; ly++) {
             const float fy = (float)(ty * fgd::kTile + ly) + 0.5f;
-            for (int lx = x0; lx <= x1; lx++) {
+            int a = x0, b = x1;
+            row_span(mm, co, fy, tx, a, b);
+            for (int lx = a; lx <= b; lx++) {
                 float alpha;
                 if (pixel_alpha<STATS>(mm, co, (float)(tx * fgd::kTile + lx) + 0.5f, fy, alpha, f))
                     atomicOr(&mrow[(ly - y0) * fgd::kTile + lx], bit);
