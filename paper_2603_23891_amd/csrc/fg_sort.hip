@@ -26,9 +26,10 @@
 //               consecutive lanes write consecutive addresses.
 //
 // Block offsets of the packing and emission steps are exclusive sums over
-// the per-block counts of all earlier blocks, which every block adds up
-// itself (a few thousand L2-resident words), so no separate scan launch sits
-// between counting and writing.
+// the per-block counts of all earlier blocks. Up to 8192 blocks every block
+// adds them up itself (a few thousand L2-resident words), so no scan launch
+// sits between counting and writing; larger batches scan the counts in one
+// workgroup first.
 #include "fg_device.h"
 
 #include <algorithm>
@@ -72,6 +73,59 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_wave
     }
     __syncthreads();
     return before + x - v;
+}
+
+// Sum of v[0 .. k) over the workgroup (every thread gets it).
+__device__ __forceinline__ unsigned long long block_prefix(const uint32_t* __restrict__ v, int64_t k,
+                                                           unsigned long long* s_red)
+{
+    unsigned long long x = 0;
+    for (int64_t i0 = threadIdx.x; i0 < k; i0 += 4 * kThreads) {  // 4 independent loads per step
+        uint32_t a[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) a[u] = i0 + u * kThreads < k ? v[i0 + u * kThreads] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; u++) x += a[u];
+    }
+#pragma unroll
+    for (int d = fgd::kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, fgd::kWave);
+    if (fgd::lane_id() == 0) s_red[threadIdx.x / fgd::kWave] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) t += s_red[w];
+    __syncthreads();
+    return t;
+}
+
+// Block offsets of the packing and emission kernels: either read from counts
+// that k_block_scan turned into exclusive offsets, or, when the blocks are few
+// enough (kInlineBlocks), summed by every block from the raw counts of the
+// blocks before it (L2-resident words), which saves the scan launch; then
+// block 0 also stores the total and flags an overflow of cap.
+struct BlockOffsets {
+    const uint32_t* cnt;
+    bool inline_sum;
+    uint32_t* total;
+    int64_t cap;
+    uint32_t* status;
+    uint32_t overflow_bit;
+};
+
+__device__ __forceinline__ unsigned long long block_offset(const BlockOffsets& o, int64_t blk,
+                                                           unsigned long long* s_red)
+{
+    return o.inline_sum ? block_prefix(o.cnt, blk, s_red) : (unsigned long long)o.cnt[blk];
+}
+
+__device__ __forceinline__ void block_total(const BlockOffsets& o, int64_t nblk, unsigned long long* s_red)
+{
+    if (!o.inline_sum || blockIdx.x != 0) return;
+    const unsigned long long t = block_prefix(o.cnt, nblk, s_red);
+    if (threadIdx.x == 0) {
+        *o.total = (uint32_t)(t < 0xFFFFFFFFull ? t : 0xFFFFFFFFull);
+        if ((long long)t > o.cap) atomicOr(o.status, o.overflow_bit);
+    }
 }
 
 template <int BITS>
@@ -367,10 +421,11 @@ __global__ __launch_bounds__(kThreads) void k_vis_count(const uint32_t* __restri
 __global__ __launch_bounds__(kThreads) void k_vis_pack(const float4* __restrict__ rgb_depth,
                                                        const uint32_t* __restrict__ tiles,
                                                        const uint32_t* __restrict__ n_sel, SortViews V,
-                                                       const uint32_t* __restrict__ voff, int64_t cap_items,
+                                                       BlockOffsets voff, int64_t cap_items,
                                                        uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval)
 {
     __shared__ uint32_t s_wave[kWaves];
+    __shared__ unsigned long long s_red[kWaves];
     __shared__ uint32_t s_seg[kMaxViews + 1];
     __shared__ uint32_t s_k[kTileItems];
     __shared__ uint32_t s_v[kTileItems];
@@ -378,7 +433,7 @@ __global__ __launch_bounds__(kThreads) void k_vis_pack(const float4* __restrict_
     const int64_t n = s_seg[V.n];
     const int64_t nblk = (n + kTileItems - 1) / kTileItems;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const uint32_t base = voff[blk];
+        const unsigned long long base = block_offset(voff, blk, s_red);
         const int64_t j0 = blk * kTileItems + (int64_t)threadIdx.x * kIPT;
         uint32_t c = 0;
         bool vis[kIPT];
@@ -401,12 +456,13 @@ __global__ __launch_bounds__(kThreads) void k_vis_pack(const float4* __restrict_
         }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < total; i += kThreads)
-            if ((int64_t)base + i < cap_items) {
+            if ((long long)(base + i) < cap_items) {
                 dkey[base + i] = s_k[i];
                 dval[base + i] = s_v[i];
             }
         __syncthreads();
     }
+    block_total(voff, nblk, s_red);
 }
 
 // Per 1024 splats in depth order: the sum of their tile counts (the areas of
@@ -445,11 +501,12 @@ __global__ __launch_bounds__(kThreads) void k_count_reduce(const uint32_t* __res
 // the tile, numbered in its view's global tile ids.
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order,
                                                    const ushort4* __restrict__ rect_d, const uint32_t* __restrict__ n_p,
-                                                   int64_t cap, const uint32_t* __restrict__ boff, int64_t cap_pairs,
+                                                   int64_t cap, BlockOffsets boff, int64_t cap_pairs,
                                                    SortViews V, uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals)
 {
     __shared__ uint32_t s_wave[kWaves];
+    __shared__ unsigned long long s_red[kWaves];
     __shared__ uint32_t s_off[kEmitItems + 1];
     __shared__ uint32_t s_g[kEmitItems];
     __shared__ ushort4 s_rect[kEmitItems];
@@ -457,7 +514,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
     const int64_t nblk = (n + kEmitItems - 1) / kEmitItems;
     const int tid = threadIdx.x;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const unsigned long long base = boff[blk];
+        const unsigned long long base = block_offset(boff, blk, s_red);
         const int64_t j0 = blk * kEmitItems + (int64_t)tid * kEmitIPT;
         uint32_t c[kEmitIPT];
         uint32_t sum = 0;
@@ -519,6 +576,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
         }
         __syncthreads();
     }
+    block_total(boff, nblk, s_red);
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_p, int64_t cap,
@@ -576,6 +634,10 @@ size_t carve(void* base, int64_t sel_items, int64_t cap_items, int64_t cap_pairs
 // otherwise average four items (16-byte writes into 128-byte lines). Chosen
 // from the call's shape on the host (the counts stay on the device).
 constexpr int64_t kBigSort = (int64_t)4 << 20;
+
+// Block counts up to which the packing and emission kernels sum their block
+// offsets themselves (see BlockOffsets): up to 8M items at 1024 per block.
+constexpr int64_t kInlineBlocks = 8192;
 
 template <int BITS, int IPT>
 void radix_pass_ipt(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint32_t* n_p,
@@ -680,10 +742,13 @@ extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t c
     const unsigned gc = std::max(grid_for(sel_items, kTileItems), grid_for(2 * n_tiles, kThreads));
     hipLaunchKernelGGL(k_vis_count, dim3(gc), dim3(kThreads), 0, s, splats->tiles, n_sel, V, w.vcnt, w.counts, ranges,
                        n_tiles);
-    hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(kThreads), 0, s, w.vcnt, w.counts, (int64_t)kTileItems, sel_items,
-                       w.counts + 1, (uint32_t*)nullptr, cap_items, status, FG_STATUS_ITEM_OVERFLOW);
+    const BlockOffsets voff{w.vcnt, tiles_for(sel_items) <= kInlineBlocks, w.counts + 1, cap_items, status,
+                            FG_STATUS_ITEM_OVERFLOW};
+    if (!voff.inline_sum)
+        hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(kThreads), 0, s, w.vcnt, w.counts, (int64_t)kTileItems,
+                           sel_items, w.counts + 1, (uint32_t*)nullptr, cap_items, status, FG_STATUS_ITEM_OVERFLOW);
     hipLaunchKernelGGL(k_vis_pack, dim3(grid_for(sel_items, kTileItems)), dim3(kThreads), 0, s,
-                       (const float4*)splats->rgb_depth, splats->tiles, n_sel, V, w.vcnt, cap_items, w.dkey0, w.dval0);
+                       (const float4*)splats->rgb_depth, splats->tiles, n_sel, V, voff, cap_items, w.dkey0, w.dval0);
     uint32_t* n_vis = w.counts + 1;
     for (int p = 0; p < 4; p++) {
         const bool even = (p % 2) == 0;
@@ -694,8 +759,11 @@ extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t c
     const unsigned gv = grid_for(cap_items, kEmitItems);
     hipLaunchKernelGGL(k_count_reduce, dim3(gv), dim3(kThreads), 0, s, w.dval0, (const ushort4*)splats->rect, n_vis,
                        cap_items, w.bsum, w.rect_d);
-    hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(kThreads), 0, s, w.bsum, n_vis, (int64_t)kEmitItems, cap_items,
-                       n_pairs, (uint32_t*)nullptr, cap_pairs, status, FG_STATUS_PAIR_OVERFLOW);
+    const BlockOffsets boff{w.bsum, (cap_items + kEmitItems - 1) / kEmitItems <= kInlineBlocks, n_pairs, cap_pairs,
+                            status, FG_STATUS_PAIR_OVERFLOW};
+    if (!boff.inline_sum)
+        hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(kThreads), 0, s, w.bsum, n_vis, (int64_t)kEmitItems, cap_items,
+                           n_pairs, (uint32_t*)nullptr, cap_pairs, status, FG_STATUS_PAIR_OVERFLOW);
     int tile_bits = 1;
     while (tile_bits < 32 && (max_tile >> tile_bits) != 0) ++tile_bits;
     if (bits == 0) {
@@ -707,7 +775,7 @@ extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t c
     // emit into the buffer that the last pass will not write
     uint32_t* ek = cap_pairs == 0 ? nullptr : (passes % 2) ? w.kalt : tile_keys;
     uint32_t* ev = cap_pairs == 0 ? nullptr : (passes % 2) ? w.valt : vals;
-    hipLaunchKernelGGL(k_emit, dim3(gv), dim3(kThreads), 0, s, w.dval0, w.rect_d, n_vis, cap_items, w.bsum, cap_pairs,
+    hipLaunchKernelGGL(k_emit, dim3(gv), dim3(kThreads), 0, s, w.dval0, w.rect_d, n_vis, cap_items, boff, cap_pairs,
                        V, ek, ev);
     if (cap_pairs > 0) {
         // 3. stable sort of the pairs by tile id
