@@ -421,12 +421,25 @@ def measure_fwd_bwd(torch):
     torch.cuda.synchronize()
     blended = int(stats[3].item())
     bwd_ms = e[1].elapsed_time(e[2])
+    # the blend backward's own counters on the same frame: its gradient atomic
+    # instructions (one per wave and splat with a blended pixel), the elements
+    # they add, and the fragments it walks
+    bstats = torch.zeros(3, dtype=torch.int64, device="cuda")
+    r.tune.bwd_stats = bstats.data_ptr()
+    r.backward(*dev, views[3], dl)
+    r.tune.bwd_stats = None
+    torch.cuda.synchronize()
+    n_instr, n_elem, n_frag_bwd = (int(x) for x in bstats.cpu().tolist())
     # the projection backward's bytes: 236 B of parameters read and 236 B of
     # gradients written per Gaussian, 36 B of splat gradients read
     out = dict(one_view_ms=float(np.median(one)), batch8_ms_per_view=float(np.mean(batch)),
                forward_ms=e[0].elapsed_time(e[1]), backward_ms=bwd_ms, n_gaussians=2_000_000,
                n_pairs_central_view=n_pairs, blended_fragments_central_view=blended,
                backward_blended_fragments_per_s=blended / (bwd_ms * 1e-3),
+               backward_fragments_walked=n_frag_bwd, backward_atomic_instructions=n_instr,
+               backward_atomic_elements=n_elem,
+               backward_atomic_instructions_per_s=n_instr / (bwd_ms * 1e-3),
+               backward_atomic_elements_per_s=n_elem / (bwd_ms * 1e-3),
                backward_projection_bytes=2_000_000 * (236 + 236 + 36),
                n_rendered_central_view=n_sel,
                workload="2M raw Gaussians (city1m leaf law in view), SH3, 1920x1080, L1 loss vs seeded U[0,1] target")

@@ -157,6 +157,11 @@ typedef struct fg_tune {
     void* blend_events[2]; /* NULL, NULL: none; else two caller-owned hipEvent_t that fg_render
                               records on its stream right before and right after its blend
                               kernel (k_render), for timing that kernel alone */
+    unsigned long long* bwd_stats; /* NULL: none; else 3 device counters that fg_render_backward
+                              adds to (the caller zeroes them): [0] gradient atomic
+                              instructions of the blend's backward (one per wave and splat
+                              with a blended pixel), [1] gradient elements those add,
+                              [2] blended fragments walked */
 } fg_tune;
 
 /* ---- stage 1: traversal-free parallel filter (Sec. 3.2) ---------------- */

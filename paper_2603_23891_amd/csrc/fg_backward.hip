@@ -67,6 +67,7 @@ struct BwdView {
     int64_t max_items;        // chunk items the workspace holds (bounds *n_items)
 };
 
+template <bool STATS>
 __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restrict__ xy,
                                                          const float4* __restrict__ conic_o,
                                                          const float4* __restrict__ rgb_depth,
@@ -77,8 +78,10 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
                                                          const uint32_t* __restrict__ n_contrib,
                                                          const float* __restrict__ image,
                                                          const float* __restrict__ dL_dimage, BwdView view,
-                                                         float* __restrict__ gacc)
+                                                         float* __restrict__ gacc,
+                                                         unsigned long long* __restrict__ stats)
 {
+    unsigned long long n_frag = 0, n_instr = 0, n_elem = 0;  // STATS: this lane's counts
     __shared__ float2 s_xy[kBatch];
     __shared__ float4 s_co[kBatch];
     __shared__ float4 s_rgb[kBatch];
@@ -226,8 +229,26 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
                         mine = lane == k ? v : mine;
                     }
                     if (lane < kNG && mine != 0.0f) atomicAdd(gacc + (size_t)s_g[jj] * kNG + lane, mine);
+                    if (STATS) {
+                        const uint64_t am = __ballot(lane < kNG && mine != 0.0f);
+                        if (lane == 0 && am != 0ull) {
+                            ++n_instr;
+                            n_elem += (unsigned long long)__popcll(am);
+                        }
+                    }
                 }
+                if (STATS) n_frag += hit ? 1u : 0u;
             }
+        }
+    }
+    if (STATS) {
+        const unsigned long long c[3] = {n_instr, n_elem, n_frag};
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            unsigned long long v = c[k];
+#pragma unroll
+            for (int d = fgd::kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, fgd::kWave);
+            if (lane == 0) atomicAdd(&stats[k], v);
         }
     }
 }
@@ -487,10 +508,17 @@ extern "C" int fg_render_backward(const fg_params* p, const fg_camera* cam, cons
         view = {rv.nch, rv.mfirst, rv.mitem, rv.counters, rv.state, rv.chunk, rv.max_items};
     int64_t gb = n_tiles + (view.n_items ? rv.max_items : 0);
     if (gb > 8192) gb = 8192;
-    hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)gb), dim3(kThreads), 0, s, (const float2*)splats->xy,
-                       (const float4*)splats->conic_o, (const float4*)splats->rgb_depth, vals, ranges, cam->width,
-                       cam->height, Wt, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib, image, dL_dimage, view,
-                       gacc);
+    unsigned long long* stats = tune ? tune->bwd_stats : nullptr;
+    if (stats)
+        hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)gb), dim3(kThreads), 0, s, (const float2*)splats->xy,
+                           (const float4*)splats->conic_o, (const float4*)splats->rgb_depth, vals, ranges, cam->width,
+                           cam->height, Wt, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib, image, dL_dimage, view,
+                           gacc, stats);
+    else
+        hipLaunchKernelGGL(k_render_bwd<false>, dim3((unsigned)gb), dim3(kThreads), 0, s, (const float2*)splats->xy,
+                           (const float4*)splats->conic_o, (const float4*)splats->rgb_depth, vals, ranges, cam->width,
+                           cam->height, Wt, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib, image, dL_dimage, view,
+                           gacc, stats);
     const fgd::Cam c = fgd::make_cam(*cam);
     int64_t blocks = (cap_sel + 255) / 256;
     if (blocks > 4096) blocks = 4096;

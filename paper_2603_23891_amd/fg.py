@@ -68,7 +68,7 @@ class FgLevelwiseStats(C.Structure):
 
 class FgTune(C.Structure):
     _fields_ = [("render_batch", C.c_int32), ("radix_bits", C.c_int32), ("save_state", C.c_int32),
-                ("mask_items", C.c_int32), ("blend_events", C.c_void_p * 2)]
+                ("mask_items", C.c_int32), ("blend_events", C.c_void_p * 2), ("bwd_stats", C.c_void_p)]
 
 
 EXPORTS = ["fg_filter_workspace_size", "fg_filter", "fg_filter_noalloc", "fg_children_workspace_size",
@@ -166,14 +166,20 @@ def camera_struct(cam) -> FgCamera:
 
 
 def tune_struct(render_batch: int = 0, radix_bits: int = 0, save_state: bool = False, blend_events=None,
-                mask_items: int = 0) -> FgTune:
+                mask_items: int = 0, bwd_stats: Optional[torch.Tensor] = None) -> FgTune:
     """blend_events: None, or two recorded torch.cuda.Event (timing enabled)
-    that fg_render records around its blend kernel."""
+    that fg_render records around its blend kernel. bwd_stats: None, or an
+    int64 device tensor of at least 3 entries that fg_render_backward adds its
+    counters to (atomic instructions, gradient elements, blended fragments)."""
     t = FgTune(render_batch=render_batch, radix_bits=radix_bits, save_state=1 if save_state else 0,
                mask_items=mask_items)
     if blend_events is not None:
         t.blend_events[0] = blend_events[0].cuda_event
         t.blend_events[1] = blend_events[1].cuda_event
+    if bwd_stats is not None:
+        if bwd_stats.dtype != torch.int64 or bwd_stats.numel() < 3 or not bwd_stats.is_cuda:
+            raise ValueError("bwd_stats: an int64 device tensor of at least 3 entries")
+        t.bwd_stats = bwd_stats.data_ptr()
     return t
 
 

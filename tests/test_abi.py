@@ -97,11 +97,13 @@ def test_entry_points_reject_missing_arguments_on_the_host(lib):
 
 
 def test_tune_struct_layout():
-    """fg_tune as the header lays it out: four int32 then two event handles."""
+    """fg_tune as the header lays it out: four int32, two event handles, then
+    the backward's counter pointer."""
     t = fg.tune_struct(512, 7, True)
-    assert C.sizeof(t) == 16 + 2 * C.sizeof(C.c_void_p)
+    assert C.sizeof(t) == 16 + 3 * C.sizeof(C.c_void_p)
+    assert fg.FgTune.bwd_stats.offset == 16 + 2 * C.sizeof(C.c_void_p)
     assert (t.render_batch, t.radix_bits, t.save_state) == (512, 7, 1)
-    assert t.blend_events[0] is None and t.blend_events[1] is None
+    assert t.blend_events[0] is None and t.blend_events[1] is None and t.bwd_stats is None
 
 
 def test_filter_rejects_inconsistent_trees_on_the_host(lib):

@@ -158,3 +158,30 @@ def test_backward_long_ranges_from_saved_chunk_state(mu, chunk, mask_items):
     assert np.array_equal(img, fwd["image"])
     _, g64 = oracle.replay64(prm, cam, fwd, dL_dimage=w, want_image=False)
     check_grads(g_gpu, g64)
+
+
+def test_backward_counters():
+    """The blend backward's counters (fg_tune.bwd_stats): it walks exactly the
+    fragments the forward blended (the forward's own counter), issues one
+    gradient atomic per wave and splat with a blended pixel (so no more than
+    the fragments) adding 1 to 9 elements each, and its gradients still meet
+    the float64 bar."""
+    prm, cam, rng = make_params(5, m=3000, width=128, height=128)
+    fwd = oracle.forward32(prm, cam, 0.05)
+    w = rng.normal(0, 1, (3, cam.height, cam.width))
+    args = to_dev(prm)
+    r = diff.GaussianRenderer(prm.m, prm.sh_degree, cam.width, cam.height, cap_pairs=1 << 20)
+    r.forward(*args, cam, 0.05)
+    fstats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    fg.render_stage(cam, r.fb, tune=r.tune, frag_stats=fstats)
+    bstats = torch.zeros(3, dtype=torch.int64, device="cuda")
+    r.tune.bwd_stats = bstats.data_ptr()
+    g = r.backward(*args, cam, torch.from_numpy(w.astype(np.float32)).cuda())
+    r.tune.bwd_stats = None
+    torch.cuda.synchronize()
+    n_instr, n_elem, n_frag = (int(x) for x in bstats.cpu().tolist())
+    assert n_frag == int(fstats[3].item()) > 0
+    assert 0 < n_instr <= n_frag
+    assert n_instr <= n_elem <= 9 * n_instr
+    _, g64 = oracle.replay64(prm, cam, fwd, dL_dimage=w, want_image=False)
+    check_grads({k: v.cpu().numpy().astype(np.float64) for k, v in zip(GROUPS, g)}, g64)
