@@ -552,34 +552,38 @@ __device__ __forceinline__ void row_span(float2 mm, float4 co, float fy, int tx,
     b = (int)fb;
 }
 
-// Splat-parallel pass masks: each thread takes whole staged splats and tests
-// the pixels of its box (pixel_alpha), setting bit j of the pixel's mask word
-// j/32 (s_mask [word][pixel], zero on entry). Suits many small splats; a few
-// large ones are better served by pair_masks.
+// Pass masks of one splat (index j of the chunk, box b) on its rows: every
+// pixel of each row's span that passes the skip tests (pixel_alpha) sets bit
+// j of its mask word j/32 (s_mask [word][pixel]).
+template <bool STATS>
+__device__ __forceinline__ void splat_rows(float2 mm, float4 co, uint32_t b, int j, int tx, int ty,
+                                           uint32_t* s_mask, Frag& f)
+{
+    const int x0 = (int)(b & 255u), x1 = (int)((b >> 8) & 255u);
+    const int y0 = (int)((b >> 16) & 255u), y1 = (int)(b >> 24);
+    if (x0 > x1) return;
+    const uint32_t bit = 1u << (j & 31);
+    uint32_t* mrow = s_mask + (j >> 5) * kThreads;
+    for (int ly = y0; ly <= y1; ly++) {
+        const float fy = (float)(ty * fgd::kTile + ly) + 0.5f;
+        int a = x0, e = x1;
+        row_span(mm, co, fy, tx, a, e);
+        for (int lx = a; lx <= e; lx++) {
+            float alpha;
+            if (pixel_alpha<STATS>(mm, co, (float)(tx * fgd::kTile + lx) + 0.5f, fy, alpha, f))
+                atomicOr(&mrow[ly * fgd::kTile + lx], bit);
+        }
+    }
+}
+
+// Splat-parallel pass masks of staged splats: each thread takes whole splats
+// (s_mask zero on entry). Suits many small splats; a few large ones are
+// better served by pair_masks.
 template <bool STATS>
 __device__ __forceinline__ void splat_masks(const float2* s_xy, const float4* s_co, const uint32_t* s_box, int cnt,
                                             int tx, int ty, uint32_t* s_mask, Frag& f)
 {
-    for (int j = threadIdx.x; j < cnt; j += kThreads) {
-        const uint32_t b = s_box[j];
-        const int x0 = (int)(b & 255u), x1 = (int)((b >> 8) & 255u);
-        const int y0 = (int)((b >> 16) & 255u), y1 = (int)(b >> 24);
-        if (x0 > x1) continue;
-        const float2 mm = s_xy[j];
-        const float4 co = s_co[j];
-        const uint32_t bit = 1u << (j & 31);
-        uint32_t* mrow = s_mask + (j >> 5) * kThreads;
-        for (int ly = y0; ly <= y1; ly++) {
-            const float fy = (float)(ty * fgd::kTile + ly) + 0.5f;
-            int a = x0, b = x1;
-            row_span(mm, co, fy, tx, a, b);
-            for (int lx = a; lx <= b; lx++) {
-                float alpha;
-                if (pixel_alpha<STATS>(mm, co, (float)(tx * fgd::kTile + lx) + 0.5f, fy, alpha, f))
-                    atomicOr(&mrow[ly * fgd::kTile + lx], bit);
-            }
-        }
-    }
+    for (int j = threadIdx.x; j < cnt; j += kThreads) splat_rows<STATS>(s_xy[j], s_co[j], s_box[j], j, tx, ty, s_mask, f);
 }
 
 template <bool STATS, int N>
@@ -617,13 +621,13 @@ __global__ __launch_bounds__(kThreads) void k_masks(const float2* __restrict__ x
                                                     RenderWs ws, unsigned long long* __restrict__ frag_stats)
 {
     constexpr int kWords = CHUNK / 32;
-    __shared__ float2 s_xy[CHUNK];
-    __shared__ float4 s_co[CHUNK];
-    __shared__ uint32_t s_box[CHUNK];
     __shared__ uint32_t s_mask[kWords * kThreads];
     Frag f = {0, 0, 0, 0};
     const int tid = threadIdx.x;
     const uint32_t n_items = ws.counters[2];
+#pragma unroll
+    for (int w = 0; w < kWords; w++) s_mask[w * kThreads + tid] = 0u;
+    __syncthreads();
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const uint32_t tile = ws.mitem[item];
         const uint32_t chunk = item - ws.mfirst[tile];
@@ -631,16 +635,21 @@ __global__ __launch_bounds__(kThreads) void k_masks(const float2* __restrict__ x
         const uint32_t start = r0 + chunk * CHUNK;
         const int cnt = (int)(r1 - start < (uint32_t)CHUNK ? r1 - start : (uint32_t)CHUNK);
         const TileGeom tg = tile_geom(V, tile);
-        const int tx = tg.tx, ty = tg.ty;
-#pragma unroll
-        for (int w = 0; w < kWords; w++) s_mask[w * kThreads + tid] = 0u;
-        stage(xy, conic_o, nullptr, vals, start, cnt, tx, ty, tg.W, tg.H, s_xy, s_co, nullptr, s_box);
-        __syncthreads();
-        splat_masks<STATS>(s_xy, s_co, s_box, cnt, tx, ty, s_mask, f);
+        // each thread its own splats of the chunk, straight from the splat
+        // records (no staging: no other thread reads them)
+        for (int j = tid; j < cnt; j += kThreads) {
+            const uint32_t g = vals[start + j];
+            const float2 mm = xy[g];
+            const float4 co = conic_o[g];
+            splat_rows<STATS>(mm, co, fgd::splat_box(mm, co, tg.tx, tg.ty, tg.W, tg.H), j, tg.tx, tg.ty, s_mask, f);
+        }
         __syncthreads();
         uint32_t* out = ws.masks + (size_t)item * (kWords * kThreads);
 #pragma unroll
-        for (int w = 0; w < kWords; w++) out[w * kThreads + tid] = s_mask[w * kThreads + tid];
+        for (int w = 0; w < kWords; w++) {
+            out[w * kThreads + tid] = s_mask[w * kThreads + tid];
+            s_mask[w * kThreads + tid] = 0u;  // this thread's column, for the next item
+        }
         __syncthreads();
     }
     flush_stats<STATS, 3>(f, STATS ? frag_stats + 4 : frag_stats);
