@@ -67,6 +67,62 @@ struct BwdView {
     int64_t max_items;        // chunk items the workspace holds (bounds *n_items)
 };
 
+// Sums over the 64 lanes of the 9 gradient components, by halving: padded to
+// 16, each lane keeps half of its components and adds its partner's half of
+// the same ones, across lane bit 5, then 4 (lane shuffles), 3 and 2 (DPP row
+// and half-row mirrors, which pair lanes that differ in that bit and hold the
+// same set); then the one component left is summed within each quad. Lane l
+// returns the total of component ((l >> 2) & 15), the same in all four lanes
+// of the quad (components 9..15 are zero). 12 shuffles and 5 DPP adds, where
+// nine separate reductions take 54 DPP steps and 9 lane reads.
+__device__ __forceinline__ float grad_reduce_scatter(const float (&g)[kNG])
+{
+    const int lane = fgd::lane_id();
+    float v[16];
+#pragma unroll
+    for (int c = 0; c < 16; c++) v[c] = c < kNG ? g[c] : 0.0f;
+    float w8[8];
+    {
+        const bool hi = (lane & 32) != 0;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const float keep = hi ? v[i + 8] : v[i];
+            const float send = hi ? v[i] : v[i + 8];
+            w8[i] = keep + __shfl_xor(send, 32, fgd::kWave);
+        }
+    }
+    float w4[4];
+    {
+        const bool hi = (lane & 16) != 0;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const float keep = hi ? w8[i + 4] : w8[i];
+            const float send = hi ? w8[i] : w8[i + 4];
+            w4[i] = keep + __shfl_xor(send, 16, fgd::kWave);
+        }
+    }
+    float w2[2];
+    {
+        const bool hi = (lane & 8) != 0;  // row mirror: lane i <-> 15 - i of its row
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            const float keep = hi ? w4[i + 2] : w4[i];
+            const float send = hi ? w4[i] : w4[i + 2];
+            w2[i] = keep + fgd::dpp_mov<0x140>(send);
+        }
+    }
+    float w1;
+    {
+        const bool hi = (lane & 4) != 0;  // half-row mirror: lane i <-> 7 - i of its half row
+        const float keep = hi ? w2[1] : w2[0];
+        const float send = hi ? w2[0] : w2[1];
+        w1 = keep + fgd::dpp_mov<0x141>(send);
+    }
+    w1 = w1 + fgd::dpp_mov<0xB1>(w1);  // quad_perm [1, 0, 3, 2]
+    w1 = w1 + fgd::dpp_mov<0x4E>(w1);  // quad_perm [2, 3, 0, 1]
+    return w1;
+}
+
 template <bool STATS>
 __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restrict__ xy,
                                                          const float4* __restrict__ conic_o,
@@ -221,16 +277,14 @@ __global__ __launch_bounds__(kThreads) void k_render_bwd(const float2* __restric
                     }
                 }
                 if (__ballot(hit)) {
-                    // the 9 wave sums, then one atomic instruction: lane k adds sum k
-                    float mine = 0.0f;
-#pragma unroll
-                    for (int k = 0; k < kNG; k++) {
-                        const float v = fgd::wave_total(gr[k]);
-                        mine = lane == k ? v : mine;
-                    }
-                    if (lane < kNG && mine != 0.0f) atomicAdd(gacc + (size_t)s_g[jj] * kNG + lane, mine);
+                    // the 9 wave sums, then one atomic instruction: the first
+                    // lane of quad k adds sum k
+                    const float tot = grad_reduce_scatter(gr);
+                    const int k = lane >> 2;
+                    const bool adds = (lane & 3) == 0 && k < kNG && tot != 0.0f;
+                    if (adds) atomicAdd(gacc + (size_t)s_g[jj] * kNG + k, tot);
                     if (STATS) {
-                        const uint64_t am = __ballot(lane < kNG && mine != 0.0f);
+                        const uint64_t am = __ballot(adds);
                         if (lane == 0 && am != 0ull) {
                             ++n_instr;
                             n_elem += (unsigned long long)__popcll(am);
