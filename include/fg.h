@@ -288,8 +288,9 @@ size_t fg_sort_workspace_size(int64_t cap_sel, int32_t n_views, int64_t cap_item
  * ranges [n_tiles][2] over the tiles of all views in global id order
  * (entry t is global tile cams[0].tile_base + t): [start, end) in the sorted
  * list, [0, 0) for an empty tile.
- * Method: the splats that cover a tile are packed in (view, index) order and
- * stably radix-sorted by depth; an exclusive prefix scan of their tile counts
+ * Method: the splats that cover a tile are stably radix-sorted by depth (the
+ * first pass reads the selections in (view, index) order and leaves out the
+ * others); an exclusive prefix scan of their tile counts
  * in that order places their pairs (key emission), and a stable radix sort of
  * the pairs by tile id gives the (tile, depth, index) order (LDS-staged LSD
  * passes throughout). cap_items bounds the tile-covering splats of all views

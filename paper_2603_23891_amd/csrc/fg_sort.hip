@@ -3,9 +3,11 @@
 // The required order is ascending (tile id, depth bits, splat index). It is
 // reached with two stable sorts instead of one sort of 64-bit keys:
 //
-//   1. the splats that cover at least one tile are packed in index order
-//      (splats whose shrunk rectangle is empty emit nothing) and radix-sorted
-//      by their 32-bit depth key, so ties keep ascending splat index;
+//   1. the splats that cover at least one tile (splats whose shrunk
+//      rectangle is empty emit nothing) are radix-sorted by their 32-bit
+//      depth key, so ties keep ascending splat index; the first pass reads
+//      the selections in (view, index) order and skips the others, which
+//      packs the tile-covering splats as it sorts;
 //   2. an exclusive prefix scan of their tile counts, taken in that depth
 //      order, gives each splat its output offset, and the splat emits one
 //      (tile id, splat index) pair per tile of its rectangle;
@@ -25,11 +27,11 @@
 //               through LDS in locally sorted order, then written out so that
 //               consecutive lanes write consecutive addresses.
 //
-// Block offsets of the packing and emission steps are exclusive sums over
-// the per-block counts of all earlier blocks. Up to 8192 blocks every block
-// adds them up itself (a few thousand L2-resident words), so no scan launch
-// sits between counting and writing; larger batches scan the counts in one
-// workgroup first.
+// Block offsets of the emission step are exclusive sums over the per-block
+// counts of all earlier blocks. Up to 8192 blocks every block adds them up
+// itself (a few thousand L2-resident words), so no scan launch sits between
+// counting and writing; larger batches scan the counts in one workgroup
+// first.
 #include "fg_device.h"
 
 #include <algorithm>
@@ -98,7 +100,7 @@ __device__ __forceinline__ unsigned long long block_prefix(const uint32_t* __res
     return t;
 }
 
-// Block offsets of the packing and emission kernels: either read from counts
+// Block offsets of the emission kernel: either read from counts
 // that k_block_scan turned into exclusive offsets, or, when the blocks are few
 // enough (kInlineBlocks), summed by every block from the raw counts of the
 // blocks before it (L2-resident words), which saves the scan launch; then
@@ -125,176 +127,6 @@ __device__ __forceinline__ void block_total(const BlockOffsets& o, int64_t nblk,
     if (threadIdx.x == 0) {
         *o.total = (uint32_t)(t < 0xFFFFFFFFull ? t : 0xFFFFFFFFull);
         if ((long long)t > o.cap) atomicOr(o.status, o.overflow_bit);
-    }
-}
-
-template <int BITS>
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
-{
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < BITS; b++) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bb = __ballot(bit);
-        m &= bit ? bb : ~bb;
-    }
-    return m;
-}
-
-template <int BITS, int IPT>
-__global__ __launch_bounds__(kThreads) void k_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_p,
-                                                   int64_t cap, int shift, uint32_t* __restrict__ hist)
-{
-    constexpr int R = 1 << BITS;
-    __shared__ uint32_t h[R];
-    const int64_t n = count_of(n_p, cap);
-    const int64_t n_tiles = (n + (kThreads * IPT) - 1) / (kThreads * IPT);
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        for (int d = threadIdx.x; d < R; d += kThreads) h[d] = 0;
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < IPT; r++) {
-            const int64_t idx = tile * (kThreads * IPT) + r * kThreads + threadIdx.x;
-            const bool valid = idx < n;
-            const uint32_t d = valid ? (keys[idx] >> shift) & (R - 1) : 0u;
-            if (valid) atomicAdd(&h[d], 1u);
-        }
-        __syncthreads();
-        for (int d = threadIdx.x; d < R; d += kThreads) hist[(int64_t)d * n_tiles + tile] = h[d];
-        __syncthreads();
-    }
-}
-
-// One workgroup per digit: exclusive scan of hist[digit][0..n_tiles) in place.
-template <int IPT>
-__global__ __launch_bounds__(kThreads) void k_rowscan(const uint32_t* __restrict__ n_p, int64_t cap,
-                                                      uint32_t* __restrict__ hist, uint32_t* __restrict__ digit_total)
-{
-    __shared__ uint32_t s_wave[kWaves];
-    const int64_t n = count_of(n_p, cap);
-    const int64_t n_tiles = (n + (kThreads * IPT) - 1) / (kThreads * IPT);
-    uint32_t* row = hist + (int64_t)blockIdx.x * n_tiles;
-    const int64_t per = (n_tiles + kThreads - 1) / kThreads;
-    const int64_t lo = threadIdx.x * per;
-    const int64_t hi = lo + per < n_tiles ? lo + per : n_tiles;
-    uint32_t s = 0;
-    for (int64_t i0 = lo; i0 < hi; i0 += 4) {  // 4 independent loads per step
-        uint32_t c[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) c[u] = i0 + u < hi ? row[i0 + u] : 0u;
-#pragma unroll
-        for (int u = 0; u < 4; u++) s += c[u];
-    }
-    uint32_t total;
-    uint32_t run = block_excl_scan(s, s_wave, total);
-    for (int64_t i0 = lo; i0 < hi; i0 += 4) {
-        uint32_t c[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) c[u] = i0 + u < hi ? row[i0 + u] : 0u;
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            if (i0 + u < hi) row[i0 + u] = run;
-            run += c[u];
-        }
-    }
-    if (threadIdx.x == 0) digit_total[blockIdx.x] = total;
-}
-
-template <int BITS, int IPT>
-__global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                      uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                      const uint32_t* __restrict__ n_p, int64_t cap, int shift,
-                                                      const uint32_t* __restrict__ hist,
-                                                      const uint32_t* __restrict__ digit_total)
-{
-    constexpr int R = 1 << BITS;
-    static_assert(R <= kThreads, "one thread per digit");
-    __shared__ uint32_t s_base[R];
-    __shared__ uint32_t s_start[R];
-    // per (round, wave, digit): the group's count, then its exclusive offset
-    // among the tile's items of that digit (at most (kThreads * IPT): fits 16 bits)
-    __shared__ uint16_t s_cnt[IPT][kWaves][R];
-    __shared__ uint32_t s_keys[(kThreads * IPT)];
-    __shared__ uint32_t s_vals[(kThreads * IPT)];
-    __shared__ uint32_t s_wave[kWaves];
-    const int64_t n = count_of(n_p, cap);
-    const int64_t n_tiles = (n + (kThreads * IPT) - 1) / (kThreads * IPT);
-    const int tid = threadIdx.x;
-    const int wave = tid / fgd::kWave;
-    {
-        uint32_t tot;
-        const uint32_t v = tid < R ? digit_total[tid] : 0u;
-        const uint32_t e = block_excl_scan(v, s_wave, tot);
-        if (tid < R) s_base[tid] = e;
-    }
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        uint32_t k[IPT], v[IPT], below[IPT];
-#pragma unroll
-        for (int r = 0; r < IPT; r++) {
-            const int64_t idx = tile * (kThreads * IPT) + r * kThreads + tid;
-            const bool valid = idx < n;
-            k[r] = valid ? kin[idx] : 0xFFFFFFFFu;
-            v[r] = valid ? vin[idx] : 0u;
-        }
-        {
-            uint32_t* c32 = reinterpret_cast<uint32_t*>(&s_cnt[0][0][0]);
-            for (int i = tid; i < IPT * kWaves * R / 2; i += kThreads) c32[i] = 0u;
-        }
-        __syncthreads();
-        // every wave ranks its items of every round among equal digits
-        // (ballot match), with no barrier between rounds
-#pragma unroll
-        for (int r = 0; r < IPT; r++) {
-            const int64_t idx = tile * (kThreads * IPT) + r * kThreads + tid;
-            const bool valid = idx < n;
-            const uint32_t d = (k[r] >> shift) & (R - 1);
-            const uint64_t m = match_digit<BITS>(d, valid);
-            below[r] = (uint32_t)__popcll(m & fgd::lanemask_lt());
-            if (valid && below[r] == 0) s_cnt[r][wave][d] = (uint16_t)__popcll(m);
-        }
-        __syncthreads();
-        // per digit, groups in item order (round-major, then wave)
-        uint32_t run = 0;
-        if (tid < R) {
-#pragma unroll
-            for (int r = 0; r < IPT; r++)
-#pragma unroll
-                for (int w = 0; w < kWaves; w++) {
-                    const uint32_t c = s_cnt[r][w][tid];
-                    s_cnt[r][w][tid] = (uint16_t)run;
-                    run += c;
-                }
-        }
-        {
-            uint32_t tot;
-            const uint32_t e = block_excl_scan(run, s_wave, tot);
-            if (tid < R) s_start[tid] = e;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < IPT; r++) {
-            const int64_t idx = tile * (kThreads * IPT) + r * kThreads + tid;
-            if (idx < n) {
-                const uint32_t d = (k[r] >> shift) & (R - 1);
-                const uint32_t pos = s_start[d] + s_cnt[r][wave][d] + below[r];
-                s_keys[pos] = k[r];
-                s_vals[pos] = v[r];
-            }
-        }
-        __syncthreads();
-        const int64_t cnt = n - tile * (kThreads * IPT) < (kThreads * IPT) ? n - tile * (kThreads * IPT) : (kThreads * IPT);
-#pragma unroll
-        for (int r = 0; r < IPT; r++) {
-            const int p = r * kThreads + tid;
-            if (p < cnt) {
-                const uint32_t key = s_keys[p];
-                const uint32_t d = (key >> shift) & (R - 1);
-                const int64_t g = (int64_t)s_base[d] + hist[(int64_t)d * n_tiles + tile] + (p - s_start[d]);
-                kout[g] = key;
-                vout[g] = s_vals[p];
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -345,6 +177,236 @@ __device__ __forceinline__ uint32_t item_splat(uint32_t i, const uint32_t* s_seg
     return (uint32_t)lo * V.cap_sel + (i - s_seg[lo]);
 }
 
+template <int BITS>
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
+{
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < BITS; b++) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+// Input of the first depth pass: the concatenated selections themselves.
+// Item i is global splat g = item_splat(i); it takes part when its rectangle
+// covers a tile (tiles[g] != 0), with key = the bits of its depth and value
+// g. So the pass also packs the tile-covering splats, in (view, index) order
+// within each digit. The histogram kernel clears the tile ranges and stores
+// the item count; the scatter stores the packed count and flags an overflow
+// of cap_out.
+struct SelInput {
+    const float4* rgb_depth;
+    const uint32_t* tiles;
+    const uint32_t* n_sel;
+    uint32_t* n_items;  // selection items (written by k_hist)
+    uint32_t* n_out;    // packed items (written by k_scatter)
+    int64_t cap_out;
+    uint32_t* status;
+    uint32_t* ranges;
+    int64_t n_range_words;
+};
+
+// Key and value of item idx of a pass (valid: the item takes part).
+template <bool SEL>
+__device__ __forceinline__ void pass_item(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                          const SelInput& si, const SortViews& V, const uint32_t* s_seg,
+                                          int64_t idx, int64_t n, bool want_val, bool& valid, uint32_t& k,
+                                          uint32_t& v)
+{
+    valid = idx < n;
+    k = 0xFFFFFFFFu;
+    v = 0u;
+    if (!valid) return;
+    if constexpr (SEL) {
+        const uint32_t g = item_splat((uint32_t)idx, s_seg, V);
+        valid = si.tiles[g] != 0u;
+        if (valid) {
+            k = __float_as_uint(si.rgb_depth[g].w);
+            v = g;
+        }
+    } else {
+        k = kin[idx];
+        if (want_val) v = vin[idx];
+    }
+}
+
+template <int BITS, int IPT, bool SEL>
+__global__ __launch_bounds__(kThreads) void k_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_p,
+                                                   int64_t cap, int shift, uint32_t* __restrict__ hist, SelInput si,
+                                                   SortViews V)
+{
+    constexpr int R = 1 << BITS;
+    __shared__ uint32_t h[R];
+    __shared__ uint32_t s_seg[SEL ? kMaxViews + 1 : 1];
+    int64_t n;
+    if constexpr (SEL) {
+        for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < si.n_range_words;
+             t += (int64_t)gridDim.x * kThreads)
+            si.ranges[t] = 0u;
+        load_segments(si.n_sel, V, s_seg);
+        n = s_seg[V.n];
+        if (blockIdx.x == 0 && threadIdx.x == 0) *si.n_items = (uint32_t)n;
+    } else {
+        n = count_of(n_p, cap);
+    }
+    const int64_t n_tiles = (n + (kThreads * IPT) - 1) / (kThreads * IPT);
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        for (int d = threadIdx.x; d < R; d += kThreads) h[d] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            const int64_t idx = tile * (kThreads * IPT) + r * kThreads + threadIdx.x;
+            bool valid;
+            uint32_t k, v;
+            pass_item<SEL>(keys, nullptr, si, V, s_seg, idx, n, false, valid, k, v);
+            if (valid) atomicAdd(&h[(k >> shift) & (R - 1)], 1u);
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < R; d += kThreads) hist[(int64_t)d * n_tiles + tile] = h[d];
+        __syncthreads();
+    }
+}
+
+// One workgroup per digit: exclusive scan of hist[digit][0..n_tiles) in place.
+template <int IPT>
+__global__ __launch_bounds__(kThreads) void k_rowscan(const uint32_t* __restrict__ n_p, int64_t cap,
+                                                      uint32_t* __restrict__ hist, uint32_t* __restrict__ digit_total)
+{
+    __shared__ uint32_t s_wave[kWaves];
+    const int64_t n = count_of(n_p, cap);
+    const int64_t n_tiles = (n + (kThreads * IPT) - 1) / (kThreads * IPT);
+    uint32_t* row = hist + (int64_t)blockIdx.x * n_tiles;
+    const int64_t per = (n_tiles + kThreads - 1) / kThreads;
+    const int64_t lo = threadIdx.x * per;
+    const int64_t hi = lo + per < n_tiles ? lo + per : n_tiles;
+    uint32_t s = 0;
+    for (int64_t i0 = lo; i0 < hi; i0 += 4) {  // 4 independent loads per step
+        uint32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) c[u] = i0 + u < hi ? row[i0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; u++) s += c[u];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan(s, s_wave, total);
+    for (int64_t i0 = lo; i0 < hi; i0 += 4) {
+        uint32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) c[u] = i0 + u < hi ? row[i0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (i0 + u < hi) row[i0 + u] = run;
+            run += c[u];
+        }
+    }
+    if (threadIdx.x == 0) digit_total[blockIdx.x] = total;
+}
+
+template <int BITS, int IPT, bool SEL>
+__global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                      uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                      const uint32_t* __restrict__ n_p, int64_t cap, int shift,
+                                                      const uint32_t* __restrict__ hist,
+                                                      const uint32_t* __restrict__ digit_total, SelInput si,
+                                                      SortViews V)
+{
+    constexpr int R = 1 << BITS;
+    static_assert(R <= kThreads, "one thread per digit");
+    __shared__ uint32_t s_base[R];
+    __shared__ uint32_t s_start[R];
+    // per (round, wave, digit): the group's count, then its exclusive offset
+    // among the tile's items of that digit (at most (kThreads * IPT): fits 16 bits)
+    __shared__ uint16_t s_cnt[IPT][kWaves][R];
+    __shared__ uint32_t s_keys[(kThreads * IPT)];
+    __shared__ uint32_t s_vals[(kThreads * IPT)];
+    __shared__ uint32_t s_wave[kWaves];
+    __shared__ uint32_t s_seg[SEL ? kMaxViews + 1 : 1];
+    const int64_t n = count_of(n_p, cap);
+    const int64_t n_tiles = (n + (kThreads * IPT) - 1) / (kThreads * IPT);
+    const int tid = threadIdx.x;
+    const int wave = tid / fgd::kWave;
+    if constexpr (SEL) load_segments(si.n_sel, V, s_seg);
+    {
+        uint32_t tot;
+        const uint32_t v = tid < R ? digit_total[tid] : 0u;
+        const uint32_t e = block_excl_scan(v, s_wave, tot);
+        if (tid < R) s_base[tid] = e;
+        if (SEL && blockIdx.x == 0 && tid == 0) {
+            *si.n_out = tot;
+            if ((int64_t)tot > si.cap_out) atomicOr(si.status, FG_STATUS_ITEM_OVERFLOW);
+        }
+    }
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        uint32_t k[IPT], v[IPT], below[IPT];
+        bool ok[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            const int64_t idx = tile * (kThreads * IPT) + r * kThreads + tid;
+            pass_item<SEL>(kin, vin, si, V, s_seg, idx, n, true, ok[r], k[r], v[r]);
+        }
+        {
+            uint32_t* c32 = reinterpret_cast<uint32_t*>(&s_cnt[0][0][0]);
+            for (int i = tid; i < IPT * kWaves * R / 2; i += kThreads) c32[i] = 0u;
+        }
+        __syncthreads();
+        // every wave ranks its items of every round among equal digits
+        // (ballot match), with no barrier between rounds
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            const uint32_t d = (k[r] >> shift) & (R - 1);
+            const uint64_t m = match_digit<BITS>(d, ok[r]);
+            below[r] = (uint32_t)__popcll(m & fgd::lanemask_lt());
+            if (ok[r] && below[r] == 0) s_cnt[r][wave][d] = (uint16_t)__popcll(m);
+        }
+        __syncthreads();
+        // per digit, groups in item order (round-major, then wave)
+        uint32_t run = 0;
+        if (tid < R) {
+#pragma unroll
+            for (int r = 0; r < IPT; r++)
+#pragma unroll
+                for (int w = 0; w < kWaves; w++) {
+                    const uint32_t c = s_cnt[r][w][tid];
+                    s_cnt[r][w][tid] = (uint16_t)run;
+                    run += c;
+                }
+        }
+        uint32_t cnt;  // items of this tile that take part
+        {
+            const uint32_t e = block_excl_scan(run, s_wave, cnt);
+            if (tid < R) s_start[tid] = e;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            if (ok[r]) {
+                const uint32_t d = (k[r] >> shift) & (R - 1);
+                const uint32_t pos = s_start[d] + s_cnt[r][wave][d] + below[r];
+                s_keys[pos] = k[r];
+                s_vals[pos] = v[r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            const int p = r * kThreads + tid;
+            if ((uint32_t)p < cnt) {
+                const uint32_t key = s_keys[p];
+                const uint32_t d = (key >> shift) & (R - 1);
+                const int64_t g = (int64_t)s_base[d] + hist[(int64_t)d * n_tiles + tile] + (p - s_start[d]);
+                if (!SEL || g < si.cap_out) {
+                    kout[g] = key;
+                    vout[g] = s_vals[p];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // One workgroup: cnt[0 .. *nblk_items / per) becomes its exclusive prefix sum
 // in place, *total the sum (and *total_out, when given, a copy of it clamped
 // to 32 bits; overflow of cap sets status bit). The number of blocks is
@@ -384,85 +446,6 @@ __global__ __launch_bounds__(kThreads) void k_block_scan(uint32_t* __restrict__ 
         if (total_out) *total_out = t32;
         if ((long long)carry > cap_total) atomicOr(status, overflow_bit);
     }
-}
-
-// Per 1024 items of the concatenated selections: how many cover at least one
-// tile. Also clears the tile ranges of every view.
-__global__ __launch_bounds__(kThreads) void k_vis_count(const uint32_t* __restrict__ tiles,
-                                                        const uint32_t* __restrict__ n_sel, SortViews V,
-                                                        uint32_t* __restrict__ vcnt, uint32_t* __restrict__ n_items,
-                                                        uint32_t* __restrict__ ranges, int64_t n_tiles)
-{
-    __shared__ uint32_t s_wave[kWaves];
-    __shared__ uint32_t s_seg[kMaxViews + 1];
-    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < 2 * n_tiles; t += (int64_t)gridDim.x * kThreads)
-        ranges[t] = 0u;
-    load_segments(n_sel, V, s_seg);
-    const int64_t n = s_seg[V.n];
-    if (blockIdx.x == 0 && threadIdx.x == 0) *n_items = (uint32_t)n;
-    const int64_t nblk = (n + kTileItems - 1) / kTileItems;
-    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int r = 0; r < kIPT; r++) {
-            const int64_t j = blk * kTileItems + r * kThreads + threadIdx.x;
-            if (j < n && tiles[item_splat((uint32_t)j, s_seg, V)] != 0u) ++c;
-        }
-        uint32_t total;
-        block_excl_scan(c, s_wave, total);
-        if (threadIdx.x == 0) vcnt[blk] = total;
-    }
-}
-
-// Packs the splats that cover a tile, in concatenated order (view, then
-// index): dkey = depth bits, dval = global splat index, at the block's offset
-// (vcnt, scanned). A block's packed run is assembled in LDS, then written
-// with consecutive lanes on consecutive addresses.
-__global__ __launch_bounds__(kThreads) void k_vis_pack(const float4* __restrict__ rgb_depth,
-                                                       const uint32_t* __restrict__ tiles,
-                                                       const uint32_t* __restrict__ n_sel, SortViews V,
-                                                       BlockOffsets voff, int64_t cap_items,
-                                                       uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval)
-{
-    __shared__ uint32_t s_wave[kWaves];
-    __shared__ unsigned long long s_red[kWaves];
-    __shared__ uint32_t s_seg[kMaxViews + 1];
-    __shared__ uint32_t s_k[kTileItems];
-    __shared__ uint32_t s_v[kTileItems];
-    load_segments(n_sel, V, s_seg);
-    const int64_t n = s_seg[V.n];
-    const int64_t nblk = (n + kTileItems - 1) / kTileItems;
-    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const unsigned long long base = block_offset(voff, blk, s_red);
-        const int64_t j0 = blk * kTileItems + (int64_t)threadIdx.x * kIPT;
-        uint32_t c = 0;
-        bool vis[kIPT];
-        uint32_t g[kIPT];
-#pragma unroll
-        for (int r = 0; r < kIPT; r++) {
-            g[r] = j0 + r < n ? item_splat((uint32_t)(j0 + r), s_seg, V) : 0u;
-            vis[r] = j0 + r < n && tiles[g[r]] != 0u;
-            c += vis[r] ? 1u : 0u;
-        }
-        uint32_t total;
-        uint32_t off = block_excl_scan(c, s_wave, total);
-#pragma unroll
-        for (int r = 0; r < kIPT; r++) {
-            if (vis[r]) {
-                s_k[off] = __float_as_uint(rgb_depth[g[r]].w);
-                s_v[off] = g[r];
-                ++off;
-            }
-        }
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < total; i += kThreads)
-            if ((long long)(base + i) < cap_items) {
-                dkey[base + i] = s_k[i];
-                dval[base + i] = s_v[i];
-            }
-        __syncthreads();
-    }
-    block_total(voff, nblk, s_red);
 }
 
 // Per 1024 splats in depth order: the sum of their tile counts (the areas of
@@ -600,24 +583,25 @@ int64_t tiles_for(int64_t n) { return (n + kTileItems - 1) / kTileItems; }
 // has an even number of passes and ends in buffer 0, after which buffer 1
 // (8 bytes per splat) holds the rectangles in depth order.
 struct SortWs {
-    uint32_t *dkey0, *dval0, *dkey1, *dval1, *bsum, *kalt, *valt, *hist, *digit_total, *vcnt, *counts;
+    uint32_t *dkey0, *dval0, *dkey1, *dval1, *bsum, *kalt, *valt, *hist, *digit_total, *counts;
     ushort4* rect_d;
 };
 // counts[0]: concatenated selection items, [1]: tile-covering splats packed
 
 size_t carve(void* base, int64_t sel_items, int64_t cap_items, int64_t cap_pairs, SortWs* w)
 {
-    const int64_t ht = tiles_for(cap_items > cap_pairs ? cap_items : cap_pairs);
-    const size_t nblk_sel = (size_t)((sel_items + kTileItems - 1) / kTileItems + 1);
+    int64_t most = cap_items > cap_pairs ? cap_items : cap_pairs;
+    if (sel_items > most) most = sel_items;
+    const int64_t ht = tiles_for(most);
     const size_t nblk_emit = (size_t)((cap_items + kEmitItems - 1) / kEmitItems + 1);
-    const size_t sizes[10] = {
+    const size_t sizes[9] = {
         (size_t)cap_items * 4, (size_t)cap_items * 4, (size_t)cap_items * 8, nblk_emit * 4,
         (size_t)cap_pairs * 4, (size_t)cap_pairs * 4,
-        (size_t)256 * (size_t)(ht + 1) * 4, (size_t)256 * 4, nblk_sel * 4, 16};
-    uint32_t** dst[10] = {&w->dkey0, &w->dval0, &w->dkey1, &w->bsum, &w->kalt, &w->valt, &w->hist,
-                          &w->digit_total, &w->vcnt, &w->counts};
+        (size_t)256 * (size_t)(ht + 1) * 4, (size_t)256 * 4, 16};
+    uint32_t** dst[9] = {&w->dkey0, &w->dval0, &w->dkey1, &w->bsum, &w->kalt, &w->valt, &w->hist,
+                         &w->digit_total, &w->counts};
     size_t off = 0;
-    for (int i = 0; i < 10; i++) {
+    for (int i = 0; i < 9; i++) {
         if (base) *dst[i] = (uint32_t*)((char*)base + off);
         off += align_up(sizes[i] + 4);
     }
@@ -635,40 +619,43 @@ size_t carve(void* base, int64_t sel_items, int64_t cap_items, int64_t cap_pairs
 // from the call's shape on the host (the counts stay on the device).
 constexpr int64_t kBigSort = (int64_t)4 << 20;
 
-// Block counts up to which the packing and emission kernels sum their block
-// offsets themselves (see BlockOffsets): up to 8M items at 1024 per block.
+// Block counts up to which the emission kernel sums its block offsets itself
+// (see BlockOffsets): up to 8M splats at 1024 per block.
 constexpr int64_t kInlineBlocks = 8192;
 
-template <int BITS, int IPT>
+template <int BITS, int IPT, bool SEL>
 void radix_pass_ipt(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint32_t* n_p,
-                    int64_t cap, int shift, const SortWs& w, hipStream_t s)
+                    int64_t cap, int shift, const SortWs& w, const SelInput& si, const SortViews& V, hipStream_t s)
 {
     int64_t grid = (cap + kThreads * IPT - 1) / (kThreads * IPT);
     if (grid > 4096) grid = 4096;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((k_hist<BITS, IPT>), dim3((unsigned)grid), dim3(kThreads), 0, s, kin, n_p, cap, shift, w.hist);
+    hipLaunchKernelGGL((k_hist<BITS, IPT, SEL>), dim3((unsigned)grid), dim3(kThreads), 0, s, kin, n_p, cap, shift,
+                       w.hist, si, V);
     hipLaunchKernelGGL(k_rowscan<IPT>, dim3(1u << BITS), dim3(kThreads), 0, s, n_p, cap, w.hist, w.digit_total);
-    hipLaunchKernelGGL((k_scatter<BITS, IPT>), dim3((unsigned)grid), dim3(kThreads), 0, s, kin, vin, kout, vout, n_p,
-                       cap, shift, w.hist, w.digit_total);
+    hipLaunchKernelGGL((k_scatter<BITS, IPT, SEL>), dim3((unsigned)grid), dim3(kThreads), 0, s, kin, vin, kout, vout,
+                       n_p, cap, shift, w.hist, w.digit_total, si, V);
 }
 
-template <int BITS>
+template <int BITS, bool SEL = false>
 void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint32_t* n_p,
-                int64_t cap, int shift, bool big, const SortWs& w, hipStream_t s)
+                int64_t cap, int shift, bool big, const SortWs& w, const SelInput& si, const SortViews& V,
+                hipStream_t s)
 {
-    if (big) radix_pass_ipt<BITS, 16>(kin, vin, kout, vout, n_p, cap, shift, w, s);
-    else radix_pass_ipt<BITS, 4>(kin, vin, kout, vout, n_p, cap, shift, w, s);
+    if (big) radix_pass_ipt<BITS, 16, SEL>(kin, vin, kout, vout, n_p, cap, shift, w, si, V, s);
+    else radix_pass_ipt<BITS, 4, SEL>(kin, vin, kout, vout, n_p, cap, shift, w, si, V, s);
 }
 
 void radix_pass_bits(int bits, const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                     const uint32_t* n_p, int64_t cap, int shift, bool big, const SortWs& w, hipStream_t s)
+                     const uint32_t* n_p, int64_t cap, int shift, bool big, const SortWs& w, const SelInput& si,
+                     const SortViews& V, hipStream_t s)
 {
     switch (bits) {
-        case 4: radix_pass<4>(kin, vin, kout, vout, n_p, cap, shift, big, w, s); break;
-        case 5: radix_pass<5>(kin, vin, kout, vout, n_p, cap, shift, big, w, s); break;
-        case 6: radix_pass<6>(kin, vin, kout, vout, n_p, cap, shift, big, w, s); break;
-        case 7: radix_pass<7>(kin, vin, kout, vout, n_p, cap, shift, big, w, s); break;
-        default: radix_pass<8>(kin, vin, kout, vout, n_p, cap, shift, big, w, s); break;
+        case 4: radix_pass<4>(kin, vin, kout, vout, n_p, cap, shift, big, w, si, V, s); break;
+        case 5: radix_pass<5>(kin, vin, kout, vout, n_p, cap, shift, big, w, si, V, s); break;
+        case 6: radix_pass<6>(kin, vin, kout, vout, n_p, cap, shift, big, w, si, V, s); break;
+        case 7: radix_pass<7>(kin, vin, kout, vout, n_p, cap, shift, big, w, si, V, s); break;
+        default: radix_pass<8>(kin, vin, kout, vout, n_p, cap, shift, big, w, si, V, s); break;
     }
 }
 
@@ -732,28 +719,24 @@ extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t c
     hipStream_t s = (hipStream_t)stream;
     const uint64_t max_tile = (uint64_t)cams[0].tile_base + (uint64_t)n_tiles - 1;
 
-    // 1. splats that cover a tile, packed in (view, index) order, then their
-    //    depth order (4 passes of 8 bits, result back in buffer 0)
+    // 1. the splats that cover a tile, in depth order: the first 8-bit pass
+    //    reads the selections and packs them (into buffer 1), three more
+    //    passes end in buffer 0
     auto grid_for = [](int64_t items, int64_t per) {
         int64_t g = (items + per - 1) / per;
         return (unsigned)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
     };
     const int64_t sel_items = cap_sel * n_views;
-    const unsigned gc = std::max(grid_for(sel_items, kTileItems), grid_for(2 * n_tiles, kThreads));
-    hipLaunchKernelGGL(k_vis_count, dim3(gc), dim3(kThreads), 0, s, splats->tiles, n_sel, V, w.vcnt, w.counts, ranges,
-                       n_tiles);
-    const BlockOffsets voff{w.vcnt, tiles_for(sel_items) <= kInlineBlocks, w.counts + 1, cap_items, status,
-                            FG_STATUS_ITEM_OVERFLOW};
-    if (!voff.inline_sum)
-        hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(kThreads), 0, s, w.vcnt, w.counts, (int64_t)kTileItems,
-                           sel_items, w.counts + 1, (uint32_t*)nullptr, cap_items, status, FG_STATUS_ITEM_OVERFLOW);
-    hipLaunchKernelGGL(k_vis_pack, dim3(grid_for(sel_items, kTileItems)), dim3(kThreads), 0, s,
-                       (const float4*)splats->rgb_depth, splats->tiles, n_sel, V, voff, cap_items, w.dkey0, w.dval0);
+    const bool big_depth = n_views > 1 && cap_items >= kBigSort;
+    const SelInput sel{(const float4*)splats->rgb_depth, splats->tiles, n_sel, w.counts, w.counts + 1, cap_items,
+                       status, ranges, 2 * n_tiles};
+    const SelInput none{};
+    radix_pass<8, true>(nullptr, nullptr, w.dkey1, w.dval1, w.counts, sel_items, 0, big_depth, w, sel, V, s);
     uint32_t* n_vis = w.counts + 1;
-    for (int p = 0; p < 4; p++) {
+    for (int p = 1; p < 4; p++) {
         const bool even = (p % 2) == 0;
         radix_pass<8>(even ? w.dkey0 : w.dkey1, even ? w.dval0 : w.dval1, even ? w.dkey1 : w.dkey0,
-                      even ? w.dval1 : w.dval0, n_vis, cap_items, 8 * p, n_views > 1 && cap_items >= kBigSort, w, s);
+                      even ? w.dval1 : w.dval0, n_vis, cap_items, 8 * p, big_depth, w, none, V, s);
     }
     // 2. tile counts in depth order and key emission
     const unsigned gv = grid_for(cap_items, kEmitItems);
@@ -782,7 +765,7 @@ extern "C" int fg_sort(const fg_splats* splats, const uint32_t* n_sel, int64_t c
         uint32_t *ka = ek, *va = ev, *kb = (ek == tile_keys) ? w.kalt : tile_keys, *vb = (ev == vals) ? w.valt : vals;
         for (int p = 0; p < passes; p++) {
             radix_pass_bits(bits, ka, va, kb, vb, n_pairs, cap_pairs, bits * p, n_views > 1 && cap_pairs >= kBigSort,
-                            w, s);
+                            w, none, V, s);
             uint32_t* t;
             t = ka; ka = kb; kb = t;
             t = va; va = vb; vb = t;
