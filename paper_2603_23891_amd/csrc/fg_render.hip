@@ -139,8 +139,10 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(int64_t n_tiles, RenderV
 // ticket.
 // Work item i of the blend is order[i] for i < heavy tiles, else
 // order[n_tiles - 1 - (i - heavy tiles)]. 8 consecutive tiles per thread per
-// round; the running counts of heavy and light tiles (one 64-bit word) and of
-// mask items are scanned together.
+// round (the ranges are read and the chunk counts written with consecutive
+// lanes on consecutive tiles, and handed over through LDS); the running
+// counts of heavy and light tiles (one 64-bit word) and of mask items are
+// scanned together.
 template <int CHUNK>
 __global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __restrict__ ranges, int64_t n_tiles,
                                                            int64_t max_mask_items, uint32_t* __restrict__ nch,
@@ -151,6 +153,7 @@ __global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __res
     __shared__ uint32_t s_wave_m[kScanThreads / fgd::kWave];
     __shared__ unsigned long long s_carry;
     __shared__ uint32_t s_carry_m;
+    __shared__ uint32_t s_c[8 * kScanThreads];
     const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
     if (tid == 0) {
         s_carry = 0ull;
@@ -158,14 +161,24 @@ __global__ __launch_bounds__(kScanThreads) void k_schedule(const uint32_t* __res
     }
     __syncthreads();
     for (int64_t base = 0; base < n_tiles; base += 8 * kScanThreads) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int64_t t = base + (int64_t)k * kScanThreads + tid;
+            uint32_t ck = 0u;
+            if (t < n_tiles) {
+                const uint2 r = reinterpret_cast<const uint2*>(ranges)[t];
+                ck = (r.y - r.x + CHUNK - 1) / CHUNK;
+                nch[t] = ck;
+            }
+            s_c[k * kScanThreads + tid] = ck;
+        }
+        __syncthreads();
         uint32_t c[8];
         unsigned long long sum = 0;  // low 32: heavy tiles, high 32: light tiles
         uint32_t msum = 0;           // mask items
 #pragma unroll
         for (int k = 0; k < 8; k++) {
-            const int64_t t = base + (int64_t)tid * 8 + k;
-            c[k] = t < n_tiles ? (ranges[2 * t + 1] - ranges[2 * t] + CHUNK - 1) / CHUNK : 0u;
-            if (t < n_tiles) nch[t] = c[k];
+            c[k] = s_c[tid * 8 + k];
             if (c[k] > 1) {
                 sum += 1ull;
                 msum += c[k];
