@@ -111,7 +111,27 @@ typedef struct fg_tree {
                                 16-byte aligned (read 16 bytes at a time) */
     const int32_t* parent;   /* [N] parent index (< own index), -1 for a root */
     const uint8_t* flags;    /* [N] bit 0: leaf. Read only for index < n_internal_span */
+    const float* tile_box;   /* optional (null: unused): the boxes fg_tree_boxes writes
+                                for this tree's mean and parent planes; rebuild them
+                                whenever those planes change */
 } fg_tree;
+
+/* Filter acceleration boxes (not part of the method; they change no result).
+ * In the filter's R&L test (Sec. 3.2) a leaf passes only when its mean is in
+ * the frustum. The filter reads the nodes in blocks of 2048 consecutive
+ * indices; for a block made of leaves only, fg_tree_boxes stores the
+ * axis-aligned box of their means, and the filter skips a block whose box
+ * lies outside every view's frustum by a margin above float32 rounding (none
+ * of its leaves could pass), reading none of its nodes. A block that holds an
+ * internal node or a parent link the filter would reject gets a NaN box and is
+ * never skipped, so FG_STATUS_BAD_PARENT is reported as without boxes.
+ * fg_tree_box_floats: the float count of the box array (8 per block: lo.xyz,
+ * 0, hi.xyz, 0), -1 for n_nodes < 0. fg_tree_boxes: writes them (device
+ * memory, 16-byte aligned, caller-owned), stream-ordered. Errors:
+ * FG_ERR_INVALID_ARG (null pointers), FG_ERR_INVALID_TREE (sizes as in
+ * fg_filter), FG_ERR_HIP. */
+int64_t fg_tree_box_floats(int64_t n_nodes);
+int fg_tree_boxes(const fg_tree* tree, float* tile_box, void* stream);
 
 /* Pinhole camera: x_c = R x_w + t, axes x right, y down, z forward.
  * Pixel (i, j) has its centre at (i + 0.5, j + 0.5); u = fx x_c / z_c + cx.

@@ -154,6 +154,95 @@ __global__ __launch_bounds__(kBlock) void k_blocked(const int32_t* __restrict__ 
     if (__ballot(bad) && fgd::lane_id() == 0) atomicOr(status, FG_STATUS_BAD_PARENT);
 }
 
+// True when every point of the box [lo, hi] is outside the view's frustum
+// by more than the rounding of the per-node test: then in_frustum(to_camera)
+// is false in float32 for every node mean inside the box. Each frustum plane
+// is a linear function L of the world position (the plane's normal from the
+// rows of R); the box is outside a plane when the minimum of L over the box
+// (centre term minus the half-extents times |normal|) exceeds a margin of
+// 1e-5 (1 + k) S, S = |c|_1 + |h|_1 + |t|_1. The rounding of the node's
+// float32 transform and comparison is below 8 * 2^-24 (1 + k) S, and that of
+// this test is of the same order, so the margin holds them with a factor of
+// more than 10. A box with a NaN or infinite bound is never outside.
+__device__ __forceinline__ bool box_outside(const fgd::Cam& c, float4 lo, float4 hi)
+{
+    const float cx = 0.5f * (lo.x + hi.x), cy = 0.5f * (lo.y + hi.y), cz = 0.5f * (lo.z + hi.z);
+    const float hx = 0.5f * (hi.x - lo.x), hy = 0.5f * (hi.y - lo.y), hz = 0.5f * (hi.z - lo.z);
+    const float S = ((fabsf(cx) + fabsf(cy)) + fabsf(cz)) + ((hx + hy) + hz) +
+                    ((fabsf(c.t[0]) + fabsf(c.t[1])) + fabsf(c.t[2]));
+    // L_min(a, b) = a . centre + b - |a| . h
+    auto lmin = [&](float a0, float a1, float a2, float b) {
+        return (((a0 * cx + a1 * cy) + a2 * cz) + b) - ((fabsf(a0) * hx + fabsf(a1) * hy) + fabsf(a2) * hz);
+    };
+    const float mx = 1e-5f * (1.0f + c.kx) * S, my = 1e-5f * (1.0f + c.ky) * S, mz = 1e-5f * S;
+    // behind the near plane: znear - z > margin everywhere
+    if (lmin(-c.R[6], -c.R[7], -c.R[8], c.znear - c.t[2]) > mz) return true;
+    // x > kx z and x < -kx z
+    if (lmin(c.R[0] - c.kx * c.R[6], c.R[1] - c.kx * c.R[7], c.R[2] - c.kx * c.R[8], c.t[0] - c.kx * c.t[2]) > mx)
+        return true;
+    if (lmin(-c.R[0] - c.kx * c.R[6], -c.R[1] - c.kx * c.R[7], -c.R[2] - c.kx * c.R[8], -c.t[0] - c.kx * c.t[2]) > mx)
+        return true;
+    // y > ky z and y < -ky z
+    if (lmin(c.R[3] - c.ky * c.R[6], c.R[4] - c.ky * c.R[7], c.R[5] - c.ky * c.R[8], c.t[1] - c.ky * c.t[2]) > my)
+        return true;
+    if (lmin(-c.R[3] - c.ky * c.R[6], -c.R[4] - c.ky * c.R[7], -c.R[5] - c.ky * c.R[8], -c.t[1] - c.ky * c.t[2]) > my)
+        return true;
+    return false;
+}
+
+// One workgroup per k_select tile of kTileNodes nodes: the box of the leaf
+// means of a tile made of leaves only (index >= span), as two float4 (lo.xyz,
+// hi.xyz); NaN for a tile that also holds internal nodes or a node whose
+// parent link k_select rejects, so that such a tile is never culled.
+__global__ __launch_bounds__(kBlock) void k_tile_boxes(const float* __restrict__ mean,
+                                                       const int32_t* __restrict__ parent, int64_t N, int64_t span,
+                                                       float4* __restrict__ box)
+{
+    __shared__ float s_r[6][kWaves];
+    __shared__ int s_bad;
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int64_t t0 = tile * kTileNodes;
+    if (tid == 0) s_bad = t0 < span ? 1 : 0;
+    __syncthreads();
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
+    for (int r = 0; r < kRounds; r++) {
+        const int64_t n = t0 + r * kBlock + tid;
+        if (n < N) {
+            const int32_t p = parent[n];
+            if (p >= 0 && ((int64_t)p >= n || (int64_t)p >= span)) bad = true;
+            const float x = mean[n], y = mean[N + n], z = mean[2 * N + n];
+            v[0] = fminf(v[0], x); v[1] = fminf(v[1], y); v[2] = fminf(v[2], z);
+            v[3] = fmaxf(v[3], x); v[4] = fmaxf(v[4], y); v[5] = fmaxf(v[5], z);
+        }
+    }
+#pragma unroll
+    for (int d = fgd::kWave / 2; d > 0; d >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) v[k] = fminf(v[k], __shfl_xor(v[k], d, fgd::kWave));
+#pragma unroll
+        for (int k = 3; k < 6; k++) v[k] = fmaxf(v[k], __shfl_xor(v[k], d, fgd::kWave));
+    }
+    if (__ballot(bad) && fgd::lane_id() == 0) s_bad = 1;
+    if (fgd::lane_id() == 0)
+        for (int k = 0; k < 6; k++) s_r[k][tid / fgd::kWave] = v[k];
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kWaves; w++) {
+            for (int k = 0; k < 3; k++) v[k] = fminf(v[k], s_r[k][w]);
+            for (int k = 3; k < 6; k++) v[k] = fmaxf(v[k], s_r[k][w]);
+        }
+        if (s_bad) {
+            box[2 * tile] = make_float4(NAN, NAN, NAN, NAN);
+            box[2 * tile + 1] = make_float4(NAN, NAN, NAN, NAN);
+        } else {
+            box[2 * tile] = make_float4(v[0], v[1], v[2], 0.0f);
+            box[2 * tile + 1] = make_float4(v[3], v[4], v[5], 0.0f);
+        }
+    }
+}
+
 template <int NV>
 __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mean, const int32_t* __restrict__ parent,
                                                    const uint8_t* __restrict__ flags,
@@ -163,6 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
                                                    const fg_camera* __restrict__ dcams, int nv,
                                                    uint32_t* __restrict__ sel_bits, int64_t sel_words,
                                                    uint32_t* __restrict__ tile_cnt, int64_t n_tiles,
+                                                   const float4* __restrict__ tile_box,
                                                    uint32_t* __restrict__ status)
 {
     __shared__ uint32_t s_cnt[NV][kWaves];
@@ -170,6 +260,31 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
     const int wave = tid / fgd::kWave;
     const int64_t tile = blockIdx.x;
     const uint32_t all = (1u << nv) - 1u;
+    // A tile of leaves whose box lies outside every view's frustum selects
+    // nothing (a leaf passes R&L only inside the frustum): its selection
+    // words and count are zero, and none of its nodes is read.
+    if (tile_box && tile * kTileNodes >= span) {
+        const float4 lo = tile_box[2 * tile], hi = tile_box[2 * tile + 1];
+        bool out = true;
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            if (v >= nv) break;
+            fgd::Cam cam = cams.c[v];
+            if (dcams) fgd::pose_from(cam, dcams + v);
+            out = out && box_outside(cam, lo, hi);
+        }
+        if (out) {
+#pragma unroll
+            for (int r = 0; r < kRounds; r++) {
+                const int64_t n = tile * kTileNodes + r * kBlock + tid;
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    if (v < nv) store_wave_bits(sel_bits + v * sel_words, n - (int64_t)fgd::lane_id(), N, 0ull);
+            }
+            if (tid < nv) tile_cnt[(int64_t)tid * n_tiles + tile] = 0u;
+            return;
+        }
+    }
     bool bad = false;
     // Loads are issued phase by phase for all rounds at once (parent links and
     // flags, then the parents' blocked bits, then leaf positions), so a
@@ -402,7 +517,7 @@ void launch_pass(const fg_tree* tree, const CamSet& cs, const fg_camera* dcams, 
     }
     hipLaunchKernelGGL(k_select<NV>, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, tree->mean, tree->parent,
                        tree->flags, w.small_bits, w.blocked_bits, w.words, N, span, cs, dcams, nv, sel_bits, sel_words,
-                       w.tile_cnt, n_tiles, status);
+                       w.tile_cnt, n_tiles, (const float4*)tree->tile_box, status);
     hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)nv), dim3(kScanThreads), 0, s, w.tile_cnt, n_tiles, n_sel,
                        cap_sel, status);
     if (cap_sel > 0)
@@ -462,6 +577,25 @@ int run_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, cons
 }
 
 }  // namespace
+
+extern "C" int64_t fg_tree_box_floats(int64_t n_nodes)
+{
+    if (n_nodes < 0) return -1;
+    return 8 * ((n_nodes + kTileNodes - 1) / kTileNodes);
+}
+
+extern "C" int fg_tree_boxes(const fg_tree* tree, float* tile_box, void* stream)
+{
+    if (!tree || !tile_box) return FG_ERR_INVALID_ARG;
+    const int64_t N = tree->n_nodes, span = tree->n_internal_span;
+    if (N < 0 || N >= ((int64_t)1 << 31) || span < 0 || span > N) return FG_ERR_INVALID_TREE;
+    if (N == 0) return FG_OK;
+    if (!tree->mean || !tree->parent) return FG_ERR_INVALID_ARG;
+    const int64_t n_tiles = (N + kTileNodes - 1) / kTileNodes;
+    hipLaunchKernelGGL(k_tile_boxes, dim3((unsigned)n_tiles), dim3(kBlock), 0, (hipStream_t)stream, tree->mean,
+                       tree->parent, N, span, (float4*)tile_box);
+    return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
+}
 
 extern "C" size_t fg_filter_workspace_size(int64_t n_nodes, int64_t n_internal_span, int32_t n_views)
 {

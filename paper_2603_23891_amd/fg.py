@@ -36,7 +36,8 @@ class FgError(RuntimeError):
 class FgTree(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_internal_span", C.c_int64), ("sh_degree", C.c_int32),
                 ("max_depth", C.c_int32), ("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p),
-                ("opacity", C.c_void_p), ("sh", C.c_void_p), ("parent", C.c_void_p), ("flags", C.c_void_p)]
+                ("opacity", C.c_void_p), ("sh", C.c_void_p), ("parent", C.c_void_p), ("flags", C.c_void_p),
+                ("tile_box", C.c_void_p)]
 
 
 class FgCamera(C.Structure):
@@ -71,7 +72,8 @@ class FgTune(C.Structure):
                 ("mask_items", C.c_int32), ("blend_events", C.c_void_p * 2), ("bwd_stats", C.c_void_p)]
 
 
-EXPORTS = ["fg_filter_workspace_size", "fg_filter", "fg_filter_noalloc", "fg_children_workspace_size",
+EXPORTS = ["fg_tree_box_floats", "fg_tree_boxes", "fg_filter_workspace_size", "fg_filter", "fg_filter_noalloc",
+           "fg_children_workspace_size",
            "fg_children", "fg_filter_levelwise_workspace_size", "fg_filter_levelwise", "fg_preprocess", "fg_sort_workspace_size", "fg_sort",
            "fg_render_workspace_size", "fg_render", "fg_gtc", "fg_gtc_tau", "fg_activate", "fg_render_backward_workspace_size",
            "fg_render_backward", "fg_status_string"]
@@ -87,6 +89,10 @@ def lib():
             raise FgError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_23891_amd.build`")
         L = C.CDLL(LIB_PATH)
         vp, i64, f32, i32 = C.c_void_p, C.c_int64, C.c_float, C.c_int
+        L.fg_tree_box_floats.restype = i64
+        L.fg_tree_box_floats.argtypes = [i64]
+        L.fg_tree_boxes.restype = i32
+        L.fg_tree_boxes.argtypes = [vp, vp, vp]
         L.fg_filter_workspace_size.restype = C.c_size_t
         L.fg_filter_workspace_size.argtypes = [i64, i64, C.c_int32]
         L.fg_filter.restype = i32
@@ -187,9 +193,12 @@ def tune_struct(render_batch: int = 0, radix_bits: int = 0, save_state: bool = F
 # device-resident inputs and outputs
 # ---------------------------------------------------------------------------
 class DeviceTree:
-    """A synth.Tree (or equivalent arrays) uploaded to the GPU as the fg_tree planes."""
+    """A synth.Tree (or equivalent arrays) uploaded to the GPU as the fg_tree planes.
+    boxes: also build the filter's per-block leaf boxes (fg_tree_boxes), which
+    let it skip blocks of leaves outside every view without changing any
+    result; rebuild them (build_boxes) after changing mean or parent."""
 
-    def __init__(self, tree, device="cuda"):
+    def __init__(self, tree, device="cuda", boxes: bool = True):
         def up(a, dt):
             return torch.from_numpy(np.ascontiguousarray(a).view(dt)).to(device)
 
@@ -204,12 +213,29 @@ class DeviceTree:
         self.n_internal_span = int(tree.n_internal_span)
         self.sh_degree = int(tree.sh_degree)
         self.max_depth = int(tree.max_depth)
+        self.tile_box = None
+        if boxes:
+            self.build_boxes()
+
+    def build_boxes(self, stream=None):
+        """(Re)writes the per-block leaf boxes on the stream (default: current)."""
+        n = int(lib().fg_tree_box_floats(self.n_nodes))
+        if n < 0:
+            raise FgError("fg_tree_box_floats: invalid node count")
+        box = torch.empty(max(n, 8), dtype=torch.float32, device=self.mean.device)
+        self.tile_box = None
+        ts = self.struct()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().fg_tree_boxes(C.byref(ts), C.c_void_p(box.data_ptr()), C.c_void_p(s.cuda_stream)),
+               "fg_tree_boxes")
+        self.tile_box = box
 
     def struct(self) -> FgTree:
         return FgTree(n_nodes=self.n_nodes, n_internal_span=self.n_internal_span, sh_degree=self.sh_degree,
                       max_depth=self.max_depth, mean=self.mean.data_ptr(), scale=self.scale.data_ptr(),
                       quat=self.quat.data_ptr(), opacity=self.opacity.data_ptr(), sh=self.sh.data_ptr(),
-                      parent=self.parent.data_ptr(), flags=self.flags.data_ptr())
+                      parent=self.parent.data_ptr(), flags=self.flags.data_ptr(),
+                      tile_box=self.tile_box.data_ptr() if self.tile_box is not None else None)
 
 
 class Splats:

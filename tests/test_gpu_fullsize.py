@@ -101,3 +101,141 @@ def test_city20m_scene_tau_on_gpu(city):
     assert np.allclose(vg[:, 0], ref["G_views"], rtol=2e-6, atol=0)
     assert abs(gb.g_bar.item() - ref["G_bar"]) <= 2e-6 * ref["G_bar"]
     assert abs(gb.tau.item() - tau) <= 5e-6 * tau
+
+
+# ---------------------------------------------------------------------------
+# The filter's per-block leaf boxes (fg_tree_boxes): they skip blocks of leaves
+# outside every view and must change no selection.
+# ---------------------------------------------------------------------------
+BLOCK = 2048  # nodes per filter block (one box each)
+
+
+def host_boxes(tree):
+    """The boxes by their definition, in numpy: min/max of the leaf means of a
+    block made of leaves only; NaN for a block holding an internal node or a
+    parent link the filter rejects (p >= n or p >= span)."""
+    N, span = tree.n_nodes, tree.n_internal_span
+    nb = (N + BLOCK - 1) // BLOCK
+    out = np.full((nb, 8), np.nan, np.float32)
+    mean = tree.mean.astype(np.float32)
+    n = np.arange(N)
+    p = tree.parent.astype(np.int64)
+    bad = (p >= 0) & ((p >= n) | (p >= span))
+    for b in range(nb):
+        lo, hi = b * BLOCK, min(N, (b + 1) * BLOCK)
+        if lo < span or bad[lo:hi].any():
+            continue
+        out[b, 0:3] = mean[:, lo:hi].min(axis=1)
+        out[b, 4:7] = mean[:, lo:hi].max(axis=1)
+        out[b, 3] = out[b, 7] = 0.0
+    return out
+
+
+def outside64(cam, lo, hi, margin_scale=1e-5):
+    """The boxes the filter may skip, in float64 with the filter's margin: every
+    point of the box outside one frustum plane by 1e-5 (1 + k) S."""
+    R = np.asarray(cam.R, np.float64).reshape(3, 3)
+    t = np.asarray(cam.t, np.float64)
+    c, h = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    S = np.abs(c).sum(1) + h.sum(1) + np.abs(t).sum()
+    out = np.zeros(len(lo), bool)
+    planes = [(-R[2], cam.znear - t[2], 1.0)]
+    for row, k, tt in ((0, cam.kx, t[0]), (1, cam.ky, t[1])):
+        for sgn in (1.0, -1.0):
+            planes.append((sgn * R[row] - k * R[2], sgn * tt - k * t[2], 1.0 + k))
+    for a, b, f in planes:
+        lmin = c @ a + b - h @ np.abs(a)
+        out |= lmin > margin_scale * f * S
+    return out & np.isfinite(lo).all(1) & np.isfinite(hi).all(1)
+
+
+def selection(dtree, cam, use_boxes):
+    saved = dtree.tile_box
+    if not use_boxes:
+        dtree.tile_box = None
+    try:
+        fb = fg.FrameBuffers(dtree, cam.width, cam.height, cap_sel=8_000_000, cap_pairs=1)
+        fg.filter_stage(dtree, cam, fb, synth.TAU_R)
+        torch.cuda.synchronize()
+    finally:
+        dtree.tile_box = saved
+    n_sel, _, status = fg.read_counts(fb)
+    return fb.sel_bits.cpu().numpy().copy(), fb.sel_idx[:n_sel].cpu().numpy().copy(), status
+
+
+def test_tile_boxes_match_their_definition(city1m):
+    tree, dtree, _ = city1m
+    gpu = dtree.tile_box.cpu().numpy().reshape(-1, 8)
+    ref = host_boxes(tree)
+    assert gpu.shape == ref.shape
+    assert np.array_equal(np.isnan(gpu), np.isnan(ref))
+    assert np.array_equal(np.nan_to_num(gpu), np.nan_to_num(ref))
+    assert np.isfinite(ref[:, 0]).sum() > 400  # most blocks are leaf blocks
+
+
+def test_tile_boxes_change_no_selection_on_the_flythrough(city):
+    """Eight frames of the fly-through (single views) and the 8 training views
+    in one pass: selection words and lists are identical with and without the
+    boxes, and the boxes let the filter skip a large share of the leaf blocks."""
+    tree, dtree, _ = city
+    frames = synth.city20m_frames(64)
+    box = dtree.tile_box.cpu().numpy().reshape(-1, 8)
+    skipped = []
+    for k in range(0, 64, 8):
+        a = selection(dtree, frames[k], True)
+        b = selection(dtree, frames[k], False)
+        assert a[2] == 0 and b[2] == 0
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), k
+        skipped.append(outside64(frames[k], box[:, 0:3].astype(np.float64), box[:, 4:7].astype(np.float64)).mean())
+    assert min(skipped) > 0.2, skipped
+    # eight views in one node-major pass: a block is skipped only when it is
+    # outside all of them
+    views = synth.city20m_training_views(8)
+    got = [multiview_selection(dtree, views, use) for use in (True, False)]
+    assert np.array_equal(got[0][0], got[1][0]) and np.array_equal(got[0][1], got[1][1])
+    assert got[0][2] == 0
+
+
+def multiview_selection(dtree, cams, use_boxes):
+    nv, N = len(cams), dtree.n_nodes
+    words, cap = (N + 31) // 32, 8_000_000
+    sel_bits = torch.empty(nv * words, dtype=torch.int32, device="cuda")
+    sel_idx = torch.empty(nv * cap, dtype=torch.int32, device="cuda")
+    n_sel = torch.zeros(nv, dtype=torch.int32, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = torch.empty(fg.fg_filter_workspace_size(N, dtree.n_internal_span, nv), dtype=torch.uint8, device="cuda")
+    saved = dtree.tile_box
+    if not use_boxes:
+        dtree.tile_box = None
+    try:
+        fg.fg_filter(dtree, cams, synth.TAU_R, sel_bits, sel_idx, cap, n_sel, status, ws)
+        torch.cuda.synchronize()
+    finally:
+        dtree.tile_box = saved
+    ns = n_sel.cpu().numpy().view(np.uint32)
+    idx = sel_idx.cpu().numpy().view(np.uint32).reshape(nv, cap)
+    lists = np.concatenate([idx[v, :min(int(ns[v]), cap)] for v in range(nv)])
+    return sel_bits.cpu().numpy(), np.concatenate([ns.astype(np.int64), lists.astype(np.int64)]), int(status.item())
+
+
+def test_bad_parent_in_a_skipped_leaf_block_is_reported(city1m):
+    """A malformed parent link in a leaf block that lies outside the view: the
+    block gets no box, so the filter still reads it and reports
+    FG_STATUS_BAD_PARENT (without boxes the same)."""
+    import dataclasses
+    tree, dtree, _ = city1m
+    cam = synth.city1m_camera()
+    box = dtree.tile_box.cpu().numpy().reshape(-1, 8)
+    out = outside64(cam, box[:, 0:3].astype(np.float64), box[:, 4:7].astype(np.float64))
+    assert out.any()
+    blk = int(np.nonzero(out)[0][len(np.nonzero(out)[0]) // 2])
+    j = blk * BLOCK + 7
+    bad = tree.parent.copy()
+    bad[j] = j  # a node as its own parent
+    t2 = dataclasses.replace(tree, parent=bad)
+    d2 = fg.DeviceTree(t2)
+    assert np.isnan(d2.tile_box.cpu().numpy().reshape(-1, 8)[blk]).all()
+    fb = fg.FrameBuffers(d2, cam.width, cam.height, cap_sel=2_000_000, cap_pairs=1)
+    fg.filter_stage(d2, cam, fb, synth.TAU_R)
+    torch.cuda.synchronize()
+    assert fg.read_counts(fb)[2] & fg.FG_STATUS_BAD_PARENT
