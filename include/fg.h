@@ -117,13 +117,14 @@ typedef struct fg_tree {
 } fg_tree;
 
 /* Filter acceleration boxes (not part of the method; they change no result).
- * In the filter's R&L test (Sec. 3.2) a leaf passes only when its mean is in
- * the frustum. The filter reads the nodes in blocks of 2048 consecutive
- * indices; for a block made of leaves only, fg_tree_boxes stores the
- * axis-aligned box of their means, and the filter skips a block whose box
- * lies outside every view's frustum by a margin above float32 rounding (none
- * of its leaves could pass), reading none of its nodes. A block that holds an
- * internal node or a parent link the filter would reject gets a NaN box and is
+ * In the filter's R&L test (Sec. 3.2) a node passes only when its mean is in
+ * the frustum (a leaf by F, an internal node through small). The filter reads
+ * the nodes in blocks of 2048 consecutive indices; fg_tree_boxes stores the
+ * axis-aligned box of each block's means, and the filter skips a block whose
+ * box lies outside every view's frustum by a margin above float32 rounding
+ * (none of its nodes could pass), reading none of its nodes in the selection
+ * pass and no attributes of its internal nodes in the projected-size pass. A
+ * block holding a parent link the filter would reject gets a NaN box and is
  * never skipped, so FG_STATUS_BAD_PARENT is reported as without boxes.
  * fg_tree_box_floats: the float count of the box array (8 per block: lo.xyz,
  * 0, hi.xyz, 0), -1 for n_nodes < 0. fg_tree_boxes: writes them (device

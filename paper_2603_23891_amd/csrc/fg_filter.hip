@@ -73,18 +73,70 @@ __device__ __forceinline__ void store_wave_bits(uint32_t* __restrict__ words, in
     }
 }
 
+// True when every point of the box [lo, hi] is outside the view's frustum
+// by more than the rounding of the per-node test: then in_frustum(to_camera)
+// is false in float32 for every node mean inside the box. Each frustum plane
+// is a linear function L of the world position (the plane's normal from the
+// rows of R); the box is outside a plane when the minimum of L over the box
+// (centre term minus the half-extents times |normal|) exceeds a margin of
+// 1e-5 (1 + k) S, S = |c|_1 + |h|_1 + |t|_1. The rounding of the node's
+// float32 transform and comparison is below 8 * 2^-24 (1 + k) S, and that of
+// this test is of the same order, so the margin holds them with a factor of
+// more than 10. A box with a NaN or infinite bound is never outside.
+__device__ __forceinline__ bool box_outside(const fgd::Cam& c, float4 lo, float4 hi)
+{
+    const float cx = 0.5f * (lo.x + hi.x), cy = 0.5f * (lo.y + hi.y), cz = 0.5f * (lo.z + hi.z);
+    const float hx = 0.5f * (hi.x - lo.x), hy = 0.5f * (hi.y - lo.y), hz = 0.5f * (hi.z - lo.z);
+    const float S = ((fabsf(cx) + fabsf(cy)) + fabsf(cz)) + ((hx + hy) + hz) +
+                    ((fabsf(c.t[0]) + fabsf(c.t[1])) + fabsf(c.t[2]));
+    // L_min(a, b) = a . centre + b - |a| . h
+    auto lmin = [&](float a0, float a1, float a2, float b) {
+        return (((a0 * cx + a1 * cy) + a2 * cz) + b) - ((fabsf(a0) * hx + fabsf(a1) * hy) + fabsf(a2) * hz);
+    };
+    const float mx = 1e-5f * (1.0f + c.kx) * S, my = 1e-5f * (1.0f + c.ky) * S, mz = 1e-5f * S;
+    // behind the near plane: znear - z > margin everywhere
+    if (lmin(-c.R[6], -c.R[7], -c.R[8], c.znear - c.t[2]) > mz) return true;
+    // x > kx z and x < -kx z
+    if (lmin(c.R[0] - c.kx * c.R[6], c.R[1] - c.kx * c.R[7], c.R[2] - c.kx * c.R[8], c.t[0] - c.kx * c.t[2]) > mx)
+        return true;
+    if (lmin(-c.R[0] - c.kx * c.R[6], -c.R[1] - c.kx * c.R[7], -c.R[2] - c.kx * c.R[8], -c.t[0] - c.kx * c.t[2]) > mx)
+        return true;
+    // y > ky z and y < -ky z
+    if (lmin(c.R[3] - c.ky * c.R[6], c.R[4] - c.ky * c.R[7], c.R[5] - c.ky * c.R[8], c.t[1] - c.ky * c.t[2]) > my)
+        return true;
+    if (lmin(-c.R[3] - c.ky * c.R[6], -c.R[4] - c.ky * c.R[7], -c.R[5] - c.ky * c.R[8], -c.t[1] - c.ky * c.t[2]) > my)
+        return true;
+    return false;
+}
+
 template <int NV>
 __global__ __launch_bounds__(kBlock) void k_small(const float* __restrict__ mean, const float* __restrict__ scale,
                                                   const float* __restrict__ quat, const uint8_t* __restrict__ flags,
                                                   int64_t N, int64_t span, CamSet cams,
                                                   const fg_camera* __restrict__ dcams, int nv, float tau_R,
                                                   uint32_t* __restrict__ small_bits, int64_t words,
+                                                  const float4* __restrict__ tile_box,
                                                   uint32_t* __restrict__ status, bool reset_status)
 {
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (n == 0 && reset_status) *status = 0u;  // before any later kernel of the call sets a bit
+    // nodes of a k_select tile whose box is outside every view are not in
+    // the frustum, so none of them is small
+    bool out = false;
+    if (tile_box) {
+        const int64_t tile = ((int64_t)blockIdx.x * kBlock) / kTileNodes;
+        const float4 lo = tile_box[2 * tile], hi = tile_box[2 * tile + 1];
+        out = true;
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            if (v >= nv) break;
+            fgd::Cam cam = cams.c[v];
+            if (dcams) fgd::pose_from(cam, dcams + v);
+            out = out && box_outside(cam, lo, hi);
+        }
+    }
     uint32_t small = 0;  // bit v: small in view v
-    if (n < span && !(flags[n] & 1u)) {
+    if (!out && n < span && !(flags[n] & 1u)) {
         const float mx = mean[n], my = mean[N + n], mz = mean[2 * N + n];
         float S[6];
         bool have_cov = false;
@@ -154,46 +206,10 @@ __global__ __launch_bounds__(kBlock) void k_blocked(const int32_t* __restrict__ 
     if (__ballot(bad) && fgd::lane_id() == 0) atomicOr(status, FG_STATUS_BAD_PARENT);
 }
 
-// True when every point of the box [lo, hi] is outside the view's frustum
-// by more than the rounding of the per-node test: then in_frustum(to_camera)
-// is false in float32 for every node mean inside the box. Each frustum plane
-// is a linear function L of the world position (the plane's normal from the
-// rows of R); the box is outside a plane when the minimum of L over the box
-// (centre term minus the half-extents times |normal|) exceeds a margin of
-// 1e-5 (1 + k) S, S = |c|_1 + |h|_1 + |t|_1. The rounding of the node's
-// float32 transform and comparison is below 8 * 2^-24 (1 + k) S, and that of
-// this test is of the same order, so the margin holds them with a factor of
-// more than 10. A box with a NaN or infinite bound is never outside.
-__device__ __forceinline__ bool box_outside(const fgd::Cam& c, float4 lo, float4 hi)
-{
-    const float cx = 0.5f * (lo.x + hi.x), cy = 0.5f * (lo.y + hi.y), cz = 0.5f * (lo.z + hi.z);
-    const float hx = 0.5f * (hi.x - lo.x), hy = 0.5f * (hi.y - lo.y), hz = 0.5f * (hi.z - lo.z);
-    const float S = ((fabsf(cx) + fabsf(cy)) + fabsf(cz)) + ((hx + hy) + hz) +
-                    ((fabsf(c.t[0]) + fabsf(c.t[1])) + fabsf(c.t[2]));
-    // L_min(a, b) = a . centre + b - |a| . h
-    auto lmin = [&](float a0, float a1, float a2, float b) {
-        return (((a0 * cx + a1 * cy) + a2 * cz) + b) - ((fabsf(a0) * hx + fabsf(a1) * hy) + fabsf(a2) * hz);
-    };
-    const float mx = 1e-5f * (1.0f + c.kx) * S, my = 1e-5f * (1.0f + c.ky) * S, mz = 1e-5f * S;
-    // behind the near plane: znear - z > margin everywhere
-    if (lmin(-c.R[6], -c.R[7], -c.R[8], c.znear - c.t[2]) > mz) return true;
-    // x > kx z and x < -kx z
-    if (lmin(c.R[0] - c.kx * c.R[6], c.R[1] - c.kx * c.R[7], c.R[2] - c.kx * c.R[8], c.t[0] - c.kx * c.t[2]) > mx)
-        return true;
-    if (lmin(-c.R[0] - c.kx * c.R[6], -c.R[1] - c.kx * c.R[7], -c.R[2] - c.kx * c.R[8], -c.t[0] - c.kx * c.t[2]) > mx)
-        return true;
-    // y > ky z and y < -ky z
-    if (lmin(c.R[3] - c.ky * c.R[6], c.R[4] - c.ky * c.R[7], c.R[5] - c.ky * c.R[8], c.t[1] - c.ky * c.t[2]) > my)
-        return true;
-    if (lmin(-c.R[3] - c.ky * c.R[6], -c.R[4] - c.ky * c.R[7], -c.R[5] - c.ky * c.R[8], -c.t[1] - c.ky * c.t[2]) > my)
-        return true;
-    return false;
-}
-
-// One workgroup per k_select tile of kTileNodes nodes: the box of the leaf
-// means of a tile made of leaves only (index >= span), as two float4 (lo.xyz,
-// hi.xyz); NaN for a tile that also holds internal nodes or a node whose
-// parent link k_select rejects, so that such a tile is never culled.
+// One workgroup per k_select tile of kTileNodes nodes: the box of the means
+// of all its nodes, as two float4 (lo.xyz, hi.xyz); NaN for a tile holding a
+// node whose parent link k_select rejects, so that such a tile is never
+// culled.
 __global__ __launch_bounds__(kBlock) void k_tile_boxes(const float* __restrict__ mean,
                                                        const int32_t* __restrict__ parent, int64_t N, int64_t span,
                                                        float4* __restrict__ box)
@@ -203,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_boxes(const float* __restrict__
     const int tid = threadIdx.x;
     const int64_t tile = blockIdx.x;
     const int64_t t0 = tile * kTileNodes;
-    if (tid == 0) s_bad = t0 < span ? 1 : 0;
+    if (tid == 0) s_bad = 0;
     __syncthreads();
     float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     bool bad = false;
@@ -260,10 +276,11 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
     const int wave = tid / fgd::kWave;
     const int64_t tile = blockIdx.x;
     const uint32_t all = (1u << nv) - 1u;
-    // A tile of leaves whose box lies outside every view's frustum selects
-    // nothing (a leaf passes R&L only inside the frustum): its selection
-    // words and count are zero, and none of its nodes is read.
-    if (tile_box && tile * kTileNodes >= span) {
+    // A tile whose box lies outside every view's frustum selects nothing
+    // (R&L needs F: a leaf in the frustum, an internal node small, which
+    // includes being in the frustum): its selection words and count are
+    // zero, and none of its nodes is read.
+    if (tile_box) {
         const float4 lo = tile_box[2 * tile], hi = tile_box[2 * tile + 1];
         bool out = true;
 #pragma unroll
@@ -511,7 +528,8 @@ void launch_pass(const fg_tree* tree, const CamSet& cs, const fg_camera* dcams, 
     if (span > 0) {
         const dim3 g((unsigned)((span + kBlock - 1) / kBlock));
         hipLaunchKernelGGL(k_small<NV>, g, dim3(kBlock), 0, s, tree->mean, tree->scale, tree->quat, tree->flags, N,
-                           span, cs, dcams, nv, tau_R, w.small_bits, w.words, status, reset_status);
+                           span, cs, dcams, nv, tau_R, w.small_bits, w.words, (const float4*)tree->tile_box, status,
+                           reset_status);
         hipLaunchKernelGGL(k_blocked<NV>, g, dim3(kBlock), 0, s, tree->parent, tree->flags, w.small_bits, w.words,
                            span, tree->max_depth, nv, w.blocked_bits, status);
     }

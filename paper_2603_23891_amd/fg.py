@@ -194,9 +194,9 @@ def tune_struct(render_batch: int = 0, radix_bits: int = 0, save_state: bool = F
 # ---------------------------------------------------------------------------
 class DeviceTree:
     """A synth.Tree (or equivalent arrays) uploaded to the GPU as the fg_tree planes.
-    boxes: also build the filter's per-block leaf boxes (fg_tree_boxes), which
-    let it skip blocks of leaves outside every view without changing any
-    result; rebuild them (build_boxes) after changing mean or parent."""
+    boxes: also build the filter's per-block boxes (fg_tree_boxes), which let
+    it skip blocks of nodes outside every view without changing any result;
+    rebuild them (build_boxes) after changing mean or parent."""
 
     def __init__(self, tree, device="cuda", boxes: bool = True):
         def up(a, dt):
@@ -218,7 +218,7 @@ class DeviceTree:
             self.build_boxes()
 
     def build_boxes(self, stream=None):
-        """(Re)writes the per-block leaf boxes on the stream (default: current)."""
+        """(Re)writes the per-block boxes on the stream (default: current)."""
         n = int(lib().fg_tree_box_floats(self.n_nodes))
         if n < 0:
             raise FgError("fg_tree_box_floats: invalid node count")
