@@ -126,12 +126,17 @@ typedef struct fg_tree {
  * pass and no attributes of its internal nodes in the projected-size pass. A
  * block holding a parent link the filter would reject gets a NaN box and is
  * never skipped, so FG_STATUS_BAD_PARENT is reported as without boxes.
- * fg_tree_box_floats: the float count of the box array (8 per block: lo.xyz,
- * 0, hi.xyz, 0), -1 for n_nodes < 0. fg_tree_boxes: writes them (device
- * memory, 16-byte aligned, caller-owned), stream-ordered. Errors:
- * FG_ERR_INVALID_ARG (null pointers), FG_ERR_INVALID_TREE (sizes as in
- * fg_filter), FG_ERR_HIP. */
-int64_t fg_tree_box_floats(int64_t n_nodes);
+ * The same array also holds, per 256 consecutive nodes below n_internal_span,
+ * the index range of their children: the filter leaves out the ancestor walks
+ * of such a group when all of its children lie in skipped blocks (only those
+ * children read the walks' results), unless a node of the group has a parent
+ * chain the filter would reject.
+ * fg_tree_box_floats: the float count of the array (8 per block: lo.xyz, 0,
+ * hi.xyz, 0; then 2 int32 per group), -1 for inconsistent sizes.
+ * fg_tree_boxes: writes it (device memory, 16-byte aligned, caller-owned),
+ * stream-ordered. Errors: FG_ERR_INVALID_ARG (null pointers),
+ * FG_ERR_INVALID_TREE (sizes as in fg_filter), FG_ERR_HIP. */
+int64_t fg_tree_box_floats(int64_t n_nodes, int64_t n_internal_span);
 int fg_tree_boxes(const fg_tree* tree, float* tile_box, void* stream);
 
 /* Pinhole camera: x_c = R x_w + t, axes x right, y down, z forward.

@@ -167,13 +167,53 @@ __global__ __launch_bounds__(kBlock) void k_small(const float* __restrict__ mean
     }
 }
 
+// Whether the ancestor walks of k_blocked workgroup blockIdx.x can be left
+// out: blocked(n) is read only by k_select, for the children of n, and a
+// child in a tile whose box is outside every view is never selected. So the
+// walks are skipped when the children of the workgroup's nodes (index range
+// crange, from the tree's boxes) lie in at most 8 such tiles, or when there
+// are none. A workgroup whose nodes have a malformed parent chain has the
+// range (-1, -1) and is always walked, so its FG_STATUS_BAD_PARENT is kept.
+template <int NV>
+__device__ __forceinline__ bool skip_walks(const float4* __restrict__ tile_box, const int2* __restrict__ crange,
+                                           const CamSet& cams, const fg_camera* __restrict__ dcams, int nv)
+{
+    if (!tile_box) return false;
+    const int2 cr = crange[blockIdx.x];
+    if (cr.x < 0) return false;
+    if (cr.x > cr.y) return true;
+    const int64_t t0 = cr.x / kTileNodes, t1 = cr.y / kTileNodes;
+    if (t1 - t0 >= 8) return false;
+    bool out = true;
+    for (int64_t t = t0; t <= t1 && out; t++) {
+        const float4 lo = tile_box[2 * t], hi = tile_box[2 * t + 1];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            if (v >= nv) break;
+            fgd::Cam cam = cams.c[v];
+            if (dcams) fgd::pose_from(cam, dcams + v);
+            out = out && box_outside(cam, lo, hi);
+        }
+    }
+    return out;
+}
+
 template <int NV>
 __global__ __launch_bounds__(kBlock) void k_blocked(const int32_t* __restrict__ parent, const uint8_t* __restrict__ flags,
                                                     const uint32_t* __restrict__ small_bits, int64_t words,
                                                     int64_t span, int max_depth, int nv,
-                                                    uint32_t* __restrict__ blocked_bits, uint32_t* __restrict__ status)
+                                                    uint32_t* __restrict__ blocked_bits, const float4* __restrict__ tile_box,
+                                                    const int2* __restrict__ crange, CamSet cams,
+                                                    const fg_camera* __restrict__ dcams, uint32_t* __restrict__ status)
 {
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (skip_walks<NV>(tile_box, crange, cams, dcams, nv)) {
+        const int64_t base = n - (int64_t)fgd::lane_id();
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            if (v < nv) store_wave_bits(blocked_bits + v * words, base, span, 0ull);
+        return;
+    }
     const uint32_t all = (1u << nv) - 1u;
     uint32_t blocked = 0;  // bit v: self or an ancestor small in view v
     bool bad = false;
@@ -257,6 +297,69 @@ __global__ __launch_bounds__(kBlock) void k_tile_boxes(const float* __restrict__
             box[2 * tile + 1] = make_float4(v[3], v[4], v[5], 0.0f);
         }
     }
+}
+
+// Child index ranges per k_blocked workgroup (kBlock consecutive nodes below
+// span): (INT32_MAX, -1) before k_child_ranges, which takes every node with
+// a well-formed parent link into its parent's range.
+__global__ void k_crange_init(int2* __restrict__ crange, int64_t n_blocks)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n_blocks) crange[b] = make_int2(INT32_MAX, -1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_child_ranges(const int32_t* __restrict__ parent, int64_t N, int64_t span,
+                                                         int2* __restrict__ crange)
+{
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int32_t p = n < N ? parent[n] : -1;
+    if (p < 0 || (int64_t)p >= n || (int64_t)p >= span) p = -1;
+    const int32_t b = p >= 0 ? p / kBlock : -1;
+    // most waves hold the children of one workgroup's nodes: one atomic pair
+    const int32_t b0 = __shfl(b, 0, fgd::kWave);
+    const bool same = __ballot(b != b0) == 0ull;
+    if (same) {
+        if (b0 >= 0) {
+            int32_t lo = (int32_t)n, hi = (int32_t)n;
+#pragma unroll
+            for (int d = fgd::kWave / 2; d > 0; d >>= 1) {
+                lo = min(lo, __shfl_xor(lo, d, fgd::kWave));
+                hi = max(hi, __shfl_xor(hi, d, fgd::kWave));
+            }
+            if (fgd::lane_id() == 0) {
+                atomicMin(&crange[b0].x, lo);
+                atomicMax(&crange[b0].y, hi);
+            }
+        }
+    } else if (b >= 0) {
+        atomicMin(&crange[b].x, (int32_t)n);
+        atomicMax(&crange[b].y, (int32_t)n);
+    }
+}
+
+// (-1, -1) for the workgroups holding a node below span whose parent chain
+// k_blocked could reject (a link not below its child or not below span, or
+// longer than max_depth), so that their walks always run.
+__global__ __launch_bounds__(kBlock) void k_chain_check(const int32_t* __restrict__ parent, int64_t span,
+                                                        int max_depth, int2* __restrict__ crange)
+{
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool bad = false;
+    if (n < span) {
+        int64_t a = n;
+        int32_t p = parent[n];
+        int hops = 0;
+        while (p >= 0) {
+            if ((int64_t)p >= a || (int64_t)p >= span || hops >= max_depth) {
+                bad = true;
+                break;
+            }
+            a = p;
+            p = parent[p];
+            ++hops;
+        }
+    }
+    if (__ballot(bad) && fgd::lane_id() == 0) crange[blockIdx.x] = make_int2(-1, -1);
 }
 
 template <int NV>
@@ -530,8 +633,10 @@ void launch_pass(const fg_tree* tree, const CamSet& cs, const fg_camera* dcams, 
         hipLaunchKernelGGL(k_small<NV>, g, dim3(kBlock), 0, s, tree->mean, tree->scale, tree->quat, tree->flags, N,
                            span, cs, dcams, nv, tau_R, w.small_bits, w.words, (const float4*)tree->tile_box, status,
                            reset_status);
+        const float4* box = (const float4*)tree->tile_box;
+        const int2* crange = box ? (const int2*)(box + 2 * n_tiles) : nullptr;
         hipLaunchKernelGGL(k_blocked<NV>, g, dim3(kBlock), 0, s, tree->parent, tree->flags, w.small_bits, w.words,
-                           span, tree->max_depth, nv, w.blocked_bits, status);
+                           span, tree->max_depth, nv, w.blocked_bits, box, crange, cs, dcams, status);
     }
     hipLaunchKernelGGL(k_select<NV>, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, tree->mean, tree->parent,
                        tree->flags, w.small_bits, w.blocked_bits, w.words, N, span, cs, dcams, nv, sel_bits, sel_words,
@@ -596,10 +701,10 @@ int run_filter(const fg_tree* tree, const fg_camera* cams, int32_t n_views, cons
 
 }  // namespace
 
-extern "C" int64_t fg_tree_box_floats(int64_t n_nodes)
+extern "C" int64_t fg_tree_box_floats(int64_t n_nodes, int64_t n_internal_span)
 {
-    if (n_nodes < 0) return -1;
-    return 8 * ((n_nodes + kTileNodes - 1) / kTileNodes);
+    if (n_nodes < 0 || n_internal_span < 0 || n_internal_span > n_nodes) return -1;
+    return 8 * ((n_nodes + kTileNodes - 1) / kTileNodes) + 2 * ((n_internal_span + kBlock - 1) / kBlock);
 }
 
 extern "C" int fg_tree_boxes(const fg_tree* tree, float* tile_box, void* stream)
@@ -609,9 +714,20 @@ extern "C" int fg_tree_boxes(const fg_tree* tree, float* tile_box, void* stream)
     if (N < 0 || N >= ((int64_t)1 << 31) || span < 0 || span > N) return FG_ERR_INVALID_TREE;
     if (N == 0) return FG_OK;
     if (!tree->mean || !tree->parent) return FG_ERR_INVALID_ARG;
+    if (span > 0 && tree->max_depth < 0) return FG_ERR_INVALID_TREE;
     const int64_t n_tiles = (N + kTileNodes - 1) / kTileNodes;
-    hipLaunchKernelGGL(k_tile_boxes, dim3((unsigned)n_tiles), dim3(kBlock), 0, (hipStream_t)stream, tree->mean,
-                       tree->parent, N, span, (float4*)tile_box);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_tile_boxes, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, tree->mean, tree->parent, N, span,
+                       (float4*)tile_box);
+    if (span > 0) {
+        int2* crange = (int2*)(tile_box + 8 * n_tiles);
+        const int64_t nb = (span + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(k_crange_init, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, crange, nb);
+        hipLaunchKernelGGL(k_child_ranges, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           tree->parent, N, span, crange);
+        hipLaunchKernelGGL(k_chain_check, dim3((unsigned)nb), dim3(kBlock), 0, s, tree->parent, span,
+                           tree->max_depth, crange);
+    }
     return hipGetLastError() == hipSuccess ? FG_OK : FG_ERR_HIP;
 }
 

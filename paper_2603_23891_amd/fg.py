@@ -90,7 +90,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i64, f32, i32 = C.c_void_p, C.c_int64, C.c_float, C.c_int
         L.fg_tree_box_floats.restype = i64
-        L.fg_tree_box_floats.argtypes = [i64]
+        L.fg_tree_box_floats.argtypes = [i64, i64]
         L.fg_tree_boxes.restype = i32
         L.fg_tree_boxes.argtypes = [vp, vp, vp]
         L.fg_filter_workspace_size.restype = C.c_size_t
@@ -219,7 +219,7 @@ class DeviceTree:
 
     def build_boxes(self, stream=None):
         """(Re)writes the per-block boxes on the stream (default: current)."""
-        n = int(lib().fg_tree_box_floats(self.n_nodes))
+        n = int(lib().fg_tree_box_floats(self.n_nodes, self.n_internal_span))
         if n < 0:
             raise FgError("fg_tree_box_floats: invalid node count")
         box = torch.empty(max(n, 8), dtype=torch.float32, device=self.mean.device)

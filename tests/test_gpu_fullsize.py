@@ -108,6 +108,54 @@ def test_city20m_scene_tau_on_gpu(city):
 # outside every view and must change no selection.
 # ---------------------------------------------------------------------------
 BLOCK = 2048  # nodes per filter block (one box each)
+GROUP = 256   # nodes per ancestor-walk group (one child range each)
+
+
+def boxes_of(dtree):
+    nb = (dtree.n_nodes + BLOCK - 1) // BLOCK
+    return dtree.tile_box[:8 * nb].cpu().numpy().reshape(-1, 8)
+
+
+def cranges_of(dtree):
+    nb = (dtree.n_nodes + BLOCK - 1) // BLOCK
+    return dtree.tile_box[8 * nb:].cpu().numpy().view(np.int32).reshape(-1, 2)
+
+
+def host_cranges(tree):
+    """Child index ranges per group of 256 nodes below span, by definition:
+    min/max index of the nodes whose parent link is well formed (p < n,
+    p < span) and points into the group; (INT32_MAX, -1) without children;
+    (-1, -1) when a node of the group below span has a parent chain that is
+    malformed or longer than max_depth."""
+    N, span = tree.n_nodes, tree.n_internal_span
+    ng = (span + GROUP - 1) // GROUP
+    out = np.empty((ng, 2), np.int64)
+    out[:, 0], out[:, 1] = np.iinfo(np.int32).max, -1
+    n = np.arange(N)
+    p = tree.parent.astype(np.int64)
+    ok = (p >= 0) & (p < n) & (p < span)
+    g = p[ok] // GROUP
+    np.minimum.at(out[:, 0], g, n[ok])
+    np.maximum.at(out[:, 1], g, n[ok])
+    # chain walk of every node below span, as the filter's ancestor walk
+    a = np.arange(span)
+    cur = p[:span].copy()
+    bad = np.zeros(span, bool)
+    live = cur >= 0
+    for hops in range(64):
+        if not live.any():
+            break
+        idx = np.nonzero(live)[0]
+        c, prev = cur[idx], a[idx]
+        b = (c >= prev) | (c >= span) | (hops >= tree.max_depth)
+        bad[idx[b]] = True
+        live[idx[b]] = False
+        go = idx[~b]
+        a[go] = cur[go]
+        cur[go] = p[cur[go]]
+        live[go] = cur[go] >= 0
+    out[np.unique(np.nonzero(bad)[0] // GROUP)] = -1
+    return out.astype(np.int32)
 
 
 def host_boxes(tree):
@@ -165,12 +213,13 @@ def selection(dtree, cam, use_boxes):
 
 def test_tile_boxes_match_their_definition(city1m):
     tree, dtree, _ = city1m
-    gpu = dtree.tile_box.cpu().numpy().reshape(-1, 8)
+    gpu = boxes_of(dtree)
     ref = host_boxes(tree)
     assert gpu.shape == ref.shape
     assert np.array_equal(np.isnan(gpu), np.isnan(ref))
     assert np.array_equal(np.nan_to_num(gpu), np.nan_to_num(ref))
     assert np.isfinite(ref[:, 0]).all()
+    assert np.array_equal(cranges_of(dtree), host_cranges(tree))
 
 
 def test_tile_boxes_change_no_selection_on_the_flythrough(city):
@@ -179,7 +228,7 @@ def test_tile_boxes_change_no_selection_on_the_flythrough(city):
     boxes, and the boxes let the filter skip a large share of the blocks."""
     tree, dtree, _ = city
     frames = synth.city20m_frames(64)
-    box = dtree.tile_box.cpu().numpy().reshape(-1, 8)
+    box = boxes_of(dtree)
     skipped = []
     for k in range(0, 64, 8):
         a = selection(dtree, frames[k], True)
@@ -226,7 +275,7 @@ def test_bad_parent_in_a_skipped_leaf_block_is_reported(city1m):
     import dataclasses
     tree, dtree, _ = city1m
     cam = synth.city1m_camera()
-    box = dtree.tile_box.cpu().numpy().reshape(-1, 8)
+    box = boxes_of(dtree)
     out = outside64(cam, box[:, 0:3].astype(np.float64), box[:, 4:7].astype(np.float64))
     out &= np.arange(out.size) * BLOCK >= tree.n_internal_span
     assert out.any()
@@ -236,7 +285,7 @@ def test_bad_parent_in_a_skipped_leaf_block_is_reported(city1m):
     bad[j] = j  # a node as its own parent
     t2 = dataclasses.replace(tree, parent=bad)
     d2 = fg.DeviceTree(t2)
-    assert np.isnan(d2.tile_box.cpu().numpy().reshape(-1, 8)[blk]).all()
+    assert np.isnan(boxes_of(d2)[blk]).all()
     fb = fg.FrameBuffers(d2, cam.width, cam.height, cap_sel=2_000_000, cap_pairs=1)
     fg.filter_stage(d2, cam, fb, synth.TAU_R)
     torch.cuda.synchronize()
