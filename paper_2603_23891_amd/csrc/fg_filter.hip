@@ -115,28 +115,12 @@ __global__ __launch_bounds__(kBlock) void k_small(const float* __restrict__ mean
                                                   int64_t N, int64_t span, CamSet cams,
                                                   const fg_camera* __restrict__ dcams, int nv, float tau_R,
                                                   uint32_t* __restrict__ small_bits, int64_t words,
-                                                  const float4* __restrict__ tile_box,
                                                   uint32_t* __restrict__ status, bool reset_status)
 {
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (n == 0 && reset_status) *status = 0u;  // before any later kernel of the call sets a bit
-    // nodes of a k_select tile whose box is outside every view are not in
-    // the frustum, so none of them is small
-    bool out = false;
-    if (tile_box) {
-        const int64_t tile = ((int64_t)blockIdx.x * kBlock) / kTileNodes;
-        const float4 lo = tile_box[2 * tile], hi = tile_box[2 * tile + 1];
-        out = true;
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-            if (v >= nv) break;
-            fgd::Cam cam = cams.c[v];
-            if (dcams) fgd::pose_from(cam, dcams + v);
-            out = out && box_outside(cam, lo, hi);
-        }
-    }
     uint32_t small = 0;  // bit v: small in view v
-    if (!out && n < span && !(flags[n] & 1u)) {
+    if (n < span && !(flags[n] & 1u)) {
         const float mx = mean[n], my = mean[N + n], mz = mean[2 * N + n];
         float S[6];
         bool have_cov = false;
@@ -489,65 +473,51 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
 }
 
 // One workgroup per view: tile_cnt[v][0 .. n_tiles) becomes its exclusive
-// prefix sum in place; n_sel[v] = the total. Rounds of 8 x 1024 counts: each
-// round is loaded and stored with consecutive lanes on consecutive words and
-// transposed through LDS, so that every thread scans 8 consecutive counts.
-constexpr int kScanPer = 8;
-constexpr int kScanRound = kScanPer * kScanThreads;
-
+// prefix sum in place; n_sel[v] = the total. Each thread takes a run of
+// consecutive tiles, read 8 at a time with independent loads.
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t* __restrict__ tile_cnt, int64_t n_tiles,
                                                             uint32_t* __restrict__ n_sel, int64_t cap_sel,
                                                             uint32_t* __restrict__ status)
 {
-    __shared__ uint32_t s_buf[kScanRound];
     __shared__ uint32_t s_wave[kScanThreads / fgd::kWave];
     uint32_t* row = tile_cnt + (int64_t)blockIdx.x * n_tiles;
     const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
-    uint32_t carry = 0;
-    for (int64_t base = 0; base < n_tiles; base += kScanRound) {
+    const int64_t per = (n_tiles + kScanThreads - 1) / kScanThreads;
+    const int64_t lo = tid * per, hi = lo + per < n_tiles ? lo + per : n_tiles;
+    uint32_t s = 0;
+    for (int64_t i0 = lo; i0 < hi; i0 += 8) {
+        uint32_t c[8];
 #pragma unroll
-        for (int k = 0; k < kScanPer; k++) {
-            const int64_t i = base + k * kScanThreads + tid;
-            s_buf[k * kScanThreads + tid] = i < n_tiles ? row[i] : 0u;
-        }
-        __syncthreads();
-        uint32_t c[kScanPer];
-        uint32_t s = 0;
+        for (int u = 0; u < 8; u++) c[u] = i0 + u < hi ? row[i0 + u] : 0u;
 #pragma unroll
-        for (int k = 0; k < kScanPer; k++) {
-            c[k] = s_buf[tid * kScanPer + k];
-            s += c[k];
-        }
-        uint32_t x = s;
+        for (int u = 0; u < 8; u++) s += c[u];
+    }
+    uint32_t x = s;
 #pragma unroll
-        for (int d = 1; d < fgd::kWave; d <<= 1) {
-            const uint32_t y = __shfl_up(x, d, fgd::kWave);
-            if (lane >= d) x += y;
-        }
-        if (lane == fgd::kWave - 1) s_wave[wave] = x;
-        __syncthreads();
-        uint32_t run = carry + x - s, total = 0;
-        for (int w = 0; w < kScanThreads / fgd::kWave; w++) {
-            if (w < wave) run += s_wave[w];
-            total += s_wave[w];
-        }
+    for (int d = 1; d < fgd::kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, fgd::kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == fgd::kWave - 1) s_wave[wave] = x;
+    __syncthreads();
+    uint32_t run = x - s, total = 0;
+    for (int w = 0; w < kScanThreads / fgd::kWave; w++) {
+        if (w < wave) run += s_wave[w];
+        total += s_wave[w];
+    }
+    for (int64_t i0 = lo; i0 < hi; i0 += 8) {
+        uint32_t c[8];
 #pragma unroll
-        for (int k = 0; k < kScanPer; k++) {
-            s_buf[tid * kScanPer + k] = run;
-            run += c[k];
-        }
-        __syncthreads();
+        for (int u = 0; u < 8; u++) c[u] = i0 + u < hi ? row[i0 + u] : 0u;
 #pragma unroll
-        for (int k = 0; k < kScanPer; k++) {
-            const int64_t i = base + k * kScanThreads + tid;
-            if (i < n_tiles) row[i] = s_buf[k * kScanThreads + tid];
+        for (int u = 0; u < 8; u++) {
+            if (i0 + u < hi) row[i0 + u] = run;
+            run += c[u];
         }
-        carry += total;
-        __syncthreads();  // s_buf and s_wave are reused by the next round
     }
     if (tid == 0) {
-        n_sel[blockIdx.x] = carry;
-        if ((int64_t)carry > cap_sel) atomicOr(status, FG_STATUS_SEL_OVERFLOW);
+        n_sel[blockIdx.x] = total;
+        if ((int64_t)total > cap_sel) atomicOr(status, FG_STATUS_SEL_OVERFLOW);
     }
 }
 
@@ -631,8 +601,7 @@ void launch_pass(const fg_tree* tree, const CamSet& cs, const fg_camera* dcams, 
     if (span > 0) {
         const dim3 g((unsigned)((span + kBlock - 1) / kBlock));
         hipLaunchKernelGGL(k_small<NV>, g, dim3(kBlock), 0, s, tree->mean, tree->scale, tree->quat, tree->flags, N,
-                           span, cs, dcams, nv, tau_R, w.small_bits, w.words, (const float4*)tree->tile_box, status,
-                           reset_status);
+                           span, cs, dcams, nv, tau_R, w.small_bits, w.words, status, reset_status);
         const float4* box = (const float4*)tree->tile_box;
         const int2* crange = box ? (const int2*)(box + 2 * n_tiles) : nullptr;
         hipLaunchKernelGGL(k_blocked<NV>, g, dim3(kBlock), 0, s, tree->parent, tree->flags, w.small_bits, w.words,
