@@ -63,10 +63,36 @@ def pct(x, q):
     return float(np.percentile(np.asarray(x, np.float64), q))
 
 
-def filter_bytes(tree, small_words, n_sel):
-    """Bytes the filter must move for one frame: parent of every node, flags,
-    mean/scale/quat of internal nodes, the mean of every leaf that no small
-    ancestor culls, the small bits, the selection mask and the compacted ids."""
+FILTER_BLOCK = 2048  # nodes per selection-pass workgroup (one box each)
+
+
+def blocks_read(boxes, cam):
+    """The 2048-node blocks the selection pass reads for one view: those whose
+    box (the tree's fg_tree_boxes) is not outside the frustum by the filter's
+    margin, evaluated here in float64 (the byte model's count; the kernel's
+    float32 decision can differ only for boxes within rounding of the margin)."""
+    R = np.asarray(cam.R, np.float64).reshape(3, 3)
+    t = np.asarray(cam.t, np.float64)
+    lo, hi = boxes[:, 0:3].astype(np.float64), boxes[:, 4:7].astype(np.float64)
+    c, h = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    S = np.abs(c).sum(1) + h.sum(1) + np.abs(t).sum()
+    out = np.zeros(len(boxes), bool)
+    planes = [(-R[2], cam.znear - t[2], 1.0)]
+    for row, k, tt in ((0, cam.kx, t[0]), (1, cam.ky, t[1])):
+        for sgn in (1.0, -1.0):
+            planes.append((sgn * R[row] - k * R[2], sgn * tt - k * t[2], 1.0 + k))
+    with np.errstate(invalid="ignore"):
+        for a, b, f in planes:
+            out |= (c @ a + b - h @ np.abs(a)) > 1e-5 * f * S
+    return ~(out & np.isfinite(lo).all(1) & np.isfinite(hi).all(1))
+
+
+def filter_bytes(tree, small_words, n_sel, read_blocks=None):
+    """Bytes the filter must move for one frame: flags and mean/scale/quat of
+    internal nodes and the small bits (projected-size pass); in the blocks the
+    selection pass reads (all of them without boxes), the parent of every node
+    and the mean of every leaf that no small ancestor culls; the selection
+    mask and the compacted ids."""
     N, span = tree.n_nodes, tree.n_internal_span
     small = ((small_words[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1).reshape(-1)[:span].astype(bool)
     culled = np.zeros(N, bool)
@@ -75,8 +101,9 @@ def filter_bytes(tree, small_words, n_sel):
         a, b = offs[lvl], offs[lvl + 1]
         p = tree.parent[a:b]
         culled[a:b] = culled[p] | small[p]
-    leaves_tested = int((~culled[span:]).sum())
-    return (4 * N + 41 * span + span // 8 + 12 * leaves_tested + N // 8 + 4 * n_sel), leaves_tested
+    read = np.ones(N, bool) if read_blocks is None else np.repeat(read_blocks, FILTER_BLOCK)[:N]
+    leaves_tested = int((~culled[span:] & read[span:]).sum())
+    return (4 * int(read.sum()) + 41 * span + span // 8 + 12 * leaves_tested + N // 8 + 4 * n_sel), leaves_tested
 
 
 def sort_bytes(n_sel, n_vis, n_pairs, tile_passes, n_tiles):
@@ -671,7 +698,11 @@ def main():
         n_sel, n_pairs, status = fg.read_counts(fb)
         assert status == 0, f"frame {k}: status {status}"
         words = fb.filter_ws[: 4 * ((tree.n_internal_span + 31) // 32)].cpu().numpy().view(np.uint32)
-        fbytes, leaves_tested = filter_bytes(tree, words, n_sel)
+        rb = None
+        if dtree.tile_box is not None:
+            nb = (tree.n_nodes + FILTER_BLOCK - 1) // FILTER_BLOCK
+            rb = blocks_read(dtree.tile_box[:8 * nb].cpu().numpy().reshape(-1, 8), cams[k])
+        fbytes, leaves_tested = filter_bytes(tree, words, n_sel, rb)
         s = stats.cpu().numpy().astype(np.float64)
         n_tiles = cams[k].n_tiles
         passes = int(np.ceil(max(1, int(n_tiles - 1).bit_length()) / 8))
