@@ -123,7 +123,7 @@ typedef struct fg_tree {
  * axis-aligned box of each block's means, and the filter skips a block whose
  * box lies outside every view's frustum by a margin above float32 rounding
  * (none of its nodes could pass), reading none of its nodes in the selection
- * pass. A
+ * pass and no attributes of its internal nodes in the projected-size pass. A
  * block holding a parent link the filter would reject gets a NaN box and is
  * never skipped, so FG_STATUS_BAD_PARENT is reported as without boxes.
  * The same array also holds, per 256 consecutive nodes below n_internal_span,

@@ -115,12 +115,28 @@ __global__ __launch_bounds__(kBlock) void k_small(const float* __restrict__ mean
                                                   int64_t N, int64_t span, CamSet cams,
                                                   const fg_camera* __restrict__ dcams, int nv, float tau_R,
                                                   uint32_t* __restrict__ small_bits, int64_t words,
+                                                  const float4* __restrict__ tile_box,
                                                   uint32_t* __restrict__ status, bool reset_status)
 {
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (n == 0 && reset_status) *status = 0u;  // before any later kernel of the call sets a bit
+    // nodes of a k_select tile whose box is outside every view are not in
+    // the frustum, so none of them is small
+    bool out = false;
+    if (tile_box) {
+        const int64_t tile = ((int64_t)blockIdx.x * kBlock) / kTileNodes;
+        const float4 lo = tile_box[2 * tile], hi = tile_box[2 * tile + 1];
+        out = true;
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            if (v >= nv) break;
+            fgd::Cam cam = cams.c[v];
+            if (dcams) fgd::pose_from(cam, dcams + v);
+            out = out && box_outside(cam, lo, hi);
+        }
+    }
     uint32_t small = 0;  // bit v: small in view v
-    if (n < span && !(flags[n] & 1u)) {
+    if (!out && n < span && !(flags[n] & 1u)) {
         const float mx = mean[n], my = mean[N + n], mz = mean[2 * N + n];
         float S[6];
         bool have_cov = false;
@@ -601,7 +617,8 @@ void launch_pass(const fg_tree* tree, const CamSet& cs, const fg_camera* dcams, 
     if (span > 0) {
         const dim3 g((unsigned)((span + kBlock - 1) / kBlock));
         hipLaunchKernelGGL(k_small<NV>, g, dim3(kBlock), 0, s, tree->mean, tree->scale, tree->quat, tree->flags, N,
-                           span, cs, dcams, nv, tau_R, w.small_bits, w.words, status, reset_status);
+                           span, cs, dcams, nv, tau_R, w.small_bits, w.words, (const float4*)tree->tile_box, status,
+                           reset_status);
         const float4* box = (const float4*)tree->tile_box;
         const int2* crange = box ? (const int2*)(box + 2 * n_tiles) : nullptr;
         hipLaunchKernelGGL(k_blocked<NV>, g, dim3(kBlock), 0, s, tree->parent, tree->flags, w.small_bits, w.words,
