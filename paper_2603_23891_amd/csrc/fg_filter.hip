@@ -489,51 +489,65 @@ __global__ __launch_bounds__(kBlock) void k_select(const float* __restrict__ mea
 }
 
 // One workgroup per view: tile_cnt[v][0 .. n_tiles) becomes its exclusive
-// prefix sum in place; n_sel[v] = the total. Each thread takes a run of
-// consecutive tiles, read 8 at a time with independent loads.
+// prefix sum in place; n_sel[v] = the total. Rounds of 8 x 1024 counts: each
+// round is loaded and stored with consecutive lanes on consecutive words and
+// transposed through LDS, so that every thread scans 8 consecutive counts.
+constexpr int kScanPer = 8;
+constexpr int kScanRound = kScanPer * kScanThreads;
+
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t* __restrict__ tile_cnt, int64_t n_tiles,
                                                             uint32_t* __restrict__ n_sel, int64_t cap_sel,
                                                             uint32_t* __restrict__ status)
 {
+    __shared__ uint32_t s_buf[kScanRound];
     __shared__ uint32_t s_wave[kScanThreads / fgd::kWave];
     uint32_t* row = tile_cnt + (int64_t)blockIdx.x * n_tiles;
     const int tid = threadIdx.x, lane = fgd::lane_id(), wave = tid / fgd::kWave;
-    const int64_t per = (n_tiles + kScanThreads - 1) / kScanThreads;
-    const int64_t lo = tid * per, hi = lo + per < n_tiles ? lo + per : n_tiles;
-    uint32_t s = 0;
-    for (int64_t i0 = lo; i0 < hi; i0 += 8) {
-        uint32_t c[8];
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < n_tiles; base += kScanRound) {
 #pragma unroll
-        for (int u = 0; u < 8; u++) c[u] = i0 + u < hi ? row[i0 + u] : 0u;
-#pragma unroll
-        for (int u = 0; u < 8; u++) s += c[u];
-    }
-    uint32_t x = s;
-#pragma unroll
-    for (int d = 1; d < fgd::kWave; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, fgd::kWave);
-        if (lane >= d) x += y;
-    }
-    if (lane == fgd::kWave - 1) s_wave[wave] = x;
-    __syncthreads();
-    uint32_t run = x - s, total = 0;
-    for (int w = 0; w < kScanThreads / fgd::kWave; w++) {
-        if (w < wave) run += s_wave[w];
-        total += s_wave[w];
-    }
-    for (int64_t i0 = lo; i0 < hi; i0 += 8) {
-        uint32_t c[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) c[u] = i0 + u < hi ? row[i0 + u] : 0u;
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-            if (i0 + u < hi) row[i0 + u] = run;
-            run += c[u];
+        for (int k = 0; k < kScanPer; k++) {
+            const int64_t i = base + k * kScanThreads + tid;
+            s_buf[k * kScanThreads + tid] = i < n_tiles ? row[i] : 0u;
         }
+        __syncthreads();
+        uint32_t c[kScanPer];
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; k++) {
+            c[k] = s_buf[tid * kScanPer + k];
+            s += c[k];
+        }
+        uint32_t x = s;
+#pragma unroll
+        for (int d = 1; d < fgd::kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, fgd::kWave);
+            if (lane >= d) x += y;
+        }
+        if (lane == fgd::kWave - 1) s_wave[wave] = x;
+        __syncthreads();
+        uint32_t run = carry + x - s, total = 0;
+        for (int w = 0; w < kScanThreads / fgd::kWave; w++) {
+            if (w < wave) run += s_wave[w];
+            total += s_wave[w];
+        }
+#pragma unroll
+        for (int k = 0; k < kScanPer; k++) {
+            s_buf[tid * kScanPer + k] = run;
+            run += c[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kScanPer; k++) {
+            const int64_t i = base + k * kScanThreads + tid;
+            if (i < n_tiles) row[i] = s_buf[k * kScanThreads + tid];
+        }
+        carry += total;
+        __syncthreads();  // s_buf and s_wave are reused by the next round
     }
     if (tid == 0) {
-        n_sel[blockIdx.x] = total;
-        if ((int64_t)total > cap_sel) atomicOr(status, FG_STATUS_SEL_OVERFLOW);
+        n_sel[blockIdx.x] = carry;
+        if ((int64_t)carry > cap_sel) atomicOr(status, FG_STATUS_SEL_OVERFLOW);
     }
 }
 
