@@ -184,9 +184,11 @@ def measure_graph_flythrough(torch, dtree, cams, tau_R, tau, K):
 
 def measure_gtc_prepass(torch, dtree, fb, tau_golden, G_golden):
     """The GTC pre-pass (Fig. 2(b)) on the GPU over the scene's 8 training
-    views: filter, 3-sigma preprocess, sort and fg_gtc per view, then
-    tau = lambda_G / G_bar (Eq. (8)) on the device; checked against the stored
-    tau of the oracle's pre-pass."""
+    views: filter, 3-sigma preprocess, sort, a blend with saved chunk state
+    and the chunk-parallel fg_gtc per view, then tau = lambda_G / G_bar
+    (Eq. (8)) on the device; checked against the stored tau of the oracle's
+    pre-pass. Also timed on the last view: the KPC stage (that blend and the
+    KPC walk) and the walk with one workgroup per tile instead."""
     from paper_2603_23891_amd import fg, synth
     views = synth.city20m_training_views(8)
     gb = fg.GtcBuffers(fb, len(views))
@@ -202,18 +204,23 @@ def measure_gtc_prepass(torch, dtree, fb, tau_golden, G_golden):
     torch.cuda.synchronize()
     ms = e[0].elapsed_time(e[1]) / reps
     assert not gb.status.any(), gb.status
-    # the KPC kernel alone, on the last view's sorted pairs
-    ek = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ek[0].record(stream)
-    for _ in range(reps):
-        fg.gtc_view_stage(views[-1], fb, gb, len(views) - 1)
-    ek[1].record(stream)
-    torch.cuda.synchronize()
+    # the KPC stage alone, on the last view's sorted pairs: chunk-parallel
+    # (blend with saved state, then the walk) and one workgroup per tile
+    stage_ms = []
+    for chunked in (True, False):
+        ek = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ek[0].record(stream)
+        for _ in range(reps):
+            fg.gtc_view_stage(views[-1], fb, gb, len(views) - 1, chunked=chunked)
+        ek[1].record(stream)
+        torch.cuda.synchronize()
+        stage_ms.append(ek[0].elapsed_time(ek[1]) / reps)
     n_pairs_last = fg.read_counts(fb)[1]
     tau = float(gb.tau.item())
     out = dict(views=len(views), ms=ms, ms_per_view=ms / len(views), tau=tau, G_bar=float(gb.g_bar.item()),
                tau_stored=tau_golden, G_bar_stored=G_golden, tau_rel_err=abs(tau - tau_golden) / tau_golden,
-               kpc_kernel_ms_last_view=ek[0].elapsed_time(ek[1]) / reps, pairs_last_view=n_pairs_last,
+               kpc_stage_ms_last_view=stage_ms[0], kpc_tile_walk_ms_last_view=stage_ms[1],
+               pairs_last_view=n_pairs_last,
                workload="8 training views of the 20M-node city, 1920x1080, 3-sigma extents")
     log(f"GTC pre-pass: {ms:.2f} ms for 8 views, tau {tau:.7f} (stored {tau_golden:.7f})")
     assert out["tau_rel_err"] <= 5e-6, out

@@ -391,10 +391,21 @@ int fg_render(const fg_splats* splats, const uint32_t* vals, const uint32_t* ran
  * n_pairs (device) and cap_pairs are the sort's pair count and capacity:
  * when the sort overflowed (n_pairs > cap_pairs) every tile is left undefined
  * and view_gtc = (NaN, -1), which fg_gtc_tau reports as an overflow.
- * Errors: FG_ERR_INVALID_ARG (null pointers, bad edges). */
+ * With n_contrib, render_ws, render_ws_bytes and tune all NULL/0, each tile's
+ * list is walked front to back by one workgroup. When the view was also
+ * rendered by fg_render (same sort, camera and cap_pairs) with a tune that
+ * sets save_state, passing that call's n_contrib, ws and tune splits the long
+ * lists into their chunks: each chunk is walked from the transmittance the
+ * blend saved after the previous one, and a fragment counts exactly when its
+ * list position is below the pixel's contributor count and it passes the
+ * skip tests, so every alpha * T and every per-pair sum is the same as in
+ * the tile walk, with the long tiles no longer on one workgroup.
+ * Errors: FG_ERR_INVALID_ARG (null pointers, bad edges, a render workspace
+ * that does not match or holds no saved state). */
 int fg_gtc(const fg_splats* splats, const uint32_t* vals, const uint32_t* ranges, const fg_camera* cam,
            const uint32_t* n_pairs, int64_t cap_pairs, float* kpc, float* tile_gtc, double* view_gtc, const float* hist_edges,
-           int32_t n_edges, uint32_t* kpc_hist, void* stream);
+           int32_t n_edges, uint32_t* kpc_hist, const uint32_t* n_contrib, const void* render_ws,
+           size_t render_ws_bytes, const fg_tune* tune, void* stream);
 
 /* Eq. (8) over n_views views: view_gtc [n_views][2] (device float64, each
  * written by fg_gtc); g_bar (device float64) = the mean view GTC over the

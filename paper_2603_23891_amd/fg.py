@@ -118,7 +118,7 @@ def lib():
         L.fg_render_workspace_size.argtypes = [vp, C.c_int32, i64, vp]
         L.fg_render.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp, i64, vp, vp, vp, C.c_size_t, vp, vp]
         L.fg_gtc.restype = i32
-        L.fg_gtc.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, C.c_int32, vp, vp]
+        L.fg_gtc.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, C.c_int32, vp, vp, vp, C.c_size_t, vp, vp]
         L.fg_gtc_tau.restype = i32
         L.fg_gtc_tau.argtypes = [vp, C.c_int32, f32, vp, vp, vp, vp]
         L.fg_activate.restype = i32
@@ -355,13 +355,17 @@ def fg_render(splats: Splats, vals, ranges, cams, bg: Sequence[float], image, fi
 
 
 def fg_gtc(splats: Splats, vals, ranges, cam, n_pairs, cap_pairs: int, kpc, tile_gtc, view_gtc, hist_edges=None,
-           kpc_hist=None, stream=None):
-    """hist_edges: None or a sequence of ascending floats (host); kpc_hist the device counts."""
+           kpc_hist=None, stream=None, n_contrib=None, render_ws=None, tune: Optional[FgTune] = None):
+    """hist_edges: None or a sequence of ascending floats (host); kpc_hist the
+    device counts. n_contrib, render_ws, tune: those of an fg_render of the
+    same view with saved state (chunk-parallel walk), or all None."""
     ss, cs = splats.struct(), camera_struct(cam)
     n_e = 0 if hist_edges is None else len(hist_edges)
     ev = (C.c_float * max(n_e, 1))(*([float(e) for e in hist_edges] if n_e else [0.0]))
+    ws_bytes = 0 if render_ws is None else render_ws.numel() * render_ws.element_size()
     _check(lib().fg_gtc(_ref(ss), _p(vals), _p(ranges), _ref(cs), _p(n_pairs), cap_pairs, _p(kpc), _p(tile_gtc), _p(view_gtc),
-                        C.cast(ev, C.c_void_p) if n_e else None, n_e, _p(kpc_hist), _stream(stream)), "fg_gtc")
+                        C.cast(ev, C.c_void_p) if n_e else None, n_e, _p(kpc_hist), _p(n_contrib), _p(render_ws),
+                        ws_bytes, _ref(tune) if tune is not None else None, _stream(stream)), "fg_gtc")
 
 
 def fg_gtc_tau(view_gtc, n_views: int, lambda_G: float, g_bar, tau, status=None, stream=None):
@@ -452,6 +456,15 @@ class GtcBuffers:
 
     def __init__(self, fb: FrameBuffers, n_views: int = 1, device="cuda"):
         self.kpc = torch.empty(max(fb.cap_pairs, 1), dtype=torch.float32, device=device)
+        # workspace of the blend run with saved state before each view's KPC walk
+        self.tune = tune_struct(0, save_state=True)
+
+        class _C:  # camera of this size, only for the workspace query
+            R = np.eye(3, dtype=np.float32).reshape(9); t = np.zeros(3, np.float32); campos = t
+            fx = fy = cx = cy = 1.0; znear = 0.2; kx = ky = 1.0; tile_base = 0
+        _C.width, _C.height = fb.width, fb.height
+        self.render_ws = torch.empty(fg_render_workspace_size(_C, fb.cap_pairs, self.tune), dtype=torch.uint8,
+                                     device=device)
         self.tile_gtc = torch.empty(fb.ranges.shape[0], dtype=torch.float32, device=device)
         self.view_gtc = torch.zeros((n_views, 2), dtype=torch.float64, device=device)
         self.g_bar = torch.zeros(1, dtype=torch.float64, device=device)
@@ -460,9 +473,18 @@ class GtcBuffers:
 
 
 def gtc_view_stage(cam, fb: FrameBuffers, gb: GtcBuffers, v: int = 0, hist_edges=None, kpc_hist=None,
-                   stream=None):
-    fg_gtc(fb.splats, fb.vals, fb.ranges, cam, fb.n_pairs, fb.cap_pairs, gb.kpc, gb.tile_gtc, gb.view_gtc[v],
-           hist_edges, kpc_hist, stream)
+                   stream=None, chunked: bool = True, status=None):
+    """KPC, tile and view GTC of the view sorted into fb. chunked: first blend
+    the view with saved state (into fb's image planes) so that the KPC walk
+    runs chunk-parallel; else one workgroup walks each tile's whole list."""
+    if chunked:
+        fg_render(fb.splats, fb.vals, fb.ranges, cam, (0.0, 0.0, 0.0), fb.image, fb.final_T, fb.n_contrib,
+                  fb.cap_pairs, None, fb.status if status is None else status, gb.render_ws, gb.tune, stream)
+        fg_gtc(fb.splats, fb.vals, fb.ranges, cam, fb.n_pairs, fb.cap_pairs, gb.kpc, gb.tile_gtc, gb.view_gtc[v],
+               hist_edges, kpc_hist, stream, fb.n_contrib, gb.render_ws, gb.tune)
+    else:
+        fg_gtc(fb.splats, fb.vals, fb.ranges, cam, fb.n_pairs, fb.cap_pairs, gb.kpc, gb.tile_gtc, gb.view_gtc[v],
+               hist_edges, kpc_hist, stream)
 
 
 def scene_tau(tree: DeviceTree, cams, fb: FrameBuffers, lambda_G: float = 0.2, tau_R: float = 3.0,
@@ -480,7 +502,7 @@ def scene_tau(tree: DeviceTree, cams, fb: FrameBuffers, lambda_G: float = 0.2, t
         fg_preprocess(tree, cam, 0.0, fb.sel_idx, fb.n_sel, fb.cap_sel, fb.splats, st, stream)
         fg_sort(fb.splats, fb.n_sel, fb.cap_sel, cam, fb.tile_keys, fb.vals, fb.cap_pairs, fb.n_pairs, fb.ranges, st,
                 fb.sort_ws, None, stream)
-        gtc_view_stage(cam, fb, gb, v, stream=stream)
+        gtc_view_stage(cam, fb, gb, v, stream=stream, status=st)
     n = len(cams)
     fg_gtc_tau(gb.view_gtc, n, lambda_G, gb.g_bar, gb.tau, gb.status[n:n + 1], stream)
     return gb

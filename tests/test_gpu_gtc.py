@@ -33,14 +33,15 @@ def golden():
         return json.load(f)
 
 
-def gpu_view(dtree, cam, fb, tau_R, hist=True):
-    """One view through filter, 3-sigma preprocess, sort and fg_gtc."""
+def gpu_view(dtree, cam, fb, tau_R, hist=True, chunked=True):
+    """One view through filter, 3-sigma preprocess, sort and fg_gtc (by
+    default chunk-parallel, after a blend with saved state)."""
     gb = fg.GtcBuffers(fb, 1)
     fg.filter_stage(dtree, cam, fb, tau_R)
     fg.preprocess_stage(dtree, cam, fb, 0.0)
     fg.sort_stage(cam, fb)
     h = torch.zeros(len(EDGES) + 1, dtype=torch.int32, device="cuda") if hist else None
-    fg.gtc_view_stage(cam, fb, gb, 0, EDGES if hist else None, h)
+    fg.gtc_view_stage(cam, fb, gb, 0, EDGES if hist else None, h, chunked=chunked)
     torch.cuda.synchronize()
     n_sel, n_pairs, status = fg.read_counts(fb)
     assert status == 0
@@ -107,7 +108,10 @@ def test_random_forest_gtc(seed):
 @pytest.mark.parametrize("opacity_logit_mu", [-3.0, 1.0])
 def test_heavy_tiles_gtc(opacity_logit_mu):
     """Thousands of small splats on a few tiles, translucent (no termination)
-    and opaque (whole tiles terminate: their later pairs get 0 unvisited)."""
+    and opaque (whole tiles terminate: their later pairs get 0 unvisited).
+    Both walks: chunk-parallel from the blend's saved state, and one
+    workgroup per tile; they also agree with each other to float32 rounding
+    of the per-splat sums (the four waves' sums meet in an LDS atomic)."""
     rng = np.random.default_rng(7)
     n = 12000
     cam = synth.make_camera(np.eye(3), (0, 0, 0), 200, 120)
@@ -128,6 +132,13 @@ def test_heavy_tiles_gtc(opacity_logit_mu):
     if opacity_logit_mu > 0:
         assert np.sum(o["kpc"] == 0) > 1000  # pairs behind terminated pixels
     assert_gtc_parity(g, o)
+    t = gpu_view(dt, cam, fb, 3.0, chunked=False)
+    assert_gtc_parity(t, o)
+    assert np.all(np.abs(g["kpc"] - t["kpc"]) <= 1e-6 * np.abs(t["kpc"]) + 1e-9)
+    m = ~np.isnan(t["tile"])
+    assert np.array_equal(np.isnan(g["tile"]), np.isnan(t["tile"]))
+    assert np.all(np.abs(g["tile"][m] - t["tile"][m]) <= 1e-6 * np.abs(t["tile"][m]) + 1e-9)
+    assert g["view"][1] == t["view"][1] and abs(g["view"][0] - t["view"][0]) <= 1e-6 * abs(t["view"][0])
 
 
 def test_city_block_ragged_gtc():
