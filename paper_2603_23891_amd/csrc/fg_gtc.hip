@@ -17,6 +17,10 @@
 //               tile's pairs to tile_gtc[t] (Eq. (6): pairs with zero
 //               contribution count), and tiles with pairs add G_t and 1 to the
 //               view's two float64 accumulators.
+//   k_kpc_items the same KPC when the view was blended with saved
+//               per-chunk state: the chunks of long lists walk in parallel
+//               from the saved transmittance, the other tiles whole;
+//               k_tile_gtc then forms each tile's GTC from the pairs' KPC.
 //   k_gtc_view  turns the accumulators into the view GTC of Eq. (7).
 //   k_gtc_tau   mean of the view GTCs over the views that hold pairs, and
 //               tau = lambda_G / G_bar.
