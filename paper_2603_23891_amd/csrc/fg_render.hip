@@ -12,14 +12,15 @@
 //             splats) is one work item: per-pixel bit masks of the splats
 //             whose alpha passes the skip tests there go to global memory.
 //             All chunks run in parallel.
-//   k_render  one workgroup per tile that holds splats (heavy tiles first,
-//             tiles claimed from an atomic ticket): one pixel per lane walks
-//             the tile's splats in list order, chunk by chunk, visiting only
-//             the marked ones and recomputing alpha with the same
-//             expressions, so every value and decision is bit-identical to
-//             one sequential pass. Light tiles compute their single chunk's
-//             masks in place. In a heavy tile each wave walks the chunks for
-//             its own 64 pixels at its own pace.
+//   k_render  one workgroup per light tile and per half of a heavy tile
+//             (heavy work first, items claimed from an atomic ticket): each
+//             pixel walks the tile's splats in list order, chunk by chunk,
+//             visiting only the marked ones and recomputing alpha with the
+//             same expressions, so every value and decision is bit-identical
+//             to one sequential pass. Light tiles (one lane per pixel)
+//             compute their single chunk's masks in place. In a heavy tile
+//             each wave walks the chunks for its own 32 pixels at its own
+//             pace, two lanes per pixel sharing the alphas.
 //
 // Before them, k_schedule counts each tile's chunks and orders the tiles that
 // hold splats, and k_tile_prep writes the pixels of the others (background,
@@ -137,8 +138,9 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(int64_t n_tiles, RenderV
 // order[] in tile order and light ones from its back in reverse tile order;
 // numbers the mask items of heavy tiles (first item per tile) and resets the
 // ticket.
-// Work item i of the blend is order[i] for i < heavy tiles, else
-// order[n_tiles - 1 - (i - heavy tiles)]. 8 consecutive tiles per thread per
+// With h heavy tiles, work item i of the blend is part i % L of heavy tile
+// order[i / L] for i < L h (L = kHeavyLanes parts per heavy tile), else the
+// light tile order[n_tiles - 1 - (i - L h)]. 8 consecutive tiles per thread per
 // round (the ranges are read and the chunk counts written with consecutive
 // lanes on consecutive tiles, and handed over through LDS); the running
 // counts of heavy and light tiles (one 64-bit word) and of mask items are
@@ -705,10 +707,56 @@ __device__ __forceinline__ void blend_step(PixelState& p, bool valid, float alph
 // time and their alphas (independent of T) computed together, so their LDS
 // reads and arithmetic overlap; the blend steps then run strictly in list
 // order.
-template <int CHUNK, bool STATS, int STRIDE>
+//
+// With LPP > 1 lanes per pixel (heavy tiles), the LPP lanes of a pixel hold
+// the same mask words and state and run the same steps in lockstep; lane
+// `sub` of the pixel computes the alphas of group positions sub, sub + LPP,
+// ..., and the group's alphas are exchanged across the pixel's lanes (which
+// lie 64 / LPP apart) before the blend steps, so each lane evaluates 4 / LPP
+// exponentials per group instead of 4. Every lane then applies the same
+// steps to the same values, and the results equal the one-lane walk's.
+template <int LPP>
+__device__ __forceinline__ void group_alphas(const float2* s_xy, const float4* s_co, float fpx, float fpy, int sub,
+                                             int j0, int j1, int j2, int j3, float& a0, float& a1, float& a2,
+                                             float& a3)
+{
+    constexpr int P = fgd::kWave / LPP;
+    if constexpr (LPP == 1) {
+        a0 = passed_alpha(s_xy[j0], s_co[j0], fpx, fpy);
+        a1 = passed_alpha(s_xy[j1], s_co[j1], fpx, fpy);
+        a2 = passed_alpha(s_xy[j2], s_co[j2], fpx, fpy);
+        a3 = passed_alpha(s_xy[j3], s_co[j3], fpx, fpy);
+    } else if constexpr (LPP == 2) {
+        const int ja = sub ? j1 : j0, jb = sub ? j3 : j2;
+        const float ma = passed_alpha(s_xy[ja], s_co[ja], fpx, fpy);
+        const float mb = passed_alpha(s_xy[jb], s_co[jb], fpx, fpy);
+        const float oa = __shfl_xor(ma, P, fgd::kWave);
+        const float ob = __shfl_xor(mb, P, fgd::kWave);
+        a0 = sub ? oa : ma;
+        a1 = sub ? ma : oa;
+        a2 = sub ? ob : mb;
+        a3 = sub ? mb : ob;
+    } else {
+        static_assert(LPP == 4, "1, 2 or 4 lanes per pixel");
+        const int jm = sub == 0 ? j0 : sub == 1 ? j1 : sub == 2 ? j2 : j3;
+        const float m = passed_alpha(s_xy[jm], s_co[jm], fpx, fpy);
+        // the alpha of position k sits on the pixel's lane k, i.e. at lane
+        // distance (k ^ sub) * P
+        const float x1 = __shfl_xor(m, P, fgd::kWave);
+        const float x2 = __shfl_xor(m, 2 * P, fgd::kWave);
+        const float x3 = __shfl_xor(m, 3 * P, fgd::kWave);
+        const auto pick = [&](int d) { return d == 0 ? m : d == 1 ? x1 : d == 2 ? x2 : x3; };
+        a0 = pick(sub);
+        a1 = pick(1 ^ sub);
+        a2 = pick(2 ^ sub);
+        a3 = pick(3 ^ sub);
+    }
+}
+
+template <int CHUNK, bool STATS, int STRIDE, int LPP = 1>
 __device__ __forceinline__ void walk(const uint32_t* mcol, const float2* s_xy, const float4* s_co,
                                      const float4* s_rgb, float fpx, float fpy, uint32_t base, PixelState& p,
-                                     Frag& f)
+                                     Frag& f, int sub = 0)
 {
     constexpr int kPairs = CHUNK / 64;
     uint32_t summary = 0;
@@ -733,10 +781,8 @@ __device__ __forceinline__ void walk(const uint32_t* mcol, const float2* s_xy, c
             const bool v3 = m != 0ull;
             const int j3 = v3 ? b + __builtin_ctzll(m) : j0;
             m &= m - 1ull;
-            const float a0 = passed_alpha(s_xy[j0], s_co[j0], fpx, fpy);
-            const float a1 = passed_alpha(s_xy[j1], s_co[j1], fpx, fpy);
-            const float a2 = passed_alpha(s_xy[j2], s_co[j2], fpx, fpy);
-            const float a3 = passed_alpha(s_xy[j3], s_co[j3], fpx, fpy);
+            float a0, a1, a2, a3;
+            group_alphas<LPP>(s_xy, s_co, fpx, fpy, sub, j0, j1, j2, j3, a0, a1, a2, a3);
             const float4 c0 = s_rgb[j0], c1 = s_rgb[j1], c2 = s_rgb[j2], c3 = s_rgb[j3];
             blend_step<STATS>(p, true, a0, c0, base + (uint32_t)j0, f);
             blend_step<STATS>(p, v1, a1, c1, base + (uint32_t)j1, f);
@@ -783,7 +829,7 @@ __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ xy, const
                                             const float4* __restrict__ rgb_depth, const uint32_t* __restrict__ masks,
                                             uint32_t r0, uint32_t r1, uint32_t chunk,
                                             const uint32_t (&g)[ChunkRegs<CHUNK>::S], uint32_t mf,
-                                            uint32_t n_mask_items, ChunkRegs<CHUNK>& R)
+                                            uint32_t n_mask_items, int pix, ChunkRegs<CHUNK>& R)
 {
     const int cnt = chunk_count<CHUNK>(r0, r1, chunk);
 #pragma unroll
@@ -802,7 +848,7 @@ __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ xy, const
     if (mf + chunk < n_mask_items) {
         const uint32_t* src = masks + (size_t)(mf + chunk) * (CHUNK / 32 * kThreads);
 #pragma unroll
-        for (int w = 0; w < CHUNK / 32; w++) R.m[w] = src[w * kThreads + threadIdx.x];
+        for (int w = 0; w < CHUNK / 32; w++) R.m[w] = src[w * kThreads + pix];
     } else {
 #pragma unroll
         for (int w = 0; w < CHUNK / 32; w++) R.m[w] = 0u;
@@ -818,14 +864,17 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Pass masks of a staged chunk for the 64 pixels of one wave (rows y0 ..
-// y0 + 3 of the tile), when the chunk's masks were not stored: each lane
-// takes every 64th splat and tests the pixels of its box in those rows.
-// w_mask [word][64] is zero on entry.
-template <bool STATS>
+// Pass masks of a staged chunk for the 64 / LPP pixels of one wave (rows
+// y0 .. y0 + 4 / LPP - 1 of the tile), when the chunk's masks were not
+// stored: each lane takes every 64th splat and tests the pixels of its box
+// in those rows. w_mask [word][64] is zero on entry; a pixel's bits go to
+// each of its LPP lanes' columns.
+template <bool STATS, int LPP>
 __device__ __forceinline__ void wave_masks(const float2* w_xy, const float4* w_co, int cnt, int tx, int ty, int W,
                                            int H, int y0, uint32_t* w_mask, Frag& f)
 {
+    constexpr int P = fgd::kWave / LPP;
+    constexpr int kRows = P / fgd::kTile;
     for (int j = fgd::lane_id(); j < cnt; j += fgd::kWave) {
         const float2 mm = w_xy[j];
         const float4 co = w_co[j];
@@ -833,7 +882,7 @@ __device__ __forceinline__ void wave_masks(const float2* w_xy, const float4* w_c
         const int x0 = (int)(b & 255u), x1 = (int)((b >> 8) & 255u);
         const int by0 = (int)((b >> 16) & 255u), by1 = (int)(b >> 24);
         if (x0 > x1) continue;
-        const int ya = by0 > y0 ? by0 : y0, yb = by1 < y0 + 3 ? by1 : y0 + 3;
+        const int ya = by0 > y0 ? by0 : y0, yb = by1 < y0 + kRows - 1 ? by1 : y0 + kRows - 1;
         const uint32_t bit = 1u << (j & 31);
         uint32_t* mrow = w_mask + (j >> 5) * fgd::kWave;
         for (int ly = ya; ly <= yb; ly++) {
@@ -842,14 +891,22 @@ __device__ __forceinline__ void wave_masks(const float2* w_xy, const float4* w_c
             row_span(mm, co, fy, tx, a, b);
             for (int lx = a; lx <= b; lx++) {
                 float alpha;
-                if (pixel_alpha<STATS>(mm, co, (float)(tx * fgd::kTile + lx) + 0.5f, fy, alpha, f))
-                    atomicOr(&mrow[(ly - y0) * fgd::kTile + lx], bit);
+                if (pixel_alpha<STATS>(mm, co, (float)(tx * fgd::kTile + lx) + 0.5f, fy, alpha, f)) {
+#pragma unroll
+                    for (int c = 0; c < LPP; c++) atomicOr(&mrow[c * P + (ly - y0) * fgd::kTile + lx], bit);
+                }
             }
         }
     }
 }
 
-template <int CHUNK, bool STATS>
+// Lanes per pixel in a heavy tile's walk: a heavy tile is kHeavyLanes work
+// items of 256 / kHeavyLanes pixels each. Two halve the exponentials on the
+// heavy tiles' critical path; four cost more in staging (every wave stages
+// whole chunks) than they save.
+constexpr int kHeavyLanes = 2;
+
+template <int CHUNK, bool STATS, int LPP>
 __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
                                                      const float4* __restrict__ rgb_depth,
                                                      const uint32_t* __restrict__ vals,
@@ -871,18 +928,25 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
     __shared__ uint32_t s_pref[CHUNK + 1];
     __shared__ uint32_t s_wave[kWaves];
     __shared__ uint32_t s_item;
+    constexpr int P = fgd::kWave / LPP;  // pixels per wave in a heavy tile
     const int tid = threadIdx.x;
-    const int lx = tid % fgd::kTile, ly = tid / fgd::kTile;
+    const int wave = tid / fgd::kWave, lane = fgd::lane_id();
+    const int sub = lane / P;  // this lane's place among its pixel's lanes (heavy tiles)
     const uint32_t n_mask_items = ws.counters[2];
-    const uint32_t n_work = ws.counters[3];
+    const uint32_t n_heavy = ws.counters[1];
+    // each heavy tile is LPP items (parts of 256 / LPP pixels), each light tile one
+    const uint32_t n_work = ws.counters[3] + (uint32_t)(LPP - 1) * n_heavy;
     Frag f = {0, 0, 0, 0};
     if (tid == 0) s_item = atomicAdd(&ws.counters[0], 1u);
     __syncthreads();
-    const uint32_t n_heavy = ws.counters[1];
     for (;;) {
         const uint32_t item = s_item;
         if (item >= n_work) break;
-        const uint32_t tile = ws.order[item < n_heavy ? (int64_t)item : n_tiles - 1 - (int64_t)(item - n_heavy)];
+        const bool heavy_item = item < (uint32_t)LPP * n_heavy;
+        const uint32_t tile = ws.order[heavy_item ? (int64_t)(item / LPP)
+                                                  : n_tiles - 1 - (int64_t)(item - (uint32_t)LPP * n_heavy)];
+        const int pix = heavy_item ? (int)(item % LPP) * (kThreads / LPP) + wave * P + lane % P : tid;
+        const int lx = pix % fgd::kTile, ly = pix / fgd::kTile;
         const uint32_t r0 = ranges[2 * tile], r1 = ranges[2 * tile + 1];
         const uint32_t nch = ws.nch[tile];
         // Tiles are ordered heavy first, so a light tile is followed only by
@@ -915,12 +979,11 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
             __syncthreads();
             walk<CHUNK, STATS, kThreads>(s_mask + tid, s_xy, s_co, s_rgb, fpx, fpy, 0u, p, f);
         } else {
-            // heavy tile: each wave walks the chunks for its own 64 pixels at
-            // its own pace, with its own staging area, so no wave waits on the
+            // heavy tile: each wave walks the chunks for its own 64 / LPP
+            // pixels at its own pace, with its own staging area, so no wave waits on the
             // others between chunks. While one chunk is walked, the next
             // chunk's splat records and stored masks are loaded into
             // registers, and the indices of the chunk after it.
-            const int wave = tid / fgd::kWave, lane = fgd::lane_id();
             float2* w_xy = s_xy + wave * CHUNK;
             float4* w_co = s_co + wave * CHUNK;
             float4* w_rgb = s_rgb + wave * CHUNK;
@@ -930,9 +993,10 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
             {
                 uint32_t g0[ChunkRegs<CHUNK>::S];
                 fetch_vals<CHUNK>(vals, r0, r1, 0u, g0);
-                fetch_chunk<CHUNK>(xy, conic_o, rgb_depth, ws.masks, r0, r1, 0u, g0, mf, n_mask_items, R);
+                fetch_chunk<CHUNK>(xy, conic_o, rgb_depth, ws.masks, r0, r1, 0u, g0, mf, n_mask_items, pix, R);
                 fetch_vals<CHUNK>(vals, r0, r1, 1u, gnext);
             }
+            const unsigned n_blend0 = f.n_blend;
             uint32_t chunk = 0;
             for (; chunk < nch; chunk++) {
                 // the wave stops once all of its pixels have terminated
@@ -955,34 +1019,36 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
                 wave_sync();
                 if (chunk + 1 < nch) {
                     fetch_chunk<CHUNK>(xy, conic_o, rgb_depth, ws.masks, r0, r1, chunk + 1, gnext, mf, n_mask_items,
-                                       R);
+                                       pix, R);
                     if (chunk + 2 < nch) fetch_vals<CHUNK>(vals, r0, r1, chunk + 2, gnext);
                 }
                 if (!stored) {  // beyond the mask store: masks computed here
-                    wave_masks<STATS>(w_xy, w_co, cnt, tx, ty, W, H, wave * (fgd::kWave / fgd::kTile), w_mask, f);
+                    wave_masks<STATS, LPP>(w_xy, w_co, cnt, tx, ty, W, H, (pix - lane % P) / fgd::kTile, w_mask, f);
                     wave_sync();
                 }
-                walk<CHUNK, STATS, fgd::kWave>(w_mask + lane, w_xy, w_co, w_rgb, fpx, fpy, chunk * CHUNK, p, f);
-                if (ws.state && stored) {  // per-pixel state after this chunk, for the backward
+                walk<CHUNK, STATS, fgd::kWave, LPP>(w_mask + lane, w_xy, w_co, w_rgb, fpx, fpy, chunk * CHUNK, p, f,
+                                                    sub);
+                if (ws.state && stored && sub == 0) {  // per-pixel state after this chunk, for the backward
                     float* st = ws.state + (size_t)(mf + chunk) * (4 * kThreads);
-                    st[tid] = p.T;
-                    st[kThreads + tid] = p.C0;
-                    st[2 * kThreads + tid] = p.C1;
-                    st[3 * kThreads + tid] = p.C2;
+                    st[pix] = p.T;
+                    st[kThreads + pix] = p.C0;
+                    st[2 * kThreads + pix] = p.C1;
+                    st[3 * kThreads + pix] = p.C2;
                 }
             }
             // the state after every later chunk equals the final one
-            if (ws.state) {
+            if (ws.state && sub == 0) {
                 for (; chunk < nch && mf + chunk < n_mask_items; chunk++) {
                     float* st = ws.state + (size_t)(mf + chunk) * (4 * kThreads);
-                    st[tid] = p.T;
-                    st[kThreads + tid] = p.C0;
-                    st[2 * kThreads + tid] = p.C1;
-                    st[3 * kThreads + tid] = p.C2;
+                    st[pix] = p.T;
+                    st[kThreads + pix] = p.C0;
+                    st[2 * kThreads + pix] = p.C1;
+                    st[3 * kThreads + pix] = p.C2;
                 }
             }
+            if (STATS && sub != 0) f.n_blend = n_blend0;  // a pixel's blends count on its first lane only
         }
-        if (inside) {
+        if (inside && (nch <= 1 || sub == 0)) {
             const size_t o = (size_t)py * W + px;
             const size_t plane = (size_t)W * H;
             float* img = image + 3 * tg.pix0;
@@ -1066,14 +1132,14 @@ void launch(const fg_splats* splats, const uint32_t* vals, const uint32_t* range
     if (frag_stats) {
         hipLaunchKernelGGL((k_masks<CHUNK, true>), dim3(gm), dim3(kThreads), 0, s, xy, co, vals, ranges, V, w,
                            frag_stats);
-        hipLaunchKernelGGL((k_render<CHUNK, true>), dim3(gr), dim3(kThreads), 0, s, xy, co, rgb, vals, ranges, n_tiles,
+        hipLaunchKernelGGL((k_render<CHUNK, true, kHeavyLanes>), dim3(gr), dim3(kThreads), 0, s, xy, co, rgb, vals, ranges, n_tiles,
                            V, bg[0], bg[1], bg[2], w, image, final_T, n_contrib, frag_stats);
     } else {
         hipLaunchKernelGGL((k_masks<CHUNK, false>), dim3(gm), dim3(kThreads), 0, s, xy, co, vals, ranges, V, w,
                            frag_stats);
         const bool timed = tune && tune->blend_events[0] && tune->blend_events[1];
         if (timed) (void)hipEventRecord((hipEvent_t)tune->blend_events[0], s);
-        hipLaunchKernelGGL((k_render<CHUNK, false>), dim3(gr), dim3(kThreads), 0, s, xy, co, rgb, vals, ranges, n_tiles,
+        hipLaunchKernelGGL((k_render<CHUNK, false, kHeavyLanes>), dim3(gr), dim3(kThreads), 0, s, xy, co, rgb, vals, ranges, n_tiles,
                            V, bg[0], bg[1], bg[2], w, image, final_T, n_contrib, frag_stats);
         if (timed) (void)hipEventRecord((hipEvent_t)tune->blend_events[1], s);
     }
