@@ -12,15 +12,17 @@
 //             splats) is one work item: per-pixel bit masks of the splats
 //             whose alpha passes the skip tests there go to global memory.
 //             All chunks run in parallel.
-//   k_render  one workgroup per light tile and per half of a heavy tile
-//             (heavy work first, items claimed from an atomic ticket): each
+//   k_render  one workgroup per tile, and per half of a heavy tile of 16
+//             or more chunks (heavy work first, items claimed from an atomic
+//             ticket): each
 //             pixel walks the tile's splats in list order, chunk by chunk,
 //             visiting only the marked ones and recomputing alpha with the
 //             same expressions, so every value and decision is bit-identical
 //             to one sequential pass. Light tiles (one lane per pixel)
 //             compute their single chunk's masks in place. In a heavy tile
-//             each wave walks the chunks for its own 32 pixels at its own
-//             pace, two lanes per pixel sharing the alphas.
+//             each wave walks the chunks for its own pixels at its own pace:
+//             64 pixels, or in a split tile 32 with two lanes per pixel
+//             sharing the alphas.
 //
 // Before them, k_schedule counts each tile's chunks and orders the tiles that
 // hold splats, and k_tile_prep writes the pixels of the others (background,
@@ -139,8 +141,9 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(int64_t n_tiles, RenderV
 // numbers the mask items of heavy tiles (first item per tile) and resets the
 // ticket.
 // With h heavy tiles, work item i of the blend is part i % L of heavy tile
-// order[i / L] for i < L h (L = kHeavyLanes parts per heavy tile), else the
-// light tile order[n_tiles - 1 - (i - L h)]. 8 consecutive tiles per thread per
+// order[i / L] for i < L h (L = kHeavyLanes; a heavy tile too short to be
+// split is walked by its part 0, its other parts are empty), else the light
+// tile order[n_tiles - 1 - (i - L h)]. 8 consecutive tiles per thread per
 // round (the ranges are read and the chunk counts written with consecutive
 // lanes on consecutive tiles, and handed over through LDS); the running
 // counts of heavy and light tiles (one 64-bit word) and of mask items are
@@ -900,11 +903,14 @@ __device__ __forceinline__ void wave_masks(const float2* w_xy, const float4* w_c
     }
 }
 
-// Lanes per pixel in a heavy tile's walk: a heavy tile is kHeavyLanes work
-// items of 256 / kHeavyLanes pixels each. Two halve the exponentials on the
-// heavy tiles' critical path; four cost more in staging (every wave stages
-// whole chunks) than they save.
+// Lanes per pixel in the walk of a long heavy tile: such a tile is
+// kHeavyLanes work items of 256 / kHeavyLanes pixels each. Two halve the
+// exponentials on the longest tiles' critical path; four cost more in
+// staging (every wave stages whole chunks) than they save. Only tiles of at
+// least kSplitChunks chunks are split: for shorter ones the doubled staging
+// outweighs the shorter walk (the blend was fastest at 16 among 2 to 48).
 constexpr int kHeavyLanes = 2;
+constexpr int kSplitChunks = 16;
 
 template <int CHUNK, bool STATS, int LPP>
 __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ xy, const float4* __restrict__ conic_o,
@@ -931,7 +937,6 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
     constexpr int P = fgd::kWave / LPP;  // pixels per wave in a heavy tile
     const int tid = threadIdx.x;
     const int wave = tid / fgd::kWave, lane = fgd::lane_id();
-    const int sub = lane / P;  // this lane's place among its pixel's lanes (heavy tiles)
     const uint32_t n_mask_items = ws.counters[2];
     const uint32_t n_heavy = ws.counters[1];
     // each heavy tile is LPP items (parts of 256 / LPP pixels), each light tile one
@@ -945,10 +950,21 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
         const bool heavy_item = item < (uint32_t)LPP * n_heavy;
         const uint32_t tile = ws.order[heavy_item ? (int64_t)(item / LPP)
                                                   : n_tiles - 1 - (int64_t)(item - (uint32_t)LPP * n_heavy)];
-        const int pix = heavy_item ? (int)(item % LPP) * (kThreads / LPP) + wave * P + lane % P : tid;
+        const uint32_t nch = ws.nch[tile];
+        // a heavy tile with fewer than kSplitChunks chunks is walked whole by
+        // its first item, one lane per pixel; its other items are empty
+        const bool split = LPP > 1 && heavy_item && nch >= (uint32_t)kSplitChunks;
+        const int part = heavy_item ? (int)(item % LPP) : 0;
+        if (heavy_item && !split && part != 0) {
+            __syncthreads();
+            if (tid == 0) s_item = atomicAdd(&ws.counters[0], 1u);
+            __syncthreads();
+            continue;
+        }
+        const int sub = split ? lane / P : 0;  // this lane's place among its pixel's lanes
+        const int pix = split ? part * (kThreads / LPP) + wave * P + lane % P : tid;
         const int lx = pix % fgd::kTile, ly = pix / fgd::kTile;
         const uint32_t r0 = ranges[2 * tile], r1 = ranges[2 * tile + 1];
-        const uint32_t nch = ws.nch[tile];
         // Tiles are ordered heavy first, so a light tile is followed only by
         // light ones: its workgroup claims the next tile now, hiding the
         // atomic's latency. A heavy tile's workgroup does not, so no tile
@@ -1023,11 +1039,19 @@ __global__ __launch_bounds__(kThreads) void k_render(const float2* __restrict__ 
                     if (chunk + 2 < nch) fetch_vals<CHUNK>(vals, r0, r1, chunk + 2, gnext);
                 }
                 if (!stored) {  // beyond the mask store: masks computed here
-                    wave_masks<STATS, LPP>(w_xy, w_co, cnt, tx, ty, W, H, (pix - lane % P) / fgd::kTile, w_mask, f);
+                    if (split)
+                        wave_masks<STATS, LPP>(w_xy, w_co, cnt, tx, ty, W, H, (pix - lane % P) / fgd::kTile, w_mask,
+                                               f);
+                    else
+                        wave_masks<STATS, 1>(w_xy, w_co, cnt, tx, ty, W, H, wave * (fgd::kWave / fgd::kTile), w_mask,
+                                             f);
                     wave_sync();
                 }
-                walk<CHUNK, STATS, fgd::kWave, LPP>(w_mask + lane, w_xy, w_co, w_rgb, fpx, fpy, chunk * CHUNK, p, f,
-                                                    sub);
+                if (split)
+                    walk<CHUNK, STATS, fgd::kWave, LPP>(w_mask + lane, w_xy, w_co, w_rgb, fpx, fpy, chunk * CHUNK, p,
+                                                        f, sub);
+                else
+                    walk<CHUNK, STATS, fgd::kWave, 1>(w_mask + lane, w_xy, w_co, w_rgb, fpx, fpy, chunk * CHUNK, p, f);
                 if (ws.state && stored && sub == 0) {  // per-pixel state after this chunk, for the backward
                     float* st = ws.state + (size_t)(mf + chunk) * (4 * kThreads);
                     st[pix] = p.T;

@@ -141,17 +141,22 @@ def heavy_params(seed, m, opacity_logit_mu):
     return oracle.ParamsRef(mean.T, log_scale.T, quat.T, logit, sh, 3), cam, rng
 
 
-@pytest.mark.parametrize("mu,chunk,mask_items", [(-3.0, 256, 0), (0.5, 256, 0), (-3.0, 128, 3), (0.5, 512, 2)])
+@pytest.mark.parametrize("mu,chunk,mask_items", [(-3.0, 256, 0), (0.5, 256, 0), (-3.0, 128, 3), (0.5, 512, 2),
+                                                  (0.5, 128, 0)])
 def test_backward_long_ranges_from_saved_chunk_state(mu, chunk, mask_items):
     """Translucent (pixels never saturate: every chunk blends) and opaque
     (pixels stop inside a later chunk) variants; gradients against the
     float64 oracle at the same bar, forward bit-exact. With mask_items > 0
     only the first chunks have stored masks and saved state: the tiles past
-    them are walked whole by the backward."""
+    them are walked whole by the backward. At 128-splat chunks the longest
+    tiles have 16 or more chunks, so the forward blends them as two
+    half-tile items and each half saves its own pixels' state."""
     prm, cam, rng = heavy_params(21, 9000, mu)
     fwd = oracle.forward32(prm, cam)
     lens = np.diff(fwd["ranges"], axis=1).ravel()
     assert lens.max() > 1024  # several chunks per tile
+    if chunk == 128:
+        assert lens.max() > 15 * 128 and np.any((lens > 128) & (lens <= 15 * 128))
     w = rng.normal(0, 1, (3, cam.height, cam.width))
     tune = fg.tune_struct(chunk, save_state=True, mask_items=mask_items)
     img, g_gpu, _ = gpu_fwd_bwd(prm, cam, w, tune=tune)

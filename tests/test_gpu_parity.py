@@ -11,7 +11,7 @@ import torch
 
 import oracle
 from paper_2603_23891_amd import fg, synth
-from tests.gpu_util import assert_frame_parity, run_gpu_frame
+from tests.gpu_util import assert_frame_parity, read_frame, run_gpu_frame
 
 pytestmark = pytest.mark.gpu
 
@@ -59,13 +59,22 @@ def test_ragged_image_and_city_block():
         assert_frame_parity(g, o)
 
 
+# tiles of at least this many chunks are blended as two half-tile items with
+# two lanes per pixel; shorter multi-chunk tiles as one item, one lane per pixel
+SPLIT_CHUNKS = 16
+
+
+@pytest.mark.parametrize("n", [12000, 30000])
 @pytest.mark.parametrize("opacity_logit_mu", [-3.0, 1.0])
-def test_heavy_tiles_chunked_blend(opacity_logit_mu):
+def test_heavy_tiles_chunked_blend(opacity_logit_mu, n):
     """Thousands of small splats on a few tiles: multi-chunk tiles hand the pixel
     state over between work items; translucent (no termination) and opaque
-    (termination inside a later chunk) variants."""
+    (termination inside a later chunk) variants. The denser scene has, at
+    every chunk size but 512, both tiles long enough to be split over two
+    work items and shorter multi-chunk tiles. The counting variant of the
+    blend renders the same frame, and its count of blended fragments does not
+    depend on the chunk size or on the split."""
     rng = np.random.default_rng(7)
-    n = 12000
     cam = synth.make_camera(np.eye(3), (0, 0, 0), 200, 120)
     z = rng.uniform(20, 60, n)
     px = rng.uniform(60, 110, n)
@@ -80,11 +89,25 @@ def test_heavy_tiles_chunked_blend(opacity_logit_mu):
     o = oracle.render_frame(tree, cam, 3.0, 0.0)
     L = (o["ranges"][:, 1].astype(np.int64) - o["ranges"][:, 0])
     assert L.max() > 2048
+    for chunk in ((128, 256) if n > 12000 else (128,)):
+        nch = (L + chunk - 1) // chunk
+        assert np.any(nch >= SPLIT_CHUNKS) and np.any((nch > 1) & (nch < SPLIT_CHUNKS)), chunk
+    dt = fg.DeviceTree(tree)
+    fb = fg.FrameBuffers(dt, cam.width, cam.height, tree.n_nodes, 1 << 22)
+    blended = set()
     # mask_items > 0 caps the stored chunk masks: the chunks past the cap
     # compute their masks inside the blend, wave by wave
     for chunk, mask_items in ((128, 0), (256, 0), (512, 0), (256, 3), (512, 1)):
-        g = run_gpu_frame(tree, cam, 3.0, 0.0, tune=fg.tune_struct(chunk, 0, mask_items=mask_items))
-        assert_frame_parity(g, o)
+        tune = fg.tune_struct(chunk, 0, mask_items=mask_items)
+        fg.render_frame(dt, cam, fb, 3.0, 0.0, tune=tune)
+        torch.cuda.synchronize()
+        assert_frame_parity(read_frame(fb, tree.n_nodes), o)
+        stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+        fg.render_stage(cam, fb, tune=tune, frag_stats=stats)
+        torch.cuda.synchronize()
+        assert_frame_parity(read_frame(fb, tree.n_nodes), o)
+        blended.add(int(stats[3].item()))
+    assert len(blended) == 1 and blended.pop() > 0
 
 
 def test_empty_view_and_single_node():
