@@ -110,6 +110,45 @@ def test_heavy_tiles_chunked_blend(opacity_logit_mu, n):
     assert len(blended) == 1 and blended.pop() > 0
 
 
+def test_heavy_tiles_on_the_ragged_corner():
+    """Long tiles on the image's ragged right column and bottom row (200 x 120
+    px: the last tile column and row are half outside), the longest on the
+    corner tile: split tiles whose lower half item has no pixel inside, and
+    split and unsplit tiles with a part of their columns outside."""
+    rng = np.random.default_rng(9)
+    n = 20000
+    cam = synth.make_camera(np.eye(3), (0, 0, 0), 200, 120)
+    z = rng.uniform(20, 60, n)
+    px = rng.uniform(186, 204, n)
+    py = rng.uniform(106, 124, n)
+    mean = np.stack([(px - cam.cx) * z / cam.fx, (py - cam.cy) * z / cam.fy, z], 1)
+    scale = np.exp(rng.normal(-3.2, 0.4, (n, 3))) * z[:, None] / 40
+    q = rng.standard_normal((n, 4)); q /= np.linalg.norm(q, axis=1, keepdims=True)
+    op = 1 / (1 + np.exp(-rng.normal(-3.0, 1.0, n)))
+    from tests.helpers import flat_tree
+    tree = flat_tree(mean, scale, q, op, rng.normal(0, 0.3, (n, 1, 3)))
+    o = oracle.render_frame(tree, cam, 3.0, 0.0)
+    L = o["ranges"][:, 1].astype(np.int64) - o["ranges"][:, 0]
+    Wt = (cam.width + 15) // 16
+    corner = ((cam.height + 15) // 16 - 1) * Wt + Wt - 1
+    assert L[corner] == L.max() and (L[corner] + 255) // 256 >= SPLIT_CHUNKS
+    nch = (L + 255) // 256
+    assert np.any((nch > 1) & (nch < SPLIT_CHUNKS))
+    dt = fg.DeviceTree(tree)
+    fb = fg.FrameBuffers(dt, cam.width, cam.height, tree.n_nodes, 1 << 22)
+    blended = set()
+    for chunk, mask_items in ((128, 0), (256, 0), (512, 0), (256, 5)):
+        tune = fg.tune_struct(chunk, 0, mask_items=mask_items)
+        fg.render_frame(dt, cam, fb, 3.0, 0.0, tune=tune)
+        torch.cuda.synchronize()
+        assert_frame_parity(read_frame(fb, tree.n_nodes), o)
+        stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+        fg.render_stage(cam, fb, tune=tune, frag_stats=stats)
+        torch.cuda.synchronize()
+        blended.add(int(stats[3].item()))
+    assert len(blended) == 1 and blended.pop() > 0
+
+
 def test_empty_view_and_single_node():
     cam = synth.tiny_camera(25)
     away = synth.make_camera(np.diag([1.0, -1.0, -1.0]), (0, 0, -25), 64, 48)  # looking away from the tree
